@@ -1,0 +1,581 @@
+// FP64 CPU oracle for spherical-cap GGX VNDF sampling (Dupuy & Benyoub,
+// "Sampling Visible GGX Normals with Spherical Caps", arXiv 2306.05044).
+//
+// TEST INFRASTRUCTURE ONLY.  This file is the plain, slow reference that the
+// GPU library is checked against.  Only the test suite, the smoke check and
+// the CPU-baseline leg of the benchmark may load it.  It shares no source,
+// header, table or helper with the HIP library, and it never calls it.
+//
+// Every routine follows the paper's own statement of the mathematics, in the
+// paper's order and notation, in double precision:
+//   * Philox4x32-10 from its published definition (Salmon, Moraes, Dror,
+//     Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11, Sec. 4).
+//   * the general VNDF sampler (Sec. 2, "Importance Sampling", steps 1-3)
+//     wrapped around either hemisphere sampler:
+//       - the spherical-cap sampler of Sec. 3.3 (cap in (-z_i, 1], then the
+//         half vector, normalised only after the unstretch), or
+//       - Heitz's 2018 cross-section sampler of Sec. 2 (comparison baseline);
+//   * the VNDF pdf as a linearly transformed hemisphere VNDF, Eqs. (1)-(4);
+//   * the GGX NDF, Smith G1/G2 and Cook-Torrance BRDF of Appendix A;
+//   * the Monte Carlo estimator of the direct-illumination integral,
+//     Appendix A, "Importance Sampling Using the GGX VNDF", with L == 1
+//     (directional albedo), weight f_r |cos theta_b| / PDF evaluated
+//     literally (no algebraic simplification);
+//   * its gradient by forward-mode dual numbers (exact derivative of this
+//     same program) and by central finite differences.
+//
+// Readings where the paper is silent (each also listed in the design doc):
+//   * u1 drives the azimuth and u2 the height, exactly as the cap listing.
+//   * Random numbers: u = (w >> 8) * 2^-24 from Philox words; counter
+//     (lo32(k>>1), unit, tag, hi32(k>>1)), key (lo32(seed), hi32(seed));
+//     sample k takes words (w0, w1) if k is even, else (w2, w3).
+//   * G1 is zero when the direction lies at or below the horizon (the
+//     printed G1 lacks that factor), so the pdf is zero there too.
+//   * Fresnel is Schlick's: F0 + (1 - F0)(1 - x)^5 with x = wh . wo.
+//   * Reflected directions at or below the horizon carry zero weight but
+//     still count in N.
+//   * Inputs outside the domain (w_z <= 0, alpha <= 0) give h = (0,0,1)
+//     and pdf = 0; albedo cells with wo_z <= 0 give 0 and zero gradient.
+//   * grad_theta_o is the derivative along the meridian of wo at fixed
+//     azimuth: dwo/dtheta = (cos t cos p, cos t sin p, -sin t); at the pole
+//     the azimuth is taken as 0.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (SC'11, Sec. 4): a 10-round Feistel-like network.  Each round
+// multiplies words 0 and 2 by the two round constants into 64-bit products;
+// the new words are (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1,
+// lo(M0*c0)).  The key is bumped by the two Weyl constants between rounds.
+// ---------------------------------------------------------------------------
+const uint32_t kPhiloxM0 = 0xD2511F53u;
+const uint32_t kPhiloxM1 = 0xCD9E8D57u;
+const uint32_t kPhiloxW0 = 0x9E3779B9u;
+const uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+void philox4x32_10(const uint32_t in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c[4] = {in[0], in[1], in[2], in[3]};
+    uint32_t k[2] = {key_in[0], key_in[1]};
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k[0] += kPhiloxW0;
+            k[1] += kPhiloxW1;
+        }
+        uint64_t p0 = (uint64_t)kPhiloxM0 * (uint64_t)c[0];
+        uint64_t p1 = (uint64_t)kPhiloxM1 * (uint64_t)c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k[0];
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c[3] ^ k[1];
+        uint32_t n3 = lo0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+    }
+    for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+// 24-bit uniform in [0, 1): top 24 bits of the word times 2^-24.
+double word_to_unit(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
+
+// The two uniforms of sample k of stream (seed, tag, unit).
+void stream_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, uint64_t k,
+                     double* u1, double* u2) {
+    uint64_t pair = k >> 1;
+    uint32_t ctr[4] = {(uint32_t)pair, unit, tag, (uint32_t)(pair >> 32)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    philox4x32_10(ctr, key, w);
+    if ((k & 1u) == 0) {
+        *u1 = word_to_unit(w[0]);
+        *u2 = word_to_unit(w[1]);
+    } else {
+        *u1 = word_to_unit(w[2]);
+        *u2 = word_to_unit(w[3]);
+    }
+}
+
+const uint32_t kTagSample = 2;  // vndf_sample tuples, unit 0, k = tuple index
+const uint32_t kTagAlbedo = 3;  // estimator samples, unit = cell / job index
+
+const double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual numbers with three tangents (alpha_x, alpha_y, theta_o).
+// ---------------------------------------------------------------------------
+struct Dual3 {
+    double v;
+    double d[3];
+    Dual3() : v(0.0), d{0.0, 0.0, 0.0} {}
+    Dual3(double x) : v(x), d{0.0, 0.0, 0.0} {}  // NOLINT: implicit by design
+    Dual3(double x, double d0, double d1, double d2) : v(x), d{d0, d1, d2} {}
+};
+inline Dual3 operator+(const Dual3& a, const Dual3& b) {
+    return Dual3(a.v + b.v, a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2]);
+}
+inline Dual3 operator-(const Dual3& a, const Dual3& b) {
+    return Dual3(a.v - b.v, a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2]);
+}
+inline Dual3 operator-(const Dual3& a) { return Dual3(-a.v, -a.d[0], -a.d[1], -a.d[2]); }
+inline Dual3 operator*(const Dual3& a, const Dual3& b) {
+    return Dual3(a.v * b.v, a.d[0] * b.v + a.v * b.d[0], a.d[1] * b.v + a.v * b.d[1],
+                 a.d[2] * b.v + a.v * b.d[2]);
+}
+inline Dual3 operator/(const Dual3& a, const Dual3& b) {
+    double q = a.v / b.v;
+    return Dual3(q, (a.d[0] - q * b.d[0]) / b.v, (a.d[1] - q * b.d[1]) / b.v,
+                 (a.d[2] - q * b.d[2]) / b.v);
+}
+inline Dual3 sqrt(const Dual3& a) {
+    double s = std::sqrt(a.v);
+    // At an argument of exactly zero the only way here is the clamp of a
+    // quantity that is identically zero (u2 == 0 puts the sample at the apex
+    // of the cap for every parameter value), so its derivative is zero.
+    if (s == 0.0) return Dual3(0.0);
+    double f = 0.5 / s;
+    return Dual3(s, a.d[0] * f, a.d[1] * f, a.d[2] * f);
+}
+inline double value(double x) { return x; }
+inline double value(const Dual3& x) { return x.v; }
+inline double sqrt_(double x) { return std::sqrt(x); }
+inline Dual3 sqrt_(const Dual3& x) { return sqrt(x); }
+
+template <class T>
+struct Vec3 {
+    T x, y, z;
+};
+template <class T>
+T dot(const Vec3<T>& a, const Vec3<T>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T>
+Vec3<T> normalize(const Vec3<T>& a) {
+    T n = sqrt_(dot(a, a));
+    return Vec3<T>{a.x / n, a.y / n, a.z / n};
+}
+template <class T>
+Vec3<T> cross(const Vec3<T>& a, const Vec3<T>& b) {
+    return Vec3<T>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class T>
+T clamp01(const T& x) {
+    if (value(x) < 0.0) return T(0.0);
+    if (value(x) > 1.0) return T(1.0);
+    return x;
+}
+template <class T>
+T max0(const T& x) { return value(x) > 0.0 ? x : T(0.0); }
+
+// ---------------------------------------------------------------------------
+// Hemisphere samplers (the visible normals of the unit hemisphere seen from
+// direction wi, which is unit and above the horizon).
+// ---------------------------------------------------------------------------
+
+// Spherical-cap sampler, Sec. 3.3: draw c uniformly on the cap of directions
+// with z in (-z_i, 1] (azimuth 2 pi u1, height from u2 with u2 = 0 at the
+// apex), and return the half vector c + wi without normalising it.
+template <class T>
+Vec3<T> hemisphere_cap(double u1, double u2, const Vec3<T>& wi) {
+    double phi = 2.0 * kPi * u1;
+    T z = (1.0 - u2) * (T(1.0) + wi.z) - wi.z;
+    T sin_theta = sqrt_(clamp01(T(1.0) - z * z));
+    Vec3<T> c{sin_theta * std::cos(phi), sin_theta * std::sin(phi), z};
+    return Vec3<T>{c.x + wi.x, c.y + wi.y, c.z + wi.z};
+}
+
+// Heitz's cross-section sampler (Sec. 2, as refactored in the paper):
+// orthonormal basis (w1, w2) around wi, polar sample of the unit disk, warp of
+// its second coordinate towards the projected hemisphere's cross section, and
+// reprojection onto the hemisphere.
+template <class T>
+Vec3<T> hemisphere_disk2018(double u1, double u2, const Vec3<T>& wi) {
+    T tmp = wi.x * wi.x + wi.y * wi.y;
+    Vec3<T> w1;
+    if (value(tmp) > 0.0) {
+        T inv = T(1.0) / sqrt_(tmp);
+        w1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};
+    } else {
+        w1 = Vec3<T>{T(1.0), T(0.0), T(0.0)};
+    }
+    Vec3<T> w2 = cross(wi, w1);
+    double phi = 2.0 * kPi * u1;
+    double r = std::sqrt(u2);
+    T t1 = T(r * std::cos(phi));
+    T t2 = T(r * std::sin(phi));
+    T s = (T(1.0) + wi.z) / 2.0;
+    t2 = (T(1.0) - s) * sqrt_(T(1.0) - t1 * t1) + s * t2;
+    T ti = sqrt_(max0(T(1.0) - t1 * t1 - t2 * t2));
+    return Vec3<T>{t1 * w1.x + t2 * w2.x + ti * wi.x, t1 * w1.y + t2 * w2.y + ti * wi.y,
+                   t1 * w1.z + t2 * w2.z + ti * wi.z};
+}
+
+// General VNDF sampler (Sec. 2, "Importance Sampling"): warp wi by M^-1 =
+// diag(ax, ay, 1) and normalise, sample the hemisphere, warp the normal back
+// with M^-T = diag(ax, ay, 1) and normalise.
+template <class T>
+Vec3<T> sample_vndf(double u1, double u2, const Vec3<T>& wi, const T& ax, const T& ay,
+                    int method) {
+    Vec3<T> wi_std = normalize(Vec3<T>{wi.x * ax, wi.y * ay, wi.z});
+    Vec3<T> wm_std = method == 0 ? hemisphere_cap(u1, u2, wi_std)
+                                 : hemisphere_disk2018(u1, u2, wi_std);
+    return normalize(Vec3<T>{wm_std.x * ax, wm_std.y * ay, wm_std.z});
+}
+
+// ---------------------------------------------------------------------------
+// Densities.
+// ---------------------------------------------------------------------------
+
+// Hemisphere NDF, Eq. (3): 1/pi above the horizon.
+template <class T>
+T ndf_std(const Vec3<T>& wm) { return value(wm.z) > 0.0 ? T(1.0 / kPi) : T(0.0); }
+
+// Cross-sectional area of the hemisphere seen from wi, Eq. (4).
+template <class T>
+T sigma_std(const Vec3<T>& wi) { return (T(1.0) + wi.z) / 2.0; }
+
+// Hemisphere VNDF, Eq. (2).
+template <class T>
+T vndf_std(const Vec3<T>& wm, const Vec3<T>& wi) {
+    return max0(dot(wm, wi)) * ndf_std(wm) / sigma_std(wi);
+}
+
+// GGX VNDF as a linearly transformed hemisphere VNDF, Eq. (1): the
+// hemisphere VNDF of M^T wm / |M^T wm| seen from M^-1 wi / |M^-1 wi|, times
+// the Jacobian |det M^T| / |M^T wm|^3, with M = diag(1/ax, 1/ay, 1).
+double vndf_pdf(const Vec3<double>& wm, const Vec3<double>& wi, double ax, double ay) {
+    if (!(wi.z > 0.0) || !(ax > 0.0) || !(ay > 0.0)) return 0.0;
+    Vec3<double> mtwm{wm.x / ax, wm.y / ay, wm.z};
+    double len = std::sqrt(dot(mtwm, mtwm));
+    Vec3<double> wm_std{mtwm.x / len, mtwm.y / len, mtwm.z / len};
+    Vec3<double> wi_std = normalize(Vec3<double>{wi.x * ax, wi.y * ay, wi.z});
+    double det = 1.0 / (ax * ay);
+    return vndf_std(wm_std, wi_std) * det / (len * len * len);
+}
+
+// GGX NDF, Appendix A: the hemisphere NDF of M^T wm / |M^T wm| times the
+// Jacobian |det M^T| / |M^T wm|^4.
+template <class T>
+T ggx_ndf(const Vec3<T>& wm, const T& ax, const T& ay) {
+    Vec3<T> mtwm{wm.x / ax, wm.y / ay, wm.z};
+    T len = sqrt_(dot(mtwm, mtwm));
+    Vec3<T> wm_std{mtwm.x / len, mtwm.y / len, mtwm.z / len};
+    T det = T(1.0) / (ax * ay);
+    T len2 = len * len;
+    return ndf_std(wm_std) * det / (len2 * len2);
+}
+
+// Smith monostatic shadowing G1(wm, wk), Appendix A, in its hemisphere form:
+// chi+(wk_std . wm_std) z_k_std / sigma_std(wk_std).  Zero at or below the
+// horizon (reading of the printed formula, which lacks that factor).
+template <class T>
+T smith_g1(const Vec3<T>& wm, const Vec3<T>& wk, const T& ax, const T& ay) {
+    if (!(value(wk.z) > 0.0)) return T(0.0);
+    Vec3<T> wm_std = normalize(Vec3<T>{wm.x / ax, wm.y / ay, wm.z});
+    Vec3<T> wk_std = normalize(Vec3<T>{wk.x * ax, wk.y * ay, wk.z});
+    if (!(value(dot(wk_std, wm_std)) > 0.0)) return T(0.0);
+    return wk_std.z / sigma_std(wk_std);
+}
+
+// Height-correlated Smith G2, Appendix A.
+template <class T>
+T smith_g2(const Vec3<T>& wm, const Vec3<T>& wi, const Vec3<T>& wo, const T& ax,
+           const T& ay) {
+    T gi = smith_g1(wm, wi, ax, ay);
+    T go = smith_g1(wm, wo, ax, ay);
+    T den = gi + go - gi * go;
+    if (!(value(den) > 0.0)) return T(0.0);
+    return gi * go / den;
+}
+
+// Schlick's Fresnel (the paper names F without a formula).
+template <class T>
+T fresnel_schlick(const T& x, double f0) {
+    T m = T(1.0) - x;
+    T m2 = m * m;
+    return f0 + (1.0 - f0) * (m2 * m2 * m);
+}
+
+// Cook-Torrance BRDF, Appendix A: F(wh . wo) G2 D / (4 cos(theta_i) cos(theta_o)),
+// here with wi = the view direction wa and wo = the generated direction wb.
+template <class T>
+T brdf_ggx(const Vec3<T>& wa, const Vec3<T>& wb, const T& ax, const T& ay, double f0) {
+    if (!(value(wa.z) > 0.0) || !(value(wb.z) > 0.0)) return T(0.0);
+    Vec3<T> wh = normalize(Vec3<T>{wa.x + wb.x, wa.y + wb.y, wa.z + wb.z});
+    T f = fresnel_schlick(dot(wh, wb), f0);
+    T g2 = smith_g2(wh, wa, wb, ax, ay);
+    T d = ggx_ndf(wh, ax, ay);
+    return f * g2 * d / (4.0 * wa.z * wb.z);
+}
+
+// One term of the albedo estimator (Appendix A, "Importance Sampling Using the
+// GGX VNDF", L == 1): sample wm from the VNDF seen from wa, reflect wa about
+// it, and return f_r(wb, wa) |cos theta_b| / PDF(wb, wa) with
+// PDF = G1(wm, wa) D(wm) / (4 cos theta_a).
+template <class T>
+T albedo_term(const Vec3<T>& wa, const T& ax, const T& ay, double u1, double u2, double f0,
+              int method) {
+    Vec3<T> wm = sample_vndf(u1, u2, wa, ax, ay, method);
+    T c = dot(wm, wa);
+    Vec3<T> wb{2.0 * c * wm.x - wa.x, 2.0 * c * wm.y - wa.y, 2.0 * c * wm.z - wa.z};
+    if (!(value(wb.z) > 0.0)) return T(0.0);
+    T fr = brdf_ggx(wa, wb, ax, ay, f0);
+    T cos_b = wb.z;
+    T pdf = smith_g1(wm, wa, ax, ay) * ggx_ndf(wm, ax, ay) / (4.0 * wa.z);
+    if (!(value(pdf) > 0.0)) return T(0.0);
+    return fr * cos_b / pdf;
+}
+
+// Neumaier (Kahan-Babuska) compensated sum.
+template <class T>
+struct NeumaierSum {
+    T s, c;
+    NeumaierSum() : s(0.0), c(0.0) {}
+    void add(const T& x) {
+        T t = s + x;
+        if (std::fabs(value(s)) >= std::fabs(value(x)))
+            c = c + ((s - t) + x);
+        else
+            c = c + ((x - t) + s);
+        s = t;
+    }
+    T result() const { return s + c; }
+};
+
+// Run body(i) for i in [0, n) over nthreads threads (static contiguous split).
+template <class F>
+void parallel_for(int64_t n, int nthreads, F body) {
+    if (nthreads <= 0) nthreads = (int)std::max(1u, std::thread::hardware_concurrency());
+    if (n <= 0) return;
+    if (nthreads > n) nthreads = (int)n;
+    if (nthreads == 1) {
+        for (int64_t i = 0; i < n; ++i) body(i);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t lo = n * t / nthreads, hi = n * (t + 1) / nthreads;
+        pool.emplace_back([=]() {
+            for (int64_t i = lo; i < hi; ++i) body(i);
+        });
+    }
+    for (auto& th : pool) th.join();
+}
+
+Vec3<double> unit_view(double x, double y, double z) {
+    double n = std::sqrt(x * x + y * y + z * z);
+    return Vec3<double>{x / n, y / n, z / n};
+}
+
+// Meridian tangent dwo/dtheta of a unit wo (azimuth 0 at the pole).
+Vec3<double> meridian_tangent(const Vec3<double>& wo) {
+    double rho = std::sqrt(wo.x * wo.x + wo.y * wo.y);
+    if (rho > 0.0) return Vec3<double>{wo.z * wo.x / rho, wo.z * wo.y / rho, -rho};
+    return Vec3<double>{wo.z, 0.0, 0.0};
+}
+
+double cell_albedo(const Vec3<double>& wo, double ax, double ay, int64_t n, uint64_t seed,
+                   uint32_t unit, double f0, int method) {
+    if (n <= 0 || !(wo.z > 0.0) || !(ax > 0.0) || !(ay > 0.0)) return 0.0;
+    NeumaierSum<double> acc;
+    for (int64_t k = 0; k < n; ++k) {
+        double u1, u2;
+        stream_uniforms(seed, kTagAlbedo, unit, (uint64_t)k, &u1, &u2);
+        acc.add(albedo_term(wo, ax, ay, u1, u2, f0, method));
+    }
+    return acc.result() / (double)n;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Raw Philox4x32-10 block: out = philox(ctr, key).
+void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    philox4x32_10(ctr, key, out);
+}
+
+// Uniforms of samples k0 .. k0+n-1 of stream (seed, tag, unit).
+void orc_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, uint64_t k0, int64_t n,
+                  double* u1, double* u2) {
+    for (int64_t i = 0; i < n; ++i) stream_uniforms(seed, tag, unit, k0 + (uint64_t)i, &u1[i], &u2[i]);
+}
+
+// Hemisphere sampler alone (unit, upper-hemisphere wi): the raw unnormalised
+// output of the chosen hemisphere routine.
+void orc_hemisphere_sample(int64_t n, const double* wix, const double* wiy, const double* wiz,
+                           const double* u1, const double* u2, int32_t method, double* hx,
+                           double* hy, double* hz) {
+    for (int64_t i = 0; i < n; ++i) {
+        Vec3<double> wi{wix[i], wiy[i], wiz[i]};
+        Vec3<double> h = method == 0 ? hemisphere_cap(u1[i], u2[i], wi)
+                                     : hemisphere_disk2018(u1[i], u2[i], wi);
+        hx[i] = h.x; hy[i] = h.y; hz[i] = h.z;
+    }
+}
+
+// GGX VNDF sampling of n tuples.  u1/u2 both null: Philox stream
+// (seed, tag 2, unit 0) at sample index index_base + i.  pdf may be null; it
+// is the VNDF pdf of Eq. (1) evaluated at the sample.
+int32_t orc_vndf_sample(int64_t n, const double* wix, const double* wiy, const double* wiz,
+                        const double* ax, const double* ay, const double* u1, const double* u2,
+                        uint64_t seed, uint64_t index_base, int32_t method, double* hx,
+                        double* hy, double* hz, double* pdf, int32_t nthreads) {
+    if (n < 0 || (method != 0 && method != 1)) return -1;
+    if ((u1 == nullptr) != (u2 == nullptr)) return -1;
+    parallel_for(n, nthreads, [&](int64_t i) {
+        Vec3<double> wi{wix[i], wiy[i], wiz[i]};
+        double a = ax[i], b = ay[i];
+        double r1, r2;
+        if (u1 != nullptr) {
+            r1 = u1[i]; r2 = u2[i];
+        } else {
+            stream_uniforms(seed, kTagSample, 0u, index_base + (uint64_t)i, &r1, &r2);
+        }
+        if (!(wi.z > 0.0) || !(a > 0.0) || !(b > 0.0)) {
+            hx[i] = 0.0; hy[i] = 0.0; hz[i] = 1.0;
+            if (pdf) pdf[i] = 0.0;
+            return;
+        }
+        Vec3<double> h = sample_vndf(r1, r2, wi, a, b, method);
+        hx[i] = h.x; hy[i] = h.y; hz[i] = h.z;
+        if (pdf) pdf[i] = vndf_pdf(h, wi, a, b);
+    });
+    return 0;
+}
+
+// VNDF pdf of Eq. (1) at caller-given (wm, wi, alpha).
+int32_t orc_vndf_pdf(int64_t n, const double* wix, const double* wiy, const double* wiz,
+                     const double* hx, const double* hy, const double* hz, const double* ax,
+                     const double* ay, double* pdf, int32_t nthreads) {
+    if (n < 0) return -1;
+    parallel_for(n, nthreads, [&](int64_t i) {
+        pdf[i] = vndf_pdf(Vec3<double>{hx[i], hy[i], hz[i]}, Vec3<double>{wix[i], wiy[i], wiz[i]},
+                          ax[i], ay[i]);
+    });
+    return 0;
+}
+
+// GGX NDF D(wm) and Smith G1(wm, wk) of Appendix A, element-wise.
+void orc_ggx_ndf(int64_t n, const double* hx, const double* hy, const double* hz,
+                 const double* ax, const double* ay, double* out) {
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = ggx_ndf(Vec3<double>{hx[i], hy[i], hz[i]}, ax[i], ay[i]);
+}
+void orc_smith_g1(int64_t n, const double* hx, const double* hy, const double* hz,
+                  const double* wx, const double* wy, const double* wz, const double* ax,
+                  const double* ay, double* out) {
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = smith_g1(Vec3<double>{hx[i], hy[i], hz[i]}, Vec3<double>{wx[i], wy[i], wz[i]},
+                          ax[i], ay[i]);
+}
+
+// Cook-Torrance GGX BRDF f_r(wa, wb), element-wise (Appendix A).
+void orc_brdf(int64_t n, const double* ax_, const double* ay_, const double* wax,
+              const double* way, const double* waz, const double* wbx, const double* wby,
+              const double* wbz, double f0, double* out) {
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = brdf_ggx(Vec3<double>{wax[i], way[i], waz[i]}, Vec3<double>{wbx[i], wby[i], wbz[i]},
+                          ax_[i], ay_[i], f0);
+}
+
+// Single estimator terms for caller-given uniforms (one per element).
+void orc_albedo_terms(int64_t n, const double* wox, const double* woy, const double* woz,
+                      const double* ax, const double* ay, const double* u1, const double* u2,
+                      double f0, int32_t method, double* out) {
+    for (int64_t i = 0; i < n; ++i) {
+        Vec3<double> wo{wox[i], woy[i], woz[i]};
+        if (!(wo.z > 0.0) || !(ax[i] > 0.0) || !(ay[i] > 0.0)) { out[i] = 0.0; continue; }
+        out[i] = albedo_term(unit_view(wo.x, wo.y, wo.z), ax[i], ay[i], u1[i], u2[i], f0, method);
+    }
+}
+
+// Directional albedo per cell: (1/N) sum of the estimator terms over the
+// Philox stream (seed, tag 3, unit = units[c] or c), Neumaier-summed.
+int32_t orc_albedo(int64_t ncells, const double* wox, const double* woy, const double* woz,
+                   const double* ax, const double* ay, const int64_t* nsamples,
+                   const uint32_t* units, uint64_t seed, const double* f0, int32_t method,
+                   double* albedo, int32_t nthreads) {
+    if (ncells < 0) return -1;
+    parallel_for(ncells, nthreads, [&](int64_t c) {
+        uint32_t unit = units ? units[c] : (uint32_t)c;
+        Vec3<double> wo = woz[c] > 0.0 ? unit_view(wox[c], woy[c], woz[c])
+                                       : Vec3<double>{wox[c], woy[c], woz[c]};
+        albedo[c] = cell_albedo(wo, ax[c], ay[c], nsamples[c], seed, unit, f0[c], method);
+    });
+    return 0;
+}
+
+// Albedo and its gradient w.r.t. (alpha_x, alpha_y, theta_o) per cell by
+// forward-mode dual numbers through the same estimator (common random
+// numbers: the gradient of this program's own output).
+int32_t orc_albedo_grad(int64_t ncells, const double* wox, const double* woy, const double* woz,
+                        const double* ax, const double* ay, const int64_t* nsamples,
+                        const uint32_t* units, uint64_t seed, const double* f0, double* albedo,
+                        double* g_ax, double* g_ay, double* g_theta, int32_t nthreads) {
+    if (ncells < 0) return -1;
+    parallel_for(ncells, nthreads, [&](int64_t c) {
+        uint32_t unit = units ? units[c] : (uint32_t)c;
+        int64_t n = nsamples[c];
+        albedo[c] = 0.0; g_ax[c] = 0.0; g_ay[c] = 0.0; g_theta[c] = 0.0;
+        if (n <= 0 || !(woz[c] > 0.0) || !(ax[c] > 0.0) || !(ay[c] > 0.0)) return;
+        Vec3<double> wo = unit_view(wox[c], woy[c], woz[c]);
+        Vec3<double> t = meridian_tangent(wo);
+        Vec3<Dual3> wo_d{Dual3(wo.x, 0.0, 0.0, t.x), Dual3(wo.y, 0.0, 0.0, t.y),
+                         Dual3(wo.z, 0.0, 0.0, t.z)};
+        Dual3 a(ax[c], 1.0, 0.0, 0.0), b(ay[c], 0.0, 1.0, 0.0);
+        NeumaierSum<double> sv, s0, s1, s2;
+        for (int64_t k = 0; k < n; ++k) {
+            double u1, u2;
+            stream_uniforms(seed, kTagAlbedo, unit, (uint64_t)k, &u1, &u2);
+            Dual3 w = albedo_term(wo_d, a, b, u1, u2, f0[c], 0);
+            sv.add(w.v); s0.add(w.d[0]); s1.add(w.d[1]); s2.add(w.d[2]);
+        }
+        double inv = 1.0 / (double)n;
+        albedo[c] = sv.result() * inv;
+        g_ax[c] = s0.result() * inv;
+        g_ay[c] = s1.result() * inv;
+        g_theta[c] = s2.result() * inv;
+    });
+    return 0;
+}
+
+// Central finite differences of orc_albedo (same random numbers) with the
+// given step for alpha_x, alpha_y and theta_o (wo moved along its meridian).
+int32_t orc_albedo_fd(int64_t ncells, const double* wox, const double* woy, const double* woz,
+                      const double* ax, const double* ay, const int64_t* nsamples,
+                      const uint32_t* units, uint64_t seed, const double* f0, double step,
+                      double* g_ax, double* g_ay, double* g_theta, int32_t nthreads) {
+    if (ncells < 0 || !(step > 0.0)) return -1;
+    parallel_for(ncells, nthreads, [&](int64_t c) {
+        uint32_t unit = units ? units[c] : (uint32_t)c;
+        int64_t n = nsamples[c];
+        g_ax[c] = 0.0; g_ay[c] = 0.0; g_theta[c] = 0.0;
+        if (n <= 0 || !(woz[c] > 0.0) || !(ax[c] > 0.0) || !(ay[c] > 0.0)) return;
+        Vec3<double> wo = unit_view(wox[c], woy[c], woz[c]);
+        double rho = std::sqrt(wo.x * wo.x + wo.y * wo.y);
+        double theta = std::atan2(rho, wo.z);
+        double phi = rho > 0.0 ? std::atan2(wo.y, wo.x) : 0.0;
+        auto at = [&](double th) {
+            return Vec3<double>{std::sin(th) * std::cos(phi), std::sin(th) * std::sin(phi),
+                                std::cos(th)};
+        };
+        double a = ax[c], b = ay[c];
+        g_ax[c] = (cell_albedo(wo, a + step, b, n, seed, unit, f0[c], 0) -
+                   cell_albedo(wo, a - step, b, n, seed, unit, f0[c], 0)) / (2.0 * step);
+        g_ay[c] = (cell_albedo(wo, a, b + step, n, seed, unit, f0[c], 0) -
+                   cell_albedo(wo, a, b - step, n, seed, unit, f0[c], 0)) / (2.0 * step);
+        g_theta[c] = (cell_albedo(at(theta + step), a, b, n, seed, unit, f0[c], 0) -
+                      cell_albedo(at(theta - step), a, b, n, seed, unit, f0[c], 0)) / (2.0 * step);
+    });
+    return 0;
+}
+
+int32_t orc_hardware_threads(void) {
+    return (int32_t)std::max(1u, std::thread::hardware_concurrency());
+}
+
+}  // extern "C"

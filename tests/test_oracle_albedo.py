@@ -1,0 +1,163 @@
+"""Pins of the oracle's directional-albedo estimator and its gradient (CPU only).
+
+* Normal incidence reduces the estimator to a 1-D integral over the tilt of
+  the microfacet normal: with wo = e_z, G1(wo) = 1, the VNDF is D(h) h_z and
+  the reflected direction has twice the tilt, so
+  A = int_0^{pi/4} 2 pi D(t) cos t sin t F(cos t) G1(cos 2t) dt; at alpha = 1,
+  F0 = 1 it is exactly 1 - ln 2.  Deterministic quadrature vs Monte Carlo.
+* Away from normal incidence: 2-D quadrature of int f_r(wo, wl) cos(theta_l)
+  dwl (the integral the estimator targets, Appendix A) vs Monte Carlo.
+* alpha -> 0 gives A -> F(mu); 0 <= A <= 1; a zero-weight (below-horizon)
+  sample still counts in N.
+* Dual-number gradient vs central differences of the same program (common
+  random numbers) at steps where truncation and rounding are both negligible,
+  and vs the derivative of the 1-D normal-incidence integral.
+"""
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from _hemi import hemi_grid
+
+
+def _normal_incidence(alpha, f0):
+    def integrand(t):
+        c, s = np.cos(t), np.sin(t)
+        D = 1.0 / (np.pi * alpha ** 2 * c ** 4 * (1.0 + (s / c) ** 2 / alpha ** 2) ** 2)
+        x = np.cos(2 * t)
+        zs = x / np.sqrt(alpha ** 2 * (1 - x * x) + x * x)
+        G1 = 2 * zs / (1 + zs)
+        F = f0 + (1 - f0) * (1 - c) ** 5
+        return 2 * np.pi * D * c * s * F * G1
+    pts = [alpha] if alpha < np.pi / 4 else None
+    return integrate.quad(integrand, 0.0, np.pi / 4, points=pts, epsabs=1e-13,
+                          epsrel=1e-12, limit=400)[0]
+
+
+def test_normal_incidence_closed_form():
+    assert abs(_normal_incidence(1.0, 1.0) - (1.0 - np.log(2.0))) < 1e-11
+
+
+def _mc_sigma(orc, wo, ax, ay, f0, n=20000, seed=99):
+    u1, u2 = orc.uniforms(seed, orc.TAG_ALBEDO, 0, 0, n)
+    w = orc.albedo_terms(tuple(np.full(n, c) for c in wo), np.full(n, ax), np.full(n, ay),
+                         u1, u2, f0)
+    return w.std()
+
+
+@pytest.mark.parametrize("alpha,f0", [(1.0, 1.0), (1.0, 0.04), (0.5, 1.0), (0.5, 0.04),
+                                      (0.05, 1.0), (0.01, 0.04)])
+def test_normal_incidence_mc(orc, alpha, f0):
+    N = 1 << 20
+    wo = (0.0, 0.0, 1.0)
+    A = orc.albedo(tuple([c] for c in wo), [alpha], [alpha], [N], seed=7, f0=f0)[0]
+    ref = _normal_incidence(alpha, f0)
+    sig = _mc_sigma(orc, wo, alpha, alpha, f0)
+    assert abs(A - ref) <= 4.0 * sig / np.sqrt(N) + 1e-12, (A, ref, sig)
+
+
+def _quad_albedo(orc, wo, ax, ay, f0, nb=384, nphi=384):
+    """int f_r(wo, wl) cos(theta_l) dwl over the upper hemisphere, integrating
+    over half vectors: dwl = 4 |wo.h| dh, wl = 2 (wo.h) h - wo."""
+    h, w = hemi_grid(ax, ay, nb, nphi)
+    wo = np.asarray(wo, dtype=np.float64)
+    c = h @ wo
+    wl = 2.0 * c[:, None] * h - wo
+    n = h.shape[0]
+    fr = orc.brdf(np.full(n, ax), np.full(n, ay), tuple(np.full(n, x) for x in wo),
+                  tuple(wl.T), f0)
+    integrand = np.where((c > 0) & (wl[:, 2] > 0), fr * wl[:, 2] * 4.0 * c, 0.0)
+    return (integrand * w).sum()
+
+
+@pytest.mark.parametrize("ax,ay,mu,phi,f0", [
+    (0.5, 0.5, 0.5, 0.0, 1.0),
+    (0.3, 0.7, 0.3, 1.0, 1.0),
+    (1.0, 1.0, 0.05, 0.0, 0.04),
+    (0.1, 0.02, 0.8, 2.5, 1.0),
+])
+def test_quadrature_vs_mc(orc, ax, ay, mu, phi, f0):
+    s = np.sqrt(1 - mu * mu)
+    wo = (s * np.cos(phi), s * np.sin(phi), mu)
+    ref = _quad_albedo(orc, wo, ax, ay, f0)
+    N = 1 << 20
+    A = orc.albedo(tuple([c] for c in wo), [ax], [ay], [N], seed=11, f0=f0)[0]
+    sig = _mc_sigma(orc, wo, ax, ay, f0)
+    assert abs(A - ref) <= 4.0 * sig / np.sqrt(N) + 1e-7, (A, ref, sig)
+
+
+def test_smooth_limit_and_bounds(orc):
+    mu = np.array([0.1, 0.5, 0.9, 1.0])
+    s = np.sqrt(1 - mu * mu)
+    for f0 in (0.04, 1.0):
+        A = orc.albedo((s, np.zeros(4), mu), np.full(4, 1e-4), np.full(4, 1e-4), [4096] * 4,
+                       seed=3, f0=f0)
+        F = f0 + (1 - f0) * (1 - mu) ** 5
+        assert np.allclose(A, F, atol=2e-3)
+    rng = np.random.default_rng(0)
+    m = 64
+    mu = 1 - rng.random(m)
+    s = np.sqrt(1 - mu * mu)
+    A = orc.albedo((s, np.zeros(m), mu), 10 ** (-3 * rng.random(m)), 10 ** (-3 * rng.random(m)),
+                   [2048] * m, seed=4)
+    assert np.all(A >= 0.0) and np.all(A <= 1.0)
+
+
+def test_zero_weight_samples_count(orc):
+    """At grazing view and alpha = 1 some reflections go below the horizon; the
+    estimator is the plain mean over all N terms."""
+    wo = (np.sqrt(1 - 0.05 ** 2), 0.0, 0.05)
+    n = 4096
+    u1, u2 = orc.uniforms(5, orc.TAG_ALBEDO, 0, 0, n)
+    terms = orc.albedo_terms(tuple(np.full(n, c) for c in wo), np.ones(n), np.ones(n), u1, u2)
+    assert np.any(terms == 0.0)
+    A = orc.albedo(tuple([c] for c in wo), [1.0], [1.0], [n], seed=5)[0]
+    assert abs(A - terms.mean()) < 1e-15
+
+
+def test_domain(orc):
+    A = orc.albedo(([0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [-0.5, 1.0, 1.0]), [0.5, 0.0, 0.5],
+                   [0.5, 0.5, 0.5], [100, 100, 0], seed=1)
+    assert np.all(A == 0.0)
+
+
+GRAD_CELLS = [  # (ax, ay, mu, phi)
+    (0.3, 0.5, 0.8, 0.0),
+    (0.05, 0.02, 0.95, 0.3),
+    (1.0, 0.2, 0.1, 2.0),
+    (0.01, 0.5, 0.4, 4.0),
+]
+
+
+def test_dual_vs_central_differences(orc):
+    ax = np.array([c[0] for c in GRAD_CELLS])
+    ay = np.array([c[1] for c in GRAD_CELLS])
+    mu = np.array([c[2] for c in GRAD_CELLS])
+    ph = np.array([c[3] for c in GRAD_CELLS])
+    s = np.sqrt(1 - mu * mu)
+    wo = (s * np.cos(ph), s * np.sin(ph), mu)
+    N = [1 << 14] * len(ax)
+    A, gx, gy, gt = orc.albedo_grad(wo, ax, ay, N, seed=3)
+    A2 = orc.albedo(wo, ax, ay, N, seed=3)
+    assert np.array_equal(A, A2)  # the dual program's value is the plain program's
+    fd = orc.albedo_fd(wo, ax, ay, N, seed=3, step=1e-7)
+    for g, f in zip((gx, gy, gt), fd):
+        assert np.all(np.abs(g - f) <= 1e-7 + 1e-6 * np.abs(g)), (g, f)
+
+
+def test_gradient_at_normal_incidence(orc):
+    """Isotropic, wo = e_z: d/d alpha = d/d alpha_x + d/d alpha_y must match the
+    derivative of the 1-D integral (within Monte Carlo error)."""
+    alpha = 0.4
+    N = 1 << 20
+    A, gx, gy, gt = orc.albedo_grad(([0.0], [0.0], [1.0]), [alpha], [alpha], [N], seed=13)
+    h = 1e-5
+    ref = (_normal_incidence(alpha + h, 1.0) - _normal_incidence(alpha - h, 1.0)) / (2 * h)
+    # per-sample gradient spread estimated from independent cells
+    G = []
+    for seed in range(16):
+        _, a, b, _ = orc.albedo_grad(([0.0], [0.0], [1.0]), [alpha], [alpha], [4096], seed=seed)
+        G.append(a[0] + b[0])
+    sig = np.std(G) * np.sqrt(4096)
+    assert abs(gx[0] + gy[0] - ref) <= 5.0 * sig / np.sqrt(N), (gx + gy, ref, sig)

@@ -1,0 +1,206 @@
+"""Pins of the oracle's VNDF samplers (CPU only).
+
+What fixes each part of the sampler without another implementation of it:
+
+* invariants of the construction (unit h above the horizon, facing wi);
+* the exact inverse map through the reflection law and the half vector
+  (Sec. 3.2): from h, wi and alpha the cap point c and then (u1, u2) are
+  recovered, which pins the azimuth/height roles and the cap bounds;
+* normal incidence, where the VNDF is D(h) h_z and the textbook inversion of
+  the GGX NDF (Walter et al. 2007) gives h in closed form, anisotropic too
+  (this pins which of alpha_x / alpha_y stretches which axis);
+* the uniform density of the cap, 1 / (2 pi (1 + z_i)) (Sec. 3.2);
+* a chi-square test of the samples against the pdf of Eq. (1) integrated per
+  bin, and a two-sample test of the cap sampler against Heitz's disk sampler.
+"""
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from _hemi import binned_grid, slope_coords
+import workloads
+
+
+def _wi(mu, phi, n):
+    s = np.sqrt(1.0 - mu * mu)
+    return (np.full(n, s * np.cos(phi)), np.full(n, s * np.sin(phi)), np.full(n, mu))
+
+
+CASES = [  # (ax, ay, mu, phi)
+    (0.3, 0.6, 0.2, 0.7),
+    (0.05, 0.05, 0.05, 0.0),
+    (1.0, 1.0, 0.9, 2.0),
+    (0.01, 0.2, 0.5, 4.0),
+    (0.8, 0.02, 0.7, 5.5),
+]
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_invariants(orc, method):
+    d = workloads.tuples_small(20000, seed=11)
+    wi = (d["wx"], d["wy"], d["wz"])
+    h, pdf = orc.vndf_sample(wi, d["ax"], d["ay"], seed=5, method=method)
+    assert np.allclose(np.linalg.norm(h, axis=1), 1.0, atol=1e-14)
+    assert np.all(h[:, 2] > 0.0)
+    w = np.stack([c.astype(np.float64) for c in wi], axis=1)
+    assert np.all(np.einsum("ij,ij->i", h, w) >= 0.0)
+    assert np.all(pdf > 0.0) and np.all(np.isfinite(pdf))
+
+
+def test_inverse_map_recovers_uniforms(orc):
+    """Reflect -ws about the standard-space normal to get the cap point c, then
+    read u2 from its height and u1 from its azimuth."""
+    d = workloads.tuples_streaming(20000, seed=12)
+    wi = np.stack([d["wx"], d["wy"], d["wz"]], axis=1).astype(np.float64)
+    ax = d["ax"].astype(np.float64)
+    ay = d["ay"].astype(np.float64)
+    u1, u2 = orc.uniforms(3, orc.TAG_SAMPLE, 0, 0, len(ax))
+    h, _ = orc.vndf_sample(tuple(wi.T), ax, ay, u1=u1, u2=u2, method=0)
+    hs = np.stack([h[:, 0] / ax, h[:, 1] / ay, h[:, 2]], axis=1)
+    hs /= np.linalg.norm(hs, axis=1, keepdims=True)
+    ws = np.stack([wi[:, 0] * ax, wi[:, 1] * ay, wi[:, 2]], axis=1)
+    ws /= np.linalg.norm(ws, axis=1, keepdims=True)
+    c = 2.0 * np.einsum("ij,ij->i", hs, ws)[:, None] * hs - ws
+    zs = ws[:, 2]
+    u2_rec = 1.0 - (c[:, 2] + zs) / (1.0 + zs)
+    u1_rec = np.mod(np.arctan2(c[:, 1], c[:, 0]) / (2 * np.pi), 1.0)
+    # the map is well conditioned away from the cap's apex and poles of c
+    ok = np.hypot(c[:, 0], c[:, 1]) > 1e-3
+    assert np.max(np.abs(u2_rec - u2)) < 1e-9
+    du1 = np.abs(u1_rec - u1)
+    du1 = np.minimum(du1, 1.0 - du1)
+    assert np.max(du1[ok]) < 1e-9
+    # |c| = 1: the reflected direction lies on the unit sphere, inside the cap
+    assert np.allclose(np.linalg.norm(c, axis=1), 1.0, atol=1e-12)
+    assert np.all(c[:, 2] > -zs - 1e-12)
+
+
+@pytest.mark.parametrize("ax,ay", [(0.3, 0.3), (0.05, 0.7), (1.0, 0.01)])
+def test_normal_incidence_textbook_inversion(orc, ax, ay):
+    """At wi = e_z the VNDF is D(h) h_z, whose inverse-CDF sample is
+    h ~ (ax sqrt(u2) cos 2 pi u1, ay sqrt(u2) sin 2 pi u1, sqrt(1 - u2))."""
+    n = 5000
+    u1, u2 = orc.uniforms(21, orc.TAG_SAMPLE, 0, 0, n)
+    wi = (np.zeros(n), np.zeros(n), np.ones(n))
+    ref = np.stack([ax * np.sqrt(u2) * np.cos(2 * np.pi * u1),
+                    ay * np.sqrt(u2) * np.sin(2 * np.pi * u1), np.sqrt(1.0 - u2)], axis=1)
+    ref /= np.linalg.norm(ref, axis=1, keepdims=True)
+    for method in (0, 1):
+        h, _ = orc.vndf_sample(wi, np.full(n, ax), np.full(n, ay), u1=u1, u2=u2,
+                               method=method)
+        assert np.max(np.abs(h - ref)) < 1e-12
+    if ax == ay:
+        # isotropic: tan^2(theta_h) = alpha^2 u2 / (1 - u2), phi_h = 2 pi u1
+        h, _ = orc.vndf_sample(wi, np.full(n, ax), np.full(n, ay), u1=u1, u2=u2)
+        tan2 = (h[:, 0] ** 2 + h[:, 1] ** 2) / h[:, 2] ** 2
+        assert np.allclose(tan2, ax * ax * u2 / (1.0 - u2), rtol=1e-10, atol=1e-300)
+
+
+def test_alpha_axes(orc):
+    """A tiny alpha_x keeps normals in the x = 0 plane; a tiny alpha_y in y = 0."""
+    n = 4000
+    wi = _wi(0.6, 0.8, n)
+    h, _ = orc.vndf_sample(wi, np.full(n, 1e-4), np.full(n, 0.8), seed=1)
+    assert np.max(np.abs(h[:, 0])) < 2e-3 and np.max(np.abs(h[:, 1])) > 0.3
+    h, _ = orc.vndf_sample(wi, np.full(n, 0.8), np.full(n, 1e-4), seed=1)
+    assert np.max(np.abs(h[:, 1])) < 2e-3 and np.max(np.abs(h[:, 0])) > 0.3
+
+
+@pytest.mark.parametrize("mu", [0.05, 0.5, 1.0])
+def test_cap_is_uniform(orc, mu):
+    """The cap point c = (hemisphere sample) - wi is uniform on the part of the
+    unit sphere above z = -z_i: height uniform on (-z_i, 1], azimuth uniform,
+    independent (density 1 / (2 pi (1 + z_i)))."""
+    n = 40000
+    u1, u2 = orc.uniforms(31, orc.TAG_SAMPLE, 0, 0, n)
+    wi = _wi(mu, 1.1, n)
+    hs = orc.hemisphere_sample(wi, u1, u2, method=0)
+    c = hs - np.stack(wi, axis=1)
+    assert np.allclose(np.linalg.norm(c, axis=1), 1.0, atol=1e-12)
+    zc = (c[:, 2] + mu) / (1.0 + mu)
+    assert stats.kstest(zc, "uniform").pvalue > 1e-3
+    az = np.mod(np.arctan2(c[:, 1], c[:, 0]) / (2 * np.pi), 1.0)
+    assert stats.kstest(az, "uniform").pvalue > 1e-3
+    # height and azimuth independent: 2-D histogram is flat
+    hist, _, _ = np.histogram2d(zc, az, bins=8, range=[[0, 1], [0, 1]])
+    assert stats.chisquare(hist.ravel()).pvalue > 1e-3
+
+
+def _bin_probabilities(orc, ax, ay, wi1, b_edges, p_edges):
+    """Expected probability of each (beta, phi) bin: Gauss-Legendre quadrature
+    of the pdf of Eq. (1) inside every bin."""
+    h, w, idx = binned_grid(ax, ay, b_edges, p_edges, nq=16)
+    n = h.shape[0]
+    pdf = orc.vndf_pdf(tuple(np.full(n, c) for c in wi1), (h[:, 0], h[:, 1], h[:, 2]),
+                       np.full(n, ax), np.full(n, ay))
+    nbins = (len(b_edges) - 1) * (len(p_edges) - 1)
+    return np.bincount(idx, weights=pdf * w, minlength=nbins).reshape(
+        len(b_edges) - 1, len(p_edges) - 1)
+
+
+def _hist(h, ax, ay, b_edges, p_edges):
+    beta, phi = slope_coords(h, ax, ay)
+    H, _, _ = np.histogram2d(beta, phi, bins=[b_edges, p_edges])
+    return H
+
+
+@pytest.mark.parametrize("ax,ay,mu,phi", CASES)
+def test_chi2_against_pdf(orc, ax, ay, mu, phi):
+    n = 200000
+    s = np.sqrt(1 - mu * mu)
+    wi1 = (s * np.cos(phi), s * np.sin(phi), mu)
+    b_edges = np.linspace(0, np.pi / 2, 17)
+    p_edges = np.linspace(0, 2 * np.pi, 33)
+    probs = _bin_probabilities(orc, ax, ay, wi1, b_edges, p_edges)
+    assert abs(probs.sum() - 1.0) < 1e-6
+    for method in (0, 1):
+        h, _ = orc.vndf_sample(_wi(mu, phi, n), np.full(n, ax), np.full(n, ay), seed=77,
+                               method=method)
+        H = _hist(h, ax, ay, b_edges, p_edges)
+        exp = probs.ravel() * n
+        obs = H.ravel()
+        keep = exp >= 5.0
+        # no samples where the pdf has (numerically) no mass
+        assert obs[exp < 1e-6].sum() == 0
+        o = np.append(obs[keep], obs[~keep].sum())
+        e = np.append(exp[keep], exp[~keep].sum())
+        if e[-1] < 5.0:
+            o, e = o[:-1], e[:-1]
+        e = e * o.sum() / e.sum()
+        p = stats.chisquare(o, e).pvalue
+        assert p > 1e-4, (method, p)
+
+
+@pytest.mark.parametrize("ax,ay,mu,phi", CASES[:3])
+def test_cap_matches_disk_two_sample(orc, ax, ay, mu, phi):
+    n = 200000
+    b_edges = np.linspace(0, np.pi / 2, 17)
+    p_edges = np.linspace(0, 2 * np.pi, 33)
+    hc, _ = orc.vndf_sample(_wi(mu, phi, n), np.full(n, ax), np.full(n, ay), seed=101,
+                            method=0)
+    hd, _ = orc.vndf_sample(_wi(mu, phi, n), np.full(n, ax), np.full(n, ay), seed=202,
+                            method=1)
+    A = _hist(hc, ax, ay, b_edges, p_edges).ravel()
+    B = _hist(hd, ax, ay, b_edges, p_edges).ravel()
+    keep = (A + B) >= 10
+    table = np.stack([A[keep], B[keep]])
+    p = stats.chi2_contingency(table)[1]
+    assert p > 1e-4
+
+
+def test_domain_and_stream_offset(orc):
+    n = 6
+    wi = (np.zeros(n), np.zeros(n), np.array([1.0, 0.0, -0.5, 1.0, 1.0, 0.5]))
+    ax = np.array([0.5, 0.5, 0.5, 0.0, 0.5, -1.0])
+    ay = np.array([0.5, 0.5, 0.5, 0.5, 0.0, 0.5])
+    h, pdf = orc.vndf_sample(wi, ax, ay, seed=1)
+    assert pdf[0] > 0.0
+    for i in range(1, 6):
+        assert tuple(h[i]) == (0.0, 0.0, 1.0) and pdf[i] == 0.0
+    d = workloads.tuples_small(300, seed=2)
+    wi = (d["wx"], d["wy"], d["wz"])
+    hA, pA = orc.vndf_sample(wi, d["ax"], d["ay"], seed=4, index_base=0)
+    hB, pB = orc.vndf_sample(tuple(c[100:] for c in wi), d["ax"][100:], d["ay"][100:],
+                             seed=4, index_base=100)
+    assert np.array_equal(hA[100:], hB) and np.array_equal(pA[100:], pB)
