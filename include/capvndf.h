@@ -1,0 +1,279 @@
+/*
+ * capvndf -- spherical-cap sampling of visible GGX normals on MI355X (gfx950).
+ *
+ * C ABI of libcapvndf.so.  Method: J. Dupuy and A. Benyoub, "Sampling Visible
+ * GGX Normals with Spherical Caps" (arXiv 2306.05044).  Section, equation and
+ * appendix references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are caller-owned DEVICE pointers (for example a torch tensor's
+ *    data_ptr()), FP32 unless stated, contiguous, at least 4-byte aligned.
+ *    Structure-of-arrays layout: one array per vector component.
+ *    16-byte alignment of every array (and an even index_base) selects the
+ *    vectorised path; otherwise a scalar path gives identical results.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls only enqueue work: they return before the GPU has finished and
+ *    never synchronise.  Enqueued work reads inputs and writes outputs
+ *    asynchronously, so buffers must stay alive until the stream reaches it.
+ *  - The library never allocates on these calls, except the batch-plan calls
+ *    (which own their chunk tables, partial buffers and graph).
+ *  - Return value: CAPVNDF_OK (0) or a negative CAPVNDF_ERR_* code.  All
+ *    argument checks happen on the host before any launch; on error nothing
+ *    is enqueued and capvndf_last_error() describes the problem (the message
+ *    is per thread and kept until the next failing call on that thread).
+ *    No C++ exception crosses the ABI.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key
+ *    (lo32(seed), hi32(seed)) and counter (lo32(k>>1), unit, tag, hi32(k>>1));
+ *    sample k takes words (w0, w1) when k is even and (w2, w3) when odd, and
+ *    u = (w >> 8) * 2^-24.  Tags: 2 = vndf_sample (unit 0, k = index_base + i),
+ *    3 = albedo estimators (unit = cell or job index, k = sample index).
+ *  - Domain: directions need w_z > 0 and roughness alpha > 0.  Elements
+ *    outside it give h = (0, 0, 1) and pdf = 0; albedo cells or jobs outside
+ *    it give 0 values and 0 gradients.  Inputs in the documented ranges never
+ *    produce NaN.
+ */
+#ifndef CAPVNDF_H
+#define CAPVNDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CAPVNDF_OK 0
+#define CAPVNDF_ERR_NULL_PTR (-1)
+#define CAPVNDF_ERR_BAD_SIZE (-2)
+#define CAPVNDF_ERR_MISALIGNED (-3)
+#define CAPVNDF_ERR_BAD_METHOD (-4)
+#define CAPVNDF_ERR_WORKSPACE (-5)
+#define CAPVNDF_ERR_HIP (-6)
+#define CAPVNDF_ERR_BAD_ARG (-7)
+
+/* Hemisphere routine used inside the general VNDF sampler (Sec. 2, steps 1-3). */
+#define CAPVNDF_CAP 0      /* spherical cap, Sec. 3.3 (the paper's method)   */
+#define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
+
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int32_t capvndf_version(void);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* capvndf_last_error(void);
+
+/*
+ * vndf_sample -- draw n GGX visible normals, Sec. 2 "Importance Sampling"
+ * (warp wi by M^-1 = diag(ax, ay, 1), sample the hemisphere's visible normals,
+ * warp back by M^-T and normalise) with the hemisphere routine `method`:
+ * CAPVNDF_CAP = Sec. 3.3 (uniform point c on the cap z in (-z_i, 1], half
+ * vector c + wi), CAPVNDF_DISK2018 = Heitz's cross-section sampler.
+ *
+ *   n            number of tuples (>= 0; 0 enqueues nothing)
+ *   wix,wiy,wiz  view directions wi (need not be unit; w_z > 0)       [n]
+ *   ax, ay       roughness alpha_x, alpha_y (> 0); may alias          [n]
+ *   u1, u2       uniforms in [0, 1) (u1 -> azimuth, u2 -> height, u2 = 0 at
+ *                the cap's apex; values outside [0, 1) give unspecified
+ *                results), or both NULL to draw them from Philox tag 2 at
+ *                sample index index_base + i                            [n]
+ *   seed         Philox key (ignored when u1/u2 are given)
+ *   index_base   offset of this call in the Philox stream
+ *   hx, hy, hz   out: unit microfacet normals h                        [n]
+ *   pdf          out (nullable): VNDF pdf of Eq. (1) at the sample,
+ *                G1(wi) max(0, wi.h) D(h) / w_z, per unit solid angle  [n]
+ * Errors: NULL_PTR (a required array is NULL or only one of u1/u2 given),
+ * BAD_SIZE (n < 0), MISALIGNED (not 4-byte aligned), BAD_METHOD, HIP.
+ */
+int32_t vndf_sample(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                    const float* ax, const float* ay, const float* u1, const float* u2,
+                    uint64_t seed, uint64_t index_base, int32_t method, float* hx, float* hy,
+                    float* hz, float* pdf, void* stream);
+
+/*
+ * vndf_pdf -- VNDF pdf of Eq. (1) (a linearly transformed hemisphere VNDF,
+ * Eqs. (2)-(4)) at caller-given unit normals h seen from wi:
+ * pdf = G1(wi) max(0, wi.h) D(h) / w_z with D and G1 of Appendix A.
+ *
+ *   n; wix,wiy,wiz [n]; hx,hy,hz unit normals [n]; ax, ay [n]; pdf out [n].
+ * pdf is 0 when w_z <= 0, h_z <= 0, wi.h <= 0 or alpha <= 0.
+ * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, HIP.
+ */
+int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                 const float* hx, const float* hy, const float* hz, const float* ax,
+                 const float* ay, float* pdf, void* stream);
+
+/*
+ * albedo_workspace_size -- bytes of device workspace that albedo_estimate
+ * (with_grad = 0) or albedo_estimate_backward (with_grad = 1) needs for
+ * ncells cells of nsamples samples each.  Returns 0 for invalid sizes.
+ */
+size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t with_grad);
+
+/*
+ * albedo_estimate -- directional albedo per cell: the Monte Carlo estimator
+ * of Appendix A ("Importance Sampling Using the GGX VNDF") with L == 1.  Each
+ * sample draws h with the cap sampler from the view direction wo, reflects wo
+ * about h (reflection law of Sec. 3.2) and weighs the result by
+ * f_r |cos theta_l| / PDF = F(wo.h) G2(wo, wl) / G1(wo); reflections at or
+ * below the horizon weigh 0 but count.  With Schlick's Fresnel
+ * F = F0 + (1 - F0)(1 - wo.h)^5 the albedo is linear in F0, so one stream
+ * gives both sums:
+ *   s_f1[c] = (1/N) sum G2/G1,  s_f5[c] = (1/N) sum G2/G1 (1 - wo.h)^5,
+ *   A(F0)   = F0 s_f1 + (1 - F0) s_f5.
+ * Sums are compensated (TwoSum) and reduced in a fixed order, so results are
+ * bitwise reproducible.
+ *
+ *   ncells               number of cells (>= 0)
+ *   wox,woy,woz [ncells] view directions (normalised internally; wo_z > 0)
+ *   ax, ay      [ncells] roughness
+ *   nsamples             samples per cell N (>= 0, < 2^40)
+ *   seed                 Philox key; cell c uses unit c of tag 3
+ *   s_f1, s_f5  [ncells] out
+ *   workspace            device scratch of albedo_workspace_size(ncells,
+ *                        nsamples, 0) bytes, 16-byte aligned (NULL if 0)
+ * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, WORKSPACE (too small), HIP.
+ */
+int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy, const float* woz,
+                        const float* ax, const float* ay, int64_t nsamples, uint64_t seed,
+                        float* s_f1, float* s_f5, void* workspace, size_t workspace_bytes,
+                        void* stream);
+
+/*
+ * albedo_estimate_backward -- pathwise (reparameterised) adjoint of the
+ * estimator above for A(F0) = (1/N) sum F G2/G1: the same samples, recomputed
+ * from the Philox counter (nothing is stored), differentiated at fixed
+ * (u1, u2) through the stretch, the cap map, the unstretch, the reflection,
+ * G1/G2 and Fresnel.  The weight is continuous where the reflection crosses
+ * the horizon, so the pathwise gradient is unbiased.
+ *
+ *   (same cell inputs, nsamples and seed as albedo_estimate)
+ *   f0          [ncells] Fresnel F0 per cell (NULL = 1)
+ *   grad_albedo [ncells] upstream gradient dL/dA (NULL = 1)
+ *   grad_ax, grad_ay [ncells] out: dL/dA * dA/d alpha_x, dA/d alpha_y
+ *   grad_theta_o     [ncells] out: dL/dA * dA/d theta_o, the derivative along
+ *                    the meridian of wo at fixed azimuth
+ *                    (dwo/dtheta = (cos t cos p, cos t sin p, -sin t); at the
+ *                    pole the azimuth is taken as 0)
+ *   workspace        albedo_workspace_size(ncells, nsamples, 1) bytes
+ * Errors: as albedo_estimate.
+ */
+int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* woy,
+                                 const float* woz, const float* ax, const float* ay,
+                                 int64_t nsamples, uint64_t seed, const float* f0,
+                                 const float* grad_albedo, float* grad_ax, float* grad_ay,
+                                 float* grad_theta_o, void* workspace, size_t workspace_bytes,
+                                 void* stream);
+
+/*
+ * Batched estimation of many jobs with uneven sample counts (forward value
+ * A_j(F0_j) plus, with with_grad, dA_j/d alpha_x, dA_j/d alpha_y and
+ * dA_j/d theta_o), in one persistent launch plus a fixed-order finishing pass,
+ * captured once into a HIP graph and replayed by albedo_batch_run.  Job j uses
+ * unit j of tag 3, so its values equal albedo_estimate/backward on that job.
+ *
+ * Tiling: block size, pairs of samples per thread per chunk (multiple of 8)
+ * and resident blocks per compute unit.
+ */
+typedef struct capvndf_tiling {
+    int32_t block;          /* 256 or 512 threads                            */
+    int32_t pairs_per_thread; /* chunk = block * pairs_per_thread * 2 samples */
+    int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu          */
+    int32_t reserved;
+} capvndf_tiling;
+
+typedef struct capvndf_batch_plan capvndf_batch_plan;
+
+/*
+ * albedo_batch_plan_create -- plan the batch and capture its graph.
+ *   njobs                 number of jobs (>= 1)
+ *   wox..ay      [njobs]  device job parameters (as albedo_estimate)
+ *   f0           [njobs]  device Fresnel F0 per job (NULL = 1)
+ *   nsamples_host[njobs]  HOST array of sample counts (>= 0, < 2^40)
+ *   seed                  Philox key
+ *   with_grad             0: values only; 1: values and gradients
+ *   albedo       [njobs]  device out: A_j(F0_j)
+ *   grad_ax, grad_ay, grad_theta_o [njobs] device out (ignored if !with_grad)
+ *   tiling                NULL: the tuned tiling cached for this problem
+ *                         signature (CAPVNDF_TUNE_CACHE file) or a default
+ *   stream                stream used for the capture
+ *   out                   receives the plan
+ * The plan keeps the pointers: they must stay valid while the plan is used,
+ * and new buffers need a new plan.  Errors: NULL_PTR, BAD_SIZE, BAD_ARG, HIP.
+ */
+int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, const float* woy,
+                                 const float* woz, const float* ax, const float* ay,
+                                 const float* f0, const int64_t* nsamples_host, uint64_t seed,
+                                 int32_t with_grad, float* albedo, float* grad_ax, float* grad_ay,
+                                 float* grad_theta_o, const capvndf_tiling* tiling, void* stream,
+                                 capvndf_batch_plan** out);
+
+/* Replay the plan's graph on `stream` (one hipGraphLaunch). */
+int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream);
+
+/* Same jobs and outputs as albedo_batch_run, launched the per-request way:
+ * two kernels (estimate + finish) per job for the value and two more per job
+ * for the gradient, no graph.  The baseline the batch is measured against. */
+int32_t albedo_batch_run_per_request(capvndf_batch_plan* plan, void* stream);
+
+/* Tiling and chunk statistics of a plan. */
+int32_t albedo_batch_plan_info(const capvndf_batch_plan* plan, capvndf_tiling* tiling,
+                               int64_t* nchunks, int64_t* total_samples);
+
+/* Free the plan, its device buffers and its graph (NULL is a no-op).  Call it
+ * only when no replay is pending. */
+void albedo_batch_plan_destroy(capvndf_batch_plan* plan);
+
+/*
+ * albedo_batch_autotune -- time candidate tilings on the given jobs (replays
+ * on `stream`, synchronising it) and return the fastest in *best and its mean
+ * time per run in *best_ms.  When CAPVNDF_TUNE_CACHE names a file, the result
+ * is stored there under the problem signature for later plans.
+ * Arguments as albedo_batch_plan_create; outputs are overwritten.
+ */
+int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const float* woy,
+                              const float* woz, const float* ax, const float* ay,
+                              const float* f0, const int64_t* nsamples_host, uint64_t seed,
+                              int32_t with_grad, float* albedo, float* grad_ax, float* grad_ay,
+                              float* grad_theta_o, void* stream, capvndf_tiling* best,
+                              float* best_ms);
+
+/*
+ * Random-number and measurement hooks.
+ *
+ * capvndf_uniforms -- the (u1, u2) of samples k0 .. k0+n-1 of stream
+ * (seed, tag, unit), written to device arrays u1, u2 [n] (FP32, exact).
+ */
+int32_t capvndf_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, uint64_t k0, int64_t n,
+                         float* u1, float* u2, void* stream);
+
+/* capvndf_philox_blocks -- raw Philox4x32-10 of n counters: ctr and out are
+ * device uint32 arrays of 4n words (counter i at 4i..4i+3); key is (k0, k1). */
+int32_t capvndf_philox_blocks(int64_t n, const uint32_t* ctr, uint32_t key0, uint32_t key1,
+                              uint32_t* out, void* stream);
+
+/*
+ * vndf_microbench -- register-resident sampler benchmark in the shape of the
+ * paper's GPU benchmark (Sec. 4, "GPU Synthetic Benchmark": the general
+ * sampler called 64 times per lane): each of `lanes` lanes draws its view
+ * direction and roughness once, then calls the sampler `iters` times on
+ * cheap low-discrepancy uniforms and a view elevation that changes every call,
+ * folding h into one word written to out[lane] (device, [lanes]).
+ */
+int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters, uint64_t seed,
+                        uint32_t* out, void* stream);
+
+/*
+ * capvndf_stream_probe -- plain streaming kernel with the sampler's memory
+ * traffic (5 FP32 arrays read, 4 written, same vector width and launch
+ * shape): out0 = in0 + in4, out1 = in1, out2 = in2, out3 = in3.  Measures
+ * the achievable HBM bandwidth and calibrates hardware byte counters.
+ */
+int32_t capvndf_stream_probe(int64_t n, const float* in0, const float* in1, const float* in2,
+                             const float* in3, const float* in4, float* out0, float* out1,
+                             float* out2, float* out3, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CAPVNDF_H */

@@ -1,0 +1,339 @@
+"""Spherical-cap GGX VNDF sampling on MI355X -- Python binding of libcapvndf.so.
+
+Method: Dupuy and Benyoub, "Sampling Visible GGX Normals with Spherical Caps"
+(arXiv 2306.05044).  Every step of the path runs in the HIP kernels of
+``libcapvndf.so``; this module only marshals torch tensors (device memory and
+the current stream) into the C ABI declared in ``include/capvndf.h``.  There is
+no CPU fallback: without the built library every call raises.
+
+Names mirror the C entry points: ``vndf_sample``, ``vndf_pdf``,
+``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_workspace_size``,
+``BatchPlan`` (``albedo_batch_plan_create`` / ``albedo_batch_run`` /
+``albedo_batch_run_per_request``), ``albedo_batch_autotune``, and the hooks
+``capvndf_uniforms``, ``capvndf_philox_blocks``, ``vndf_microbench`` and
+``capvndf_stream_probe``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime that libcapvndf.so links against
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcapvndf.so")
+
+CAP = 0
+DISK2018 = 1
+TAG_SAMPLE = 2
+TAG_ALBEDO = 3
+
+_METHODS = {"cap": CAP, "disk2018": DISK2018, CAP: CAP, DISK2018: DISK2018}
+
+
+class CapvndfError(RuntimeError):
+    """A libcapvndf call returned an error code."""
+
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed with code {code}: {msg}")
+        self.code = code
+
+
+class Tiling(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("pairs_per_thread", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.block, self.pairs_per_thread, self.blocks_per_cu)
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_I32 = ctypes.c_int32
+_U32 = ctypes.c_uint32
+
+_SIGNATURES = {
+    "capvndf_version": ([], _I32),
+    "capvndf_last_error": ([], ctypes.c_char_p),
+    "vndf_sample": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _U64, _I32, _P, _P, _P, _P, _P], _I32),
+    "vndf_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "albedo_workspace_size": ([_I64, _I64, _I32], ctypes.c_size_t),
+    "albedo_estimate": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, ctypes.c_size_t, _P],
+                        _I32),
+    "albedo_estimate_backward": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, _P, _P, _P,
+                                  ctypes.c_size_t, _P], _I32),
+    "albedo_batch_plan_create": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _I32, _P, _P, _P, _P,
+                                  ctypes.POINTER(Tiling), _P, ctypes.POINTER(_P)], _I32),
+    "albedo_batch_run": ([_P, _P], _I32),
+    "albedo_batch_run_per_request": ([_P, _P], _I32),
+    "albedo_batch_plan_info": ([_P, ctypes.POINTER(Tiling), ctypes.POINTER(_I64),
+                                ctypes.POINTER(_I64)], _I32),
+    "albedo_batch_plan_destroy": ([_P], None),
+    "albedo_batch_autotune": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _I32, _P, _P, _P, _P, _P,
+                               ctypes.POINTER(Tiling), ctypes.POINTER(ctypes.c_float)], _I32),
+    "capvndf_uniforms": ([_U64, _U32, _U32, _U64, _I64, _P, _P, _P], _I32),
+    "capvndf_philox_blocks": ([_I64, _P, _U32, _U32, _P, _P], _I32),
+    "vndf_microbench": ([_I32, _I64, _I32, _U64, _P, _P], _I32),
+    "capvndf_stream_probe": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcapvndf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libcapvndf.so not found at {path}: build it first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _check(fn, rc):
+    if rc != 0:
+        msg = load_library().capvndf_last_error().decode(errors="replace")
+        raise CapvndfError(fn, rc, msg)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, name, dtype=torch.float32):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (there is no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _same_len(n, **ts):
+    for k, t in ts.items():
+        if t is not None and t.numel() != n:
+            raise ValueError(f"{k} has {t.numel()} elements, expected {n}")
+
+
+def version() -> int:
+    return int(load_library().capvndf_version())
+
+
+def vndf_sample(wix, wiy, wiz, ax, ay, u1=None, u2=None, seed=0, index_base=0, method="cap",
+                with_pdf=True, out=None, stream=None):
+    """GGX VNDF samples h (and pdf) for SoA float32 GPU tensors; see
+    include/capvndf.h.  Returns (hx, hy, hz, pdf_or_None)."""
+    lib = load_library()
+    n = wix.numel()
+    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, ax=ax, ay=ay, u1=u1, u2=u2).items():
+        _dev(t, k)
+    _same_len(n, wiy=wiy, wiz=wiz, ax=ax, ay=ay, u1=u1, u2=u2)
+    if out is None:
+        hx, hy, hz = (torch.empty_like(wix) for _ in range(3))
+        pdf = torch.empty_like(wix) if with_pdf else None
+    else:
+        hx, hy, hz, pdf = out
+        for k, t in dict(hx=hx, hy=hy, hz=hz, pdf=pdf).items():
+            _dev(t, k)
+        _same_len(n, hx=hx, hy=hy, hz=hz, pdf=pdf)
+    m = _METHODS.get(method, method)
+    rc = lib.vndf_sample(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(ax), _ptr(ay), _ptr(u1),
+                         _ptr(u2), seed, index_base, m, _ptr(hx), _ptr(hy), _ptr(hz), _ptr(pdf),
+                         _stream(stream))
+    _check("vndf_sample", rc)
+    return hx, hy, hz, pdf
+
+
+def vndf_pdf(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
+    """VNDF pdf of Eq. (1) at given unit normals."""
+    lib = load_library()
+    n = wix.numel()
+    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, hx=hx, hy=hy, hz=hz, ax=ax, ay=ay).items():
+        _dev(t, k)
+    _same_len(n, wiy=wiy, wiz=wiz, hx=hx, hy=hy, hz=hz, ax=ax, ay=ay)
+    pdf = torch.empty_like(wix) if out is None else _dev(out, "out")
+    rc = lib.vndf_pdf(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(hx), _ptr(hy), _ptr(hz), _ptr(ax),
+                      _ptr(ay), _ptr(pdf), _stream(stream))
+    _check("vndf_pdf", rc)
+    return pdf
+
+
+def albedo_workspace_size(ncells: int, nsamples: int, with_grad: bool) -> int:
+    return int(load_library().albedo_workspace_size(ncells, nsamples, 1 if with_grad else 0))
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(1, (nbytes + 3) // 4), dtype=torch.float32, device=device)
+
+
+def albedo_estimate(wox, woy, woz, ax, ay, nsamples, seed, workspace=None, stream=None):
+    """(s_f1, s_f5) per cell: A(F0) = F0 s_f1 + (1 - F0) s_f5."""
+    lib = load_library()
+    n = wox.numel()
+    for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay).items():
+        _dev(t, k)
+    _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay)
+    nbytes = albedo_workspace_size(n, nsamples, False)
+    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    s1 = torch.empty_like(wox)
+    s5 = torch.empty_like(wox)
+    rc = lib.albedo_estimate(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), nsamples,
+                             seed, _ptr(s1), _ptr(s5), _ptr(ws), ws.numel() * 4, _stream(stream))
+    _check("albedo_estimate", rc)
+    return s1, s5
+
+
+def albedo_estimate_backward(wox, woy, woz, ax, ay, nsamples, seed, f0=None, grad_albedo=None,
+                             workspace=None, stream=None):
+    """(grad_ax, grad_ay, grad_theta_o) per cell for A(F0), times grad_albedo."""
+    lib = load_library()
+    n = wox.numel()
+    for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0,
+                     grad_albedo=grad_albedo).items():
+        _dev(t, k)
+    _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0, grad_albedo=grad_albedo)
+    nbytes = albedo_workspace_size(n, nsamples, True)
+    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    gx, gy, gt = (torch.empty_like(wox) for _ in range(3))
+    rc = lib.albedo_estimate_backward(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
+                                      nsamples, seed, _ptr(f0), _ptr(grad_albedo), _ptr(gx),
+                                      _ptr(gy), _ptr(gt), _ptr(ws), ws.numel() * 4,
+                                      _stream(stream))
+    _check("albedo_estimate_backward", rc)
+    return gx, gy, gt
+
+
+class BatchPlan:
+    """Batched forward (+ adjoint) estimation of uneven jobs; one graph replay
+    per run().  Holds the output tensors it writes."""
+
+    def __init__(self, wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_grad=True,
+                 tiling=None, stream=None):
+        lib = load_library()
+        n = wox.numel()
+        for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0).items():
+            _dev(t, k)
+        _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
+        ns = torch.as_tensor(nsamples, dtype=torch.int64).cpu().contiguous()
+        if ns.numel() != n:
+            raise ValueError("nsamples must have one entry per job")
+        self._inputs = (wox, woy, woz, ax, ay, f0, ns)
+        self.albedo = torch.empty_like(wox)
+        self.grad_ax = torch.empty_like(wox) if with_grad else None
+        self.grad_ay = torch.empty_like(wox) if with_grad else None
+        self.grad_theta_o = torch.empty_like(wox) if with_grad else None
+        t = None
+        if tiling is not None:
+            t = Tiling(int(tiling[0]), int(tiling[1]), int(tiling[2]), 0)
+        plan = ctypes.c_void_p()
+        rc = lib.albedo_batch_plan_create(
+            n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), _ptr(f0),
+            ctypes.c_void_p(ns.data_ptr()), seed, 1 if with_grad else 0, _ptr(self.albedo),
+            _ptr(self.grad_ax), _ptr(self.grad_ay), _ptr(self.grad_theta_o),
+            ctypes.byref(t) if t is not None else None, _stream(stream), ctypes.byref(plan))
+        _check("albedo_batch_plan_create", rc)
+        self._plan = plan
+
+    def run(self, stream=None):
+        _check("albedo_batch_run", load_library().albedo_batch_run(self._plan, _stream(stream)))
+
+    def run_per_request(self, stream=None):
+        _check("albedo_batch_run_per_request",
+               load_library().albedo_batch_run_per_request(self._plan, _stream(stream)))
+
+    def info(self):
+        t = Tiling()
+        nch = _I64()
+        tot = _I64()
+        _check("albedo_batch_plan_info",
+               load_library().albedo_batch_plan_info(self._plan, ctypes.byref(t),
+                                                     ctypes.byref(nch), ctypes.byref(tot)))
+        return {"tiling": t.as_tuple(), "nchunks": nch.value, "total_samples": tot.value}
+
+    def close(self):
+        if getattr(self, "_plan", None):
+            load_library().albedo_batch_plan_destroy(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def albedo_batch_autotune(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_grad=True,
+                          stream=None):
+    """Time candidate tilings on these jobs; returns ((block, ppt, bpc), ms)."""
+    lib = load_library()
+    n = wox.numel()
+    ns = torch.as_tensor(nsamples, dtype=torch.int64).cpu().contiguous()
+    outs = [torch.empty_like(wox) for _ in range(4)]
+    best = Tiling()
+    ms = ctypes.c_float()
+    rc = lib.albedo_batch_autotune(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
+                                   _ptr(f0), ctypes.c_void_p(ns.data_ptr()), seed,
+                                   1 if with_grad else 0, *[_ptr(o) for o in outs],
+                                   _stream(stream), ctypes.byref(best), ctypes.byref(ms))
+    _check("albedo_batch_autotune", rc)
+    return best.as_tuple(), ms.value
+
+
+def capvndf_uniforms(seed, tag, unit, k0, n, device="cuda", stream=None):
+    """(u1, u2) of samples k0..k0+n-1 of Philox stream (seed, tag, unit)."""
+    u1 = torch.empty(n, dtype=torch.float32, device=device)
+    u2 = torch.empty(n, dtype=torch.float32, device=device)
+    _check("capvndf_uniforms", load_library().capvndf_uniforms(
+        seed, tag, unit, k0, n, _ptr(u1), _ptr(u2), _stream(stream)))
+    return u1, u2
+
+
+def capvndf_philox_blocks(ctr, key0, key1, stream=None):
+    """Raw Philox4x32-10 of an int32 (n, 4) counter tensor (bit patterns)."""
+    _dev(ctr, "ctr", torch.int32)
+    out = torch.empty_like(ctr)
+    _check("capvndf_philox_blocks", load_library().capvndf_philox_blocks(
+        ctr.numel() // 4, _ptr(ctr), key0, key1, _ptr(out), _stream(stream)))
+    return out
+
+
+def vndf_microbench(method, lanes, iters, seed=1, out=None, stream=None):
+    """Register-resident sampler benchmark; returns the per-lane int32 fold."""
+    o = torch.empty(lanes, dtype=torch.int32, device="cuda") if out is None else out
+    _check("vndf_microbench", load_library().vndf_microbench(
+        _METHODS.get(method, method), lanes, iters, seed, _ptr(o), _stream(stream)))
+    return o
+
+
+def capvndf_stream_probe(ins, outs, stream=None):
+    """Streaming probe over 5 input and 4 output float32 GPU tensors."""
+    n = ins[0].numel()
+    _check("capvndf_stream_probe", load_library().capvndf_stream_probe(
+        n, *[_ptr(t) for t in ins], *[_ptr(t) for t in outs], _stream(stream)))
+
+
+from .autograd import AlbedoFunction, albedo  # noqa: E402,F401

@@ -1,0 +1,774 @@
+// Directional-albedo estimator kernels: forward (two sums from one stream),
+// pathwise adjoint, the batched persistent forward+adjoint kernel and the
+// fixed-order finishing pass, plus their C entry points.
+//
+// Work decomposition: a cell (or job) of N samples is N/2 Philox pairs, cut
+// into chunks of block * pairs_per_thread pairs.  One block reduces one chunk
+// to a compensated partial (lane TwoSum accumulators -> wavefront butterfly ->
+// LDS across waves); the finishing pass merges a cell's chunk partials in
+// chunk order.  No atomics anywhere, so every result is bitwise reproducible.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "albedo_math.hpp"
+#include "common.hpp"
+
+namespace capvndf {
+namespace {
+
+constexpr int kLutBlock = 256;
+constexpr int kLutPairsPerThread = 32;
+constexpr uint64_t kLutChunkPairs = (uint64_t)kLutBlock * kLutPairsPerThread;
+constexpr int kGroup = 8;  // pairs summed plainly before each TwoSum fold
+constexpr int kFinishBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Comp wave_reduce(Comp v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Comp o;
+        o.s = __shfl_xor(v.s, off, 64);
+        o.c = __shfl_xor(v.c, off, 64);
+        v = comp_merge(v, o);
+    }
+    return v;
+}
+
+// Reduce NACC compensated accumulators over the block and store them as
+// (s, c) pairs at dst[0 .. 2*NACC).  Must be reached by every thread.
+template <int NACC, int BLOCK>
+__device__ __forceinline__ void block_reduce_store(Comp (&acc)[NACC], float* __restrict__ dst) {
+    __shared__ Comp red[BLOCK / 64][NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) acc[a] = wave_reduce(acc[a]);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) red[wave][a] = acc[a];
+    }
+    __syncthreads();
+    if (threadIdx.x < NACC) {
+        const int a = threadIdx.x;
+        Comp r = red[0][a];
+        for (int w = 1; w < BLOCK / 64; ++w) r = comp_merge(r, red[w][a]);
+        dst[2 * a] = r.s;
+        dst[2 * a + 1] = r.c;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Per-thread sample loops over pairs [pbeg, pend) with stride BLOCK.
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uint64_t pend,
+                                          uint64_t nsamples, uint32_t unit, uint32_t k0,
+                                          uint32_t k1, Comp (&acc)[2]) {
+    for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)BLOCK * kGroup) {
+        float sg = 0.0f, sgm = 0.0f;
+#pragma unroll 2
+        for (int j = 0; j < kGroup; ++j) {
+            const uint64_t p = p0 + (uint64_t)j * BLOCK;
+            if (p < pend) {
+                const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
+                const FwdTerm t0 = albedo_fwd(c, unit24(w.w0), unit24(w.w1));
+                sg += t0.g;
+                sgm = __builtin_fmaf(t0.g, t0.m5, sgm);
+                if (2 * p + 1 < nsamples) {
+                    const FwdTerm t1 = albedo_fwd(c, unit24(w.w2), unit24(w.w3));
+                    sg += t1.g;
+                    sgm = __builtin_fmaf(t1.g, t1.m5, sgm);
+                }
+            }
+        }
+        comp_add(acc[0], sg);
+        comp_add(acc[1], sgm);
+    }
+}
+
+// Adjoint loop: accumulates w, the direct derivatives and the adjoint of ws,
+// then chains ws into (alpha_x, alpha_y, theta_o).  out = {w, gax, gay, gth}.
+template <int BLOCK>
+__device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t pbeg,
+                                          uint64_t pend, uint64_t nsamples, uint32_t unit,
+                                          uint32_t k0, uint32_t k1, Comp (&out)[4]) {
+    Comp acc[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) acc[a] = Comp{0.0f, 0.0f};
+    for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)BLOCK * kGroup) {
+        float part[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+        for (int j = 0; j < kGroup; ++j) {
+            const uint64_t p = p0 + (uint64_t)j * BLOCK;
+            if (p < pend) {
+                const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
+                const AdjTerm t0 = albedo_adj(c, f0, unit24(w.w0), unit24(w.w1));
+                part[0] += t0.w; part[1] += t0.dax; part[2] += t0.day; part[3] += t0.dth;
+                part[4] += t0.dwsx; part[5] += t0.dwsy; part[6] += t0.dzs;
+                if (2 * p + 1 < nsamples) {
+                    const AdjTerm t1 = albedo_adj(c, f0, unit24(w.w2), unit24(w.w3));
+                    part[0] += t1.w; part[1] += t1.dax; part[2] += t1.day; part[3] += t1.dth;
+                    part[4] += t1.dwsx; part[5] += t1.dwsy; part[6] += t1.dzs;
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 7; ++a) comp_add(acc[a], part[a]);
+    }
+    float gax = acc[1].s + acc[1].c;
+    float gay = acc[2].s + acc[2].c;
+    float gth = acc[3].s + acc[3].c;
+    ws_chain(c, acc[4].s + acc[4].c, acc[5].s + acc[5].c, acc[6].s + acc[6].c, gax, gay, gth);
+    out[0] = acc[0];
+    out[1] = Comp{gax, 0.0f};
+    out[2] = Comp{gay, 0.0f};
+    out[3] = Comp{gth, 0.0f};
+}
+
+// ---------------------------------------------------------------------------
+// Uniform-N kernels (one cell per group of `cpc` consecutive blocks).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
+    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
+    const float* __restrict__ ax, const float* __restrict__ ay, uint64_t nsamples, int32_t cpc,
+    uint32_t unit_base, uint32_t k0, uint32_t k1, float* __restrict__ partial) {
+    const int64_t b = blockIdx.x;
+    const int64_t cell = b / cpc;
+    const int64_t chunk = b - cell * cpc;
+    const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
+    Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+    const uint64_t npairs = (nsamples + 1) / 2;
+    const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
+    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+    if (c.ok)
+        pairs_fwd<kLutBlock>(c, pbeg, pend, nsamples, unit_base + (uint32_t)cell, k0, k1, acc);
+    block_reduce_store<2, kLutBlock>(acc, partial + b * 4);
+}
+
+__global__ __launch_bounds__(kLutBlock) void k_albedo_bwd(
+    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
+    uint64_t nsamples, int32_t cpc, uint32_t unit_base, uint32_t k0, uint32_t k1,
+    float* __restrict__ partial) {
+    const int64_t b = blockIdx.x;
+    const int64_t cell = b / cpc;
+    const int64_t chunk = b - cell * cpc;
+    const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
+    const float f0 = f0p ? f0p[cell] : 1.0f;
+    Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+    const uint64_t npairs = (nsamples + 1) / 2;
+    const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
+    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+    if (c.ok)
+        pairs_adj<kLutBlock>(c, f0, pbeg, pend, nsamples, unit_base + (uint32_t)cell, k0, k1, out);
+    Comp g[3] = {out[1], out[2], out[3]};
+    block_reduce_store<3, kLutBlock>(g, partial + b * 6);
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent kernel: block b walks its static range of chunks
+// [block_chunks[b], block_chunks[b+1]); each chunk is (job, pair range).
+// ---------------------------------------------------------------------------
+template <int BLOCK, bool GRAD>
+__global__ __launch_bounds__(BLOCK) void k_batch(
+    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
+    const int64_t* __restrict__ nsamp, const int32_t* __restrict__ chunk_job,
+    const int64_t* __restrict__ chunk_pbeg, const int64_t* __restrict__ chunk_pend,
+    const int32_t* __restrict__ block_chunks, uint32_t k0, uint32_t k1,
+    float* __restrict__ partial) {
+    const int32_t cb = block_chunks[blockIdx.x];
+    const int32_t ce = block_chunks[blockIdx.x + 1];
+    for (int32_t ch = cb; ch < ce; ++ch) {
+        const int32_t j = chunk_job[ch];
+        const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
+        const float f0 = f0p ? f0p[j] : 1.0f;
+        const uint64_t n = (uint64_t)nsamp[j];
+        const uint64_t pbeg = (uint64_t)chunk_pbeg[ch];
+        const uint64_t pend = (uint64_t)chunk_pend[ch];
+        if (GRAD) {
+            Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+            if (c.ok) pairs_adj<BLOCK>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out);
+            block_reduce_store<4, BLOCK>(out, partial + (int64_t)ch * 8);
+        } else {
+            Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+            if (c.ok) pairs_fwd<BLOCK>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc);
+            // A(F0) = F0 S1 + (1 - F0) S5, folded per chunk
+            const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
+            Comp w[1] = {Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f}};
+            block_reduce_store<1, BLOCK>(w, partial + (int64_t)ch * 2);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finishing pass: unit u merges its chunk partials in chunk order, divides by
+// its sample count and applies an optional per-unit scale.
+// Chunks of unit u: [u*cpc, (u+1)*cpc) if unit_chunks is NULL, else
+// [unit_chunks[u], unit_chunks[u+1]).
+// ---------------------------------------------------------------------------
+template <int NACC>
+__global__ __launch_bounds__(kFinishBlock) void k_finish(
+    int64_t nunits, const float* __restrict__ partial, int32_t cpc,
+    const int32_t* __restrict__ unit_chunks, const int64_t* __restrict__ nsamp_dev,
+    uint64_t nsamp_uniform, const float* __restrict__ scale, float* __restrict__ o0,
+    float* __restrict__ o1, float* __restrict__ o2, float* __restrict__ o3) {
+    const int64_t u = (int64_t)blockIdx.x * kFinishBlock + threadIdx.x;
+    if (u >= nunits) return;
+    int64_t cb, ce;
+    if (unit_chunks) {
+        cb = unit_chunks[u];
+        ce = unit_chunks[u + 1];
+    } else {
+        cb = u * cpc;
+        ce = cb + cpc;
+    }
+    Comp r[NACC];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) r[a] = Comp{0.0f, 0.0f};
+    for (int64_t ch = cb; ch < ce; ++ch) {
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) {
+            const float* p = partial + (ch * NACC + a) * 2;
+            r[a] = comp_merge(r[a], Comp{p[0], p[1]});
+        }
+    }
+    const uint64_t n = nsamp_dev ? (uint64_t)nsamp_dev[u] : nsamp_uniform;
+    const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
+    const float sc = (scale ? scale[u] : 1.0f) * inv;
+    float* outs[4] = {o0, o1, o2, o3};
+#pragma unroll
+    for (int a = 0; a < NACC; ++a) outs[a][u] = (r[a].s + r[a].c) * sc;
+}
+
+// albedo[j] = F0 s1[j] + (1 - F0) s5[j] (per-request baseline only).
+__global__ __launch_bounds__(kFinishBlock) void k_combine_f0(int64_t n, const float* __restrict__ s1,
+                                                             const float* __restrict__ s5,
+                                                             const float* __restrict__ f0p,
+                                                             float* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * kFinishBlock + threadIdx.x;
+    if (j >= n) return;
+    const float f0 = f0p ? f0p[j] : 1.0f;
+    out[j] = __builtin_fmaf(f0, s1[j], (1.0f - f0) * s5[j]);
+}
+
+inline unsigned finish_grid(int64_t n) { return (unsigned)((n + kFinishBlock - 1) / kFinishBlock); }
+
+inline int64_t lut_chunks_per_cell(int64_t nsamples) {
+    const uint64_t npairs = ((uint64_t)nsamples + 1) / 2;
+    const uint64_t c = (npairs + kLutChunkPairs - 1) / kLutChunkPairs;
+    return c == 0 ? 1 : (int64_t)c;
+}
+
+int32_t check_cells(const char* fn, int64_t ncells, int64_t nsamples, const float* wox,
+                    const float* woy, const float* woz, const float* ax, const float* ay) {
+    if (ncells < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells < 0", fn);
+    if (nsamples < 0 || nsamples >= ((int64_t)1 << 40))
+        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: nsamples must be in [0, 2^40)", fn);
+    if (ncells > 0 && (double)ncells * (double)lut_chunks_per_cell(nsamples) > 2147483647.0)
+        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells * chunks per cell exceeds the grid limit", fn);
+    if (ncells > ((int64_t)1 << 32))
+        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells exceeds the 32-bit stream unit", fn);
+    const void* req[] = {wox, woy, woz, ax, ay};
+    const char* names[] = {"wox", "woy", "woz", "ax", "ay"};
+    if (ncells > 0)
+        for (int i = 0; i < 5; ++i)
+            if (int32_t rc = check_array(req[i], names[i])) return rc;
+    return CAPVNDF_OK;
+}
+
+size_t lut_workspace(int64_t ncells, int64_t nsamples, int nacc) {
+    return (size_t)ncells * (size_t)lut_chunks_per_cell(nsamples) * (size_t)nacc * 2 * sizeof(float);
+}
+
+}  // namespace
+}  // namespace capvndf
+
+using namespace capvndf;
+
+extern "C" size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t with_grad) {
+    if (ncells < 0 || nsamples < 0 || nsamples >= ((int64_t)1 << 40)) return 0;
+    return lut_workspace(ncells, nsamples, with_grad ? 3 : 2);
+}
+
+extern "C" int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy,
+                                   const float* woz, const float* ax, const float* ay,
+                                   int64_t nsamples, uint64_t seed, float* s_f1, float* s_f5,
+                                   void* workspace, size_t workspace_bytes, void* stream) {
+    if (int32_t rc = check_cells("albedo_estimate", ncells, nsamples, wox, woy, woz, ax, ay))
+        return rc;
+    if (ncells == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(s_f1, "s_f1")) return rc;
+    if (int32_t rc = check_array(s_f5, "s_f5")) return rc;
+    const size_t need = lut_workspace(ncells, nsamples, 2);
+    if (workspace_bytes < need || workspace == nullptr)
+        return fail(CAPVNDF_ERR_WORKSPACE, "albedo_estimate: workspace of %zu bytes needed, %zu given",
+                    need, workspace == nullptr ? (size_t)0 : workspace_bytes);
+    if (!aligned_to(workspace, 16))
+        return fail(CAPVNDF_ERR_MISALIGNED, "albedo_estimate: workspace must be 16-byte aligned");
+    const int64_t cpc = lut_chunks_per_cell(nsamples);
+    const hipStream_t st = as_stream(stream);
+    float* part = static_cast<float*>(workspace);
+    hipLaunchKernelGGL(k_albedo_fwd, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox,
+                       woy, woz, ax, ay, (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed),
+                       key_hi(seed), part);
+    if (int32_t rc = check_launch("albedo_estimate launch")) return rc;
+    hipLaunchKernelGGL(k_finish<2>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                       part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr, s_f1,
+                       s_f5, nullptr, nullptr);
+    return check_launch("albedo_estimate finish launch");
+}
+
+extern "C" int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* woy,
+                                            const float* woz, const float* ax, const float* ay,
+                                            int64_t nsamples, uint64_t seed, const float* f0,
+                                            const float* grad_albedo, float* grad_ax,
+                                            float* grad_ay, float* grad_theta_o, void* workspace,
+                                            size_t workspace_bytes, void* stream) {
+    if (int32_t rc = check_cells("albedo_estimate_backward", ncells, nsamples, wox, woy, woz, ax, ay))
+        return rc;
+    if (ncells == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(grad_ax, "grad_ax")) return rc;
+    if (int32_t rc = check_array(grad_ay, "grad_ay")) return rc;
+    if (int32_t rc = check_array(grad_theta_o, "grad_theta_o")) return rc;
+    if (f0 != nullptr)
+        if (int32_t rc = check_array(f0, "f0")) return rc;
+    if (grad_albedo != nullptr)
+        if (int32_t rc = check_array(grad_albedo, "grad_albedo")) return rc;
+    const size_t need = lut_workspace(ncells, nsamples, 3);
+    if (workspace_bytes < need || workspace == nullptr)
+        return fail(CAPVNDF_ERR_WORKSPACE,
+                    "albedo_estimate_backward: workspace of %zu bytes needed, %zu given", need,
+                    workspace == nullptr ? (size_t)0 : workspace_bytes);
+    if (!aligned_to(workspace, 16))
+        return fail(CAPVNDF_ERR_MISALIGNED, "albedo_estimate_backward: workspace must be 16-byte aligned");
+    const int64_t cpc = lut_chunks_per_cell(nsamples);
+    const hipStream_t st = as_stream(stream);
+    float* part = static_cast<float*>(workspace);
+    hipLaunchKernelGGL(k_albedo_bwd, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox,
+                       woy, woz, ax, ay, f0, (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed),
+                       key_hi(seed), part);
+    if (int32_t rc = check_launch("albedo_estimate_backward launch")) return rc;
+    hipLaunchKernelGGL(k_finish<3>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                       part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, grad_albedo,
+                       grad_ax, grad_ay, grad_theta_o, nullptr);
+    return check_launch("albedo_estimate_backward finish launch");
+}
+
+// ===========================================================================
+// Batch plans.
+// ===========================================================================
+struct capvndf_batch_plan {
+    int device = 0;
+    int64_t njobs = 0, nchunks = 0, total_samples = 0;
+    capvndf_tiling tiling{};
+    int grid = 0;
+    int with_grad = 0;
+    uint64_t seed = 0;
+    const float *wox = nullptr, *woy = nullptr, *woz = nullptr, *ax = nullptr, *ay = nullptr,
+                *f0 = nullptr;
+    float *albedo = nullptr, *gax = nullptr, *gay = nullptr, *gth = nullptr;
+    std::vector<int64_t> nsamp_host;
+    // plan-owned device memory: one allocation carved into the tables
+    void* dmem = nullptr;
+    int32_t* d_chunk_job = nullptr;
+    int64_t* d_chunk_pbeg = nullptr;
+    int64_t* d_chunk_pend = nullptr;
+    int32_t* d_block_chunks = nullptr;
+    int32_t* d_job_chunks = nullptr;
+    int64_t* d_nsamp = nullptr;
+    float* d_partial = nullptr;
+    float* d_s1 = nullptr;  // per-request baseline scratch
+    float* d_s5 = nullptr;
+    float* d_req_ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace capvndf {
+namespace {
+
+bool valid_tiling(const capvndf_tiling& t) {
+    return (t.block == 256 || t.block == 512) && t.pairs_per_thread >= kGroup &&
+           t.pairs_per_thread <= 4096 && t.pairs_per_thread % kGroup == 0 &&
+           t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32;
+}
+
+capvndf_tiling default_tiling() { return capvndf_tiling{256, 32, 8, 0}; }
+
+std::string problem_signature(int device, int64_t njobs, int64_t total, int with_grad) {
+    hipDeviceProp_t prop;
+    char arch[64] = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+        for (char* p = arch; *p; ++p)
+            if (*p == ' ' || *p == ':') *p = '_';
+        cus = prop.multiProcessorCount;
+    }
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s/cu%d/jobs%lld/samples%lld/grad%d", arch, cus, (long long)njobs,
+             (long long)total, with_grad);
+    return buf;
+}
+
+// Tuning cache: text lines "<signature> <block> <pairs_per_thread> <blocks_per_cu> <ms>".
+bool cache_lookup(const std::string& sig, capvndf_tiling* out) {
+    const char* path = getenv("CAPVNDF_TUNE_CACHE");
+    if (!path || !*path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char key[256];
+    int b, p, c;
+    float ms;
+    bool found = false;
+    while (fscanf(f, "%255s %d %d %d %f", key, &b, &p, &c, &ms) == 5) {
+        capvndf_tiling t{b, p, c, 0};
+        if (sig == key && valid_tiling(t)) {
+            *out = t;  // last matching line wins
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const std::string& sig, const capvndf_tiling& t, float ms) {
+    const char* path = getenv("CAPVNDF_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %.6f\n", sig.c_str(), t.block, t.pairs_per_thread, t.blocks_per_cu, ms);
+    fclose(f);
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
+    const int g = p->with_grad;
+    const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
+    const dim3 grid((unsigned)p->grid), block((unsigned)p->tiling.block);
+#define CAPVNDF_LAUNCH_BATCH(B, G)                                                                  \
+    hipLaunchKernelGGL((k_batch<B, G>), grid, block, 0, st, p->wox, p->woy, p->woz, p->ax, p->ay, \
+                       p->f0, p->d_nsamp, p->d_chunk_job, p->d_chunk_pbeg, p->d_chunk_pend,        \
+                       p->d_block_chunks, k0, k1, p->d_partial)
+    if (p->tiling.block == 256) {
+        if (g) CAPVNDF_LAUNCH_BATCH(256, true); else CAPVNDF_LAUNCH_BATCH(256, false);
+    } else {
+        if (g) CAPVNDF_LAUNCH_BATCH(512, true); else CAPVNDF_LAUNCH_BATCH(512, false);
+    }
+#undef CAPVNDF_LAUNCH_BATCH
+    if (int32_t rc = check_launch("batch kernel launch")) return rc;
+    if (g)
+        hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
+                           p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, (uint64_t)0,
+                           nullptr, p->albedo, p->gax, p->gay, p->gth);
+    else
+        hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
+                           p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, (uint64_t)0,
+                           nullptr, p->albedo, nullptr, nullptr, nullptr);
+    return check_launch("batch finish launch");
+}
+
+void destroy_plan(capvndf_batch_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->dmem) (void)hipFree(p->dmem);
+    delete p;
+}
+
+int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const float* woz,
+                    const float* ax, const float* ay, const float* f0, const int64_t* nsamples_host,
+                    uint64_t seed, int32_t with_grad, float* albedo, float* grad_ax,
+                    float* grad_ay, float* grad_theta_o, const capvndf_tiling* tiling,
+                    capvndf_batch_plan** out) {
+    if (out == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_plan_create: out is NULL");
+    *out = nullptr;
+    if (njobs < 1 || njobs > ((int64_t)1 << 31) - 2)
+        return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_batch_plan_create: njobs must be in [1, 2^31 - 2]");
+    if (nsamples_host == nullptr)
+        return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_plan_create: nsamples_host is NULL");
+    if (int32_t rc = check_cells("albedo_batch_plan_create", njobs, 0, wox, woy, woz, ax, ay))
+        return rc;
+    if (int32_t rc = check_array(albedo, "albedo")) return rc;
+    if (f0 != nullptr)
+        if (int32_t rc = check_array(f0, "f0")) return rc;
+    if (with_grad != 0 && with_grad != 1)
+        return fail(CAPVNDF_ERR_BAD_ARG, "albedo_batch_plan_create: with_grad must be 0 or 1");
+    if (with_grad) {
+        if (int32_t rc = check_array(grad_ax, "grad_ax")) return rc;
+        if (int32_t rc = check_array(grad_ay, "grad_ay")) return rc;
+        if (int32_t rc = check_array(grad_theta_o, "grad_theta_o")) return rc;
+    }
+    int64_t total = 0, max_n = 0;
+    for (int64_t j = 0; j < njobs; ++j) {
+        const int64_t n = nsamples_host[j];
+        if (n < 0 || n >= ((int64_t)1 << 40))
+            return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_batch_plan_create: nsamples[%lld] out of [0, 2^40)",
+                        (long long)j);
+        total += n;
+        max_n = std::max(max_n, n);
+    }
+    capvndf_tiling t = default_tiling();
+    int device = 0;
+    if (int32_t rc = check_hip(hipGetDevice(&device), "hipGetDevice")) return rc;
+    if (tiling) {
+        if (!valid_tiling(*tiling))
+            return fail(CAPVNDF_ERR_BAD_ARG,
+                        "albedo_batch_plan_create: invalid tiling (block 256|512, pairs_per_thread "
+                        "a multiple of 8 in [8, 4096], blocks_per_cu in [1, 32])");
+        t = *tiling;
+    } else {
+        (void)cache_lookup(problem_signature(device, njobs, total, with_grad), &t);
+    }
+    int cus = 0;
+    if (int32_t rc = check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device),
+                               "hipDeviceGetAttribute"))
+        return rc;
+
+    // Chunk table: job-major, pair ranges of chunk_pairs.
+    const int64_t chunk_pairs = (int64_t)t.block * t.pairs_per_thread;
+    std::vector<int32_t> chunk_job;
+    std::vector<int64_t> pbeg, pend;
+    std::vector<int32_t> job_chunks((size_t)njobs + 1, 0);
+    for (int64_t j = 0; j < njobs; ++j) {
+        job_chunks[j] = (int32_t)chunk_job.size();
+        const int64_t np = (nsamples_host[j] + 1) / 2;
+        for (int64_t b = 0; b < np; b += chunk_pairs) {
+            chunk_job.push_back((int32_t)j);
+            pbeg.push_back(b);
+            pend.push_back(std::min(b + chunk_pairs, np));
+            if (chunk_job.size() > (size_t)0x7fffffff)
+                return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_batch_plan_create: too many chunks");
+        }
+    }
+    job_chunks[njobs] = (int32_t)chunk_job.size();
+    const int64_t nchunks = (int64_t)chunk_job.size();
+
+    // Static partition of the chunks over a persistent grid, balanced by pairs.
+    int64_t grid = std::max<int64_t>(1, (int64_t)cus * t.blocks_per_cu);
+    if (nchunks > 0) grid = std::min<int64_t>(grid, nchunks);
+    std::vector<int32_t> block_chunks((size_t)grid + 1, 0);
+    {
+        double sum = 0.0;
+        for (int64_t c = 0; c < nchunks; ++c) sum += (double)(pend[c] - pbeg[c]);
+        double acc = 0.0;
+        int64_t c = 0;
+        for (int64_t b = 0; b < grid; ++b) {
+            block_chunks[b] = (int32_t)c;
+            const double target = sum * (double)(b + 1) / (double)grid;
+            while (c < nchunks && (acc + 0.5 * (double)(pend[c] - pbeg[c]) <= target || b == grid - 1)) {
+                acc += (double)(pend[c] - pbeg[c]);
+                ++c;
+            }
+        }
+        block_chunks[grid] = (int32_t)nchunks;
+    }
+
+    // Device memory: tables, partials, per-request scratch.
+    const int nacc = with_grad ? 4 : 1;
+    const int64_t max_cpc = lut_chunks_per_cell(max_n);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_cj = carve(sizeof(int32_t) * std::max<int64_t>(nchunks, 1));
+    const size_t o_pb = carve(sizeof(int64_t) * std::max<int64_t>(nchunks, 1));
+    const size_t o_pe = carve(sizeof(int64_t) * std::max<int64_t>(nchunks, 1));
+    const size_t o_bc = carve(sizeof(int32_t) * (size_t)(grid + 1));
+    const size_t o_jc = carve(sizeof(int32_t) * (size_t)(njobs + 1));
+    const size_t o_ns = carve(sizeof(int64_t) * (size_t)njobs);
+    const size_t o_pa = carve(sizeof(float) * 2 * nacc * (size_t)std::max<int64_t>(nchunks, 1));
+    const size_t o_s1 = carve(sizeof(float) * (size_t)njobs);
+    const size_t o_s5 = carve(sizeof(float) * (size_t)njobs);
+    const size_t o_rw = carve(sizeof(float) * 6 * (size_t)max_cpc);
+    capvndf_batch_plan* p = new capvndf_batch_plan();
+    if (int32_t rc = check_hip(hipMalloc(&p->dmem, off), "hipMalloc (batch plan)")) {
+        p->dmem = nullptr;
+        destroy_plan(p);
+        return rc;
+    }
+    char* base = static_cast<char*>(p->dmem);
+    p->d_chunk_job = reinterpret_cast<int32_t*>(base + o_cj);
+    p->d_chunk_pbeg = reinterpret_cast<int64_t*>(base + o_pb);
+    p->d_chunk_pend = reinterpret_cast<int64_t*>(base + o_pe);
+    p->d_block_chunks = reinterpret_cast<int32_t*>(base + o_bc);
+    p->d_job_chunks = reinterpret_cast<int32_t*>(base + o_jc);
+    p->d_nsamp = reinterpret_cast<int64_t*>(base + o_ns);
+    p->d_partial = reinterpret_cast<float*>(base + o_pa);
+    p->d_s1 = reinterpret_cast<float*>(base + o_s1);
+    p->d_s5 = reinterpret_cast<float*>(base + o_s5);
+    p->d_req_ws = reinterpret_cast<float*>(base + o_rw);
+    int32_t rc = CAPVNDF_OK;
+    if (nchunks > 0) {
+        if (!rc) rc = check_hip(hipMemcpy(p->d_chunk_job, chunk_job.data(), sizeof(int32_t) * nchunks, hipMemcpyHostToDevice), "hipMemcpy");
+        if (!rc) rc = check_hip(hipMemcpy(p->d_chunk_pbeg, pbeg.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice), "hipMemcpy");
+        if (!rc) rc = check_hip(hipMemcpy(p->d_chunk_pend, pend.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    if (!rc) rc = check_hip(hipMemcpy(p->d_block_chunks, block_chunks.data(), sizeof(int32_t) * (grid + 1), hipMemcpyHostToDevice), "hipMemcpy");
+    if (!rc) rc = check_hip(hipMemcpy(p->d_job_chunks, job_chunks.data(), sizeof(int32_t) * (njobs + 1), hipMemcpyHostToDevice), "hipMemcpy");
+    if (!rc) rc = check_hip(hipMemcpy(p->d_nsamp, nsamples_host, sizeof(int64_t) * njobs, hipMemcpyHostToDevice), "hipMemcpy");
+    if (rc) {
+        destroy_plan(p);
+        return rc;
+    }
+    p->device = device;
+    p->njobs = njobs;
+    p->nchunks = nchunks;
+    p->total_samples = total;
+    p->tiling = t;
+    p->grid = (int)grid;
+    p->with_grad = with_grad;
+    p->seed = seed;
+    p->wox = wox; p->woy = woy; p->woz = woz; p->ax = ax; p->ay = ay; p->f0 = f0;
+    p->albedo = albedo;
+    p->gax = with_grad ? grad_ax : nullptr;
+    p->gay = with_grad ? grad_ay : nullptr;
+    p->gth = with_grad ? grad_theta_o : nullptr;
+    p->nsamp_host.assign(nsamples_host, nsamples_host + njobs);
+
+    // Capture the launch sequence once on a private stream.
+    hipStream_t cap = nullptr;
+    rc = check_hip(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    if (!rc) rc = check_hip(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    if (!rc) {
+        const int32_t rl = enqueue_batch(p, cap);
+        hipGraph_t g = nullptr;
+        const int32_t re = check_hip(hipStreamEndCapture(cap, &g), "hipStreamEndCapture");
+        p->graph = g;
+        rc = rl ? rl : re;
+    }
+    if (!rc) rc = check_hip(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (cap) (void)hipStreamDestroy(cap);
+    if (rc) {
+        destroy_plan(p);
+        return rc;
+    }
+    *out = p;
+    return CAPVNDF_OK;
+}
+
+}  // namespace
+}  // namespace capvndf
+
+extern "C" int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, const float* woy,
+                                            const float* woz, const float* ax, const float* ay,
+                                            const float* f0, const int64_t* nsamples_host,
+                                            uint64_t seed, int32_t with_grad, float* albedo,
+                                            float* grad_ax, float* grad_ay, float* grad_theta_o,
+                                            const capvndf_tiling* tiling, void* stream,
+                                            capvndf_batch_plan** out) {
+    (void)stream;  // capture happens on a private stream; replays use the caller's
+    return create_plan(njobs, wox, woy, woz, ax, ay, f0, nsamples_host, seed, with_grad, albedo,
+                       grad_ax, grad_ay, grad_theta_o, tiling, out);
+}
+
+extern "C" int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream) {
+    if (plan == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_run: plan is NULL");
+    return check_hip(hipGraphLaunch(plan->exec, as_stream(stream)), "hipGraphLaunch");
+}
+
+extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* stream) {
+    if (p == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_run_per_request: plan is NULL");
+    const hipStream_t st = as_stream(stream);
+    const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
+    for (int64_t j = 0; j < p->njobs; ++j) {
+        const int64_t n = p->nsamp_host[j];
+        const int64_t cpc = lut_chunks_per_cell(n);
+        hipLaunchKernelGGL(k_albedo_fwd, dim3((unsigned)cpc), dim3(kLutBlock), 0, st, p->wox + j,
+                           p->woy + j, p->woz + j, p->ax + j, p->ay + j, (uint64_t)n, (int32_t)cpc,
+                           (uint32_t)j, k0, k1, p->d_req_ws);
+        hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1, p->d_req_ws,
+                           (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr, p->d_s1 + j,
+                           p->d_s5 + j, nullptr, nullptr);
+        if (p->with_grad) {
+            hipLaunchKernelGGL(k_albedo_bwd, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
+                               p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j,
+                               p->f0 ? p->f0 + j : nullptr, (uint64_t)n, (int32_t)cpc, (uint32_t)j,
+                               k0, k1, p->d_req_ws);
+            hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
+                               p->d_req_ws, (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr,
+                               p->gax + j, p->gay + j, p->gth + j, nullptr);
+        }
+    }
+    hipLaunchKernelGGL(k_combine_f0, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
+                       p->njobs, p->d_s1, p->d_s5, p->f0, p->albedo);
+    return check_launch("albedo_batch_run_per_request launch");
+}
+
+extern "C" int32_t albedo_batch_plan_info(const capvndf_batch_plan* plan, capvndf_tiling* tiling,
+                                          int64_t* nchunks, int64_t* total_samples) {
+    if (plan == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_plan_info: plan is NULL");
+    if (tiling) *tiling = plan->tiling;
+    if (nchunks) *nchunks = plan->nchunks;
+    if (total_samples) *total_samples = plan->total_samples;
+    return CAPVNDF_OK;
+}
+
+extern "C" void albedo_batch_plan_destroy(capvndf_batch_plan* plan) { destroy_plan(plan); }
+
+extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const float* woy,
+                                         const float* woz, const float* ax, const float* ay,
+                                         const float* f0, const int64_t* nsamples_host,
+                                         uint64_t seed, int32_t with_grad, float* albedo,
+                                         float* grad_ax, float* grad_ay, float* grad_theta_o,
+                                         void* stream, capvndf_tiling* best, float* best_ms) {
+    if (best == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_autotune: best is NULL");
+    const hipStream_t st = as_stream(stream);
+    const int blocks[] = {256, 512};
+    const int ppts[] = {8, 16, 32, 64};
+    const int bpcs[] = {2, 4, 8, 16};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int32_t rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
+    if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
+    float best_t = 3.4e38f;
+    capvndf_tiling best_tiling = default_tiling();
+    int64_t total = 0;
+    for (int64_t j = 0; j < njobs && nsamples_host; ++j) total += nsamples_host[j];
+    for (int b : blocks) {
+        for (int ppt : ppts) {
+            for (int bpc : bpcs) {
+                if (rc) break;
+                if (b == 512 && bpc > 8) continue;
+                capvndf_tiling t{b, ppt, bpc, 0};
+                capvndf_batch_plan* p = nullptr;
+                rc = create_plan(njobs, wox, woy, woz, ax, ay, f0, nsamples_host, seed, with_grad,
+                                 albedo, grad_ax, grad_ay, grad_theta_o, &t, &p);
+                if (rc) break;
+                rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");  // warm-up
+                const int reps = 3;
+                if (!rc) rc = check_hip(hipEventRecord(e0, st), "hipEventRecord");
+                for (int r = 0; r < reps && !rc; ++r)
+                    rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");
+                if (!rc) rc = check_hip(hipEventRecord(e1, st), "hipEventRecord");
+                if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0.0f;
+                if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                destroy_plan(p);
+                if (!rc && ms / reps < best_t) {
+                    best_t = ms / reps;
+                    best_tiling = t;
+                }
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *best = best_tiling;
+    if (best_ms) *best_ms = best_t;
+    int device = 0;
+    if (hipGetDevice(&device) == hipSuccess)
+        cache_store(problem_signature(device, njobs, total, with_grad), best_tiling, best_t);
+    return CAPVNDF_OK;
+}

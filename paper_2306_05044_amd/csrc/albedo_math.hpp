@@ -1,0 +1,191 @@
+// Per-sample arithmetic of the directional-albedo estimator and its pathwise
+// adjoint (device side).
+//
+// Estimator (Appendix A, "Importance Sampling Using the GGX VNDF", L == 1):
+// draw h from the VNDF seen from wo (cap sampler), reflect wo about h
+// (wl = 2 (wo.h) h - wo) and weigh by f_r |cos theta_l| / PDF.  With
+// PDF = G1(wo) D(h) / (4 cos theta_o) and f_r = F G2 D / (4 cos theta_o
+// cos theta_l), D and the cosines cancel: weight = F(wo.h) G2 / G1(wo), and
+// for the height-correlated G2 = Go Gl / (Go + Gl - Go Gl) this is
+// F Gl / (Go + Gl (1 - Go)).  In the hemisphere space G1(w) = 2 zs / (1 + zs)
+// with zs the z of M^-1 w / |M^-1 w|.
+#pragma once
+
+#include "device_math.hpp"
+
+namespace capvndf {
+
+// Per-cell (or per-job) constants, uniform across the lanes working on it.
+struct CellConst {
+    float ox, oy, oz;  // unit view direction
+    float ax, ay;
+    Stretched s;       // stretched view direction
+    float go;          // G1(wo)
+    float tx, ty, tz;  // meridian tangent dwo/dtheta_o
+    bool ok;           // inside the domain
+};
+
+__device__ __forceinline__ CellConst cell_setup(float wx, float wy, float wz, float ax, float ay) {
+    CellConst c;
+    c.ok = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f);
+    if (!c.ok) {
+        wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f;
+    }
+    const float in = rsq(__builtin_fmaf(wx, wx, __builtin_fmaf(wy, wy, wz * wz)));
+    c.ox = wx * in;
+    c.oy = wy * in;
+    c.oz = wz * in;
+    c.ax = ax;
+    c.ay = ay;
+    c.s = stretch(c.ox, c.oy, c.oz, ax, ay);
+    c.go = 2.0f * c.s.zs * rcp(c.s.opz);
+    const float rho2 = __builtin_fmaf(c.ox, c.ox, c.oy * c.oy);
+    if (rho2 > 0.0f) {
+        const float ir = rsq(rho2);
+        c.tx = c.oz * c.ox * ir;
+        c.ty = c.oz * c.oy * ir;
+        c.tz = -rho2 * ir;
+    } else {
+        c.tx = c.oz; c.ty = 0.0f; c.tz = 0.0f;
+    }
+    return c;
+}
+
+// Forward term: g = G2/G1 (0 below the horizon) and m5 = (1 - wo.h)^5.
+struct FwdTerm {
+    float g, m5;
+};
+
+__device__ __forceinline__ FwdTerm albedo_fwd(const CellConst& c, float u1, float u2) {
+    const CapSample cs = cap_sample(c.s, u1, u2);
+    const Normal n = unstretch(cs.hsx, cs.hsy, cs.hsz, c.ax, c.ay);
+    const float x = __builtin_fmaf(c.ox, n.hx, __builtin_fmaf(c.oy, n.hy, c.oz * n.hz));
+    const float x2 = x + x;
+    const float wlx = __builtin_fmaf(x2, n.hx, -c.ox);
+    const float wly = __builtin_fmaf(x2, n.hy, -c.oy);
+    const float wlz = __builtin_fmaf(x2, n.hz, -c.oz);
+    const float plx = c.ax * wlx, ply = c.ay * wly;
+    const float m2 = __builtin_fmaf(plx, plx, __builtin_fmaf(ply, ply, wlz * wlz));
+    const float zl = wlz * rsq(m2);
+    const float gl = 2.0f * zl * rcp(1.0f + zl);
+    const float den = __builtin_fmaf(gl, 1.0f - c.go, c.go);
+    const float g = gl * rcp(den);
+    const float m = 1.0f - x;
+    const float mm = m * m;
+    FwdTerm r;
+    r.g = wlz > 0.0f ? g : 0.0f;
+    r.m5 = mm * mm * m;
+    return r;
+}
+
+// Adjoint term for A = mean of w = F g: the weight w and its derivatives at
+// fixed (u1, u2).  dax/day/dth hold the direct dependences on alpha and on
+// wo (already projected on the meridian tangent); dwsx/dwsy/dzs are the
+// adjoints of the stretched view direction ws = (wsx, wsy, zs), whose own
+// dependence on (alpha, wo) is the same for every sample of a cell and is
+// applied once per thread by ws_chain().
+struct AdjTerm {
+    float w, dax, day, dth, dwsx, dwsy, dzs;
+};
+
+__device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, float u1, float u2) {
+    const Stretched& s = c.s;
+    // forward sweep (as albedo_fwd, keeping the intermediates)
+    const float a = 1.0f - u2;
+    const float hsz = a * s.opz;
+    const float s2 = u2 * s.opz * (hsz + s.omz);
+    const float st = fsqrt(s2);
+    float sp, cp;
+    sincos_turns(u1, &sp, &cp);
+    const float hsx = __builtin_fmaf(st, cp, s.wsx);
+    const float hsy = __builtin_fmaf(st, sp, s.wsy);
+    const float vx = c.ax * hsx, vy = c.ay * hsy, vz = hsz;
+    const float iL = rsq(__builtin_fmaf(vx, vx, __builtin_fmaf(vy, vy, vz * vz)));
+    const float hx = vx * iL, hy = vy * iL, hz = vz * iL;
+    const float x = __builtin_fmaf(c.ox, hx, __builtin_fmaf(c.oy, hy, c.oz * hz));
+    const float x2 = x + x;
+    const float wlx = __builtin_fmaf(x2, hx, -c.ox);
+    const float wly = __builtin_fmaf(x2, hy, -c.oy);
+    const float wlz = __builtin_fmaf(x2, hz, -c.oz);
+    const float plx = c.ax * wlx, ply = c.ay * wly;
+    const float pp = __builtin_fmaf(plx, plx, ply * ply);
+    const float im = rsq(__builtin_fmaf(wlz, wlz, pp));
+    const float zl = wlz * im;
+    const float i1z = rcp(1.0f + zl);
+    const float gl = 2.0f * zl * i1z;
+    const float omg = 1.0f - c.go;
+    const float ig = rcp(__builtin_fmaf(gl, omg, c.go));
+    const float g = gl * ig;
+    const float m = 1.0f - x;
+    const float mm = m * m;
+    const float m4 = mm * mm;
+    const float f1 = 1.0f - f0;
+    const float F = __builtin_fmaf(f1, m4 * m, f0);
+
+    // reverse sweep, seeded with dw = 1
+    float dx = -5.0f * f1 * m4 * g;                            // through F(x)
+    const float dgl = F * ig * __builtin_fmaf(-g, omg, 1.0f);  // dg/dGl = Go / den^2
+    const float dgo = -F * g * ig * (1.0f - gl);               // dg/dGo
+    const float e = dgl * 2.0f * i1z * i1z * im * im * im;     // dzl * |pl|^-3
+    const float dwlz = e * pp;
+    const float ew = -e * wlz;
+    const float dplx = ew * plx, dply = ew * ply;
+    float dax = dplx * wlx;
+    float day = dply * wly;
+    const float dwlx = dplx * c.ax, dwly = dply * c.ay;
+    // wl = 2 x h - wo
+    dx += 2.0f * __builtin_fmaf(dwlx, hx, __builtin_fmaf(dwly, hy, dwlz * hz));
+    float dhx = x2 * dwlx, dhy = x2 * dwly, dhz = x2 * dwlz;
+    // x = wo . h
+    dhx = __builtin_fmaf(dx, c.ox, dhx);
+    dhy = __builtin_fmaf(dx, c.oy, dhy);
+    dhz = __builtin_fmaf(dx, c.oz, dhz);
+    const float dox = __builtin_fmaf(dx, hx, -dwlx);
+    const float doy = __builtin_fmaf(dx, hy, -dwly);
+    const float doz = __builtin_fmaf(dx, hz, -dwlz);
+    // h = v / |v|
+    const float hd = __builtin_fmaf(hx, dhx, __builtin_fmaf(hy, dhy, hz * dhz));
+    const float dvx = iL * __builtin_fmaf(-hx, hd, dhx);
+    const float dvy = iL * __builtin_fmaf(-hy, hd, dhy);
+    const float dvz = iL * __builtin_fmaf(-hz, hd, dhz);
+    // v = (ax hsx, ay hsy, hsz)
+    dax = __builtin_fmaf(dvx, hsx, dax);
+    day = __builtin_fmaf(dvy, hsy, day);
+    const float dhsx = dvx * c.ax, dhsy = dvy * c.ay;
+    // hs = (st cos phi + wsx, st sin phi + wsy, (1 - u2)(1 + zs)),
+    // st^2 = u2 (1 + zs) ((1 - u2)(1 + zs) + 1 - zs)
+    const float dst = __builtin_fmaf(dhsx, cp, dhsy * sp);
+    const float ds2u = st > 0.0f ? 0.5f * dst * rcp(st) * u2 : 0.0f;
+    const float dopz = __builtin_fmaf(dvz, a, ds2u * (2.0f * hsz + s.omz));
+    const float domz = ds2u * s.opz;
+    const float iopz = rcp(s.opz);
+    // Go = 2 zs / (1 + zs), 1 + zs, 1 - zs
+    const float dzs = __builtin_fmaf(dgo * 2.0f * iopz, iopz, dopz - domz);
+
+    const bool live = wlz > 0.0f;
+    AdjTerm r;
+    r.w = live ? F * g : 0.0f;
+    r.dax = live ? dax : 0.0f;
+    r.day = live ? day : 0.0f;
+    r.dth = live ? __builtin_fmaf(c.tx, dox, __builtin_fmaf(c.ty, doy, c.tz * doz)) : 0.0f;
+    r.dwsx = live ? dhsx : 0.0f;
+    r.dwsy = live ? dhsy : 0.0f;
+    r.dzs = live ? dzs : 0.0f;
+    return r;
+}
+
+// Chain the adjoint of ws = p / |p|, p = (ax ox, ay oy, oz), into
+// (alpha_x, alpha_y, theta_o): dp = (dws - ws (ws . dws)) / |p|.
+__device__ __forceinline__ void ws_chain(const CellConst& c, float dwsx, float dwsy, float dzs,
+                                         float& gax, float& gay, float& gth) {
+    const Stretched& s = c.s;
+    const float wd = __builtin_fmaf(s.wsx, dwsx, __builtin_fmaf(s.wsy, dwsy, s.zs * dzs));
+    const float dpx = s.il * __builtin_fmaf(-s.wsx, wd, dwsx);
+    const float dpy = s.il * __builtin_fmaf(-s.wsy, wd, dwsy);
+    const float dpz = s.il * __builtin_fmaf(-s.zs, wd, dzs);
+    gax = __builtin_fmaf(dpx, c.ox, gax);
+    gay = __builtin_fmaf(dpy, c.oy, gay);
+    gth = __builtin_fmaf(c.tx * c.ax, dpx, __builtin_fmaf(c.ty * c.ay, dpy, __builtin_fmaf(c.tz, dpz, gth)));
+}
+
+}  // namespace capvndf

@@ -1,0 +1,274 @@
+// Device-side building blocks of the spherical-cap GGX VNDF path (gfx950).
+//
+// Everything here is per-lane register arithmetic in FP32 (plus 32-bit
+// integer work for the random numbers); the kernels in the .hip files wrap it
+// with coalesced structure-of-arrays I/O and wavefront/LDS reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace capvndf {
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// SC'11, Sec. 4).  Ten rounds; each multiplies words 0 and 2 by the round
+// constants into full 64-bit products and mixes the high halves with the
+// other two words and the key; the key advances by the Weyl constants.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kM0 = 0xD2511F53u;
+constexpr uint32_t kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u;
+constexpr uint32_t kW1 = 0xBB67AE85u;
+
+// Stream tags of the counter layout: counter = (lo32(k >> 1), unit, tag,
+// hi32(k >> 1)), key = (lo32(seed), hi32(seed)); sample k uses words 0,1 when
+// k is even and words 2,3 when k is odd.
+constexpr uint32_t kTagSample = 2;  // vndf_sample: unit 0, k = index_base + i
+constexpr uint32_t kTagAlbedo = 3;  // estimator: unit = cell or job, k = sample
+
+struct Words {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kM0 * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)kM1 * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kW0;
+        k1 += kW1;
+    }
+    return Words{c0, c1, c2, c3};
+}
+
+// The block holding samples 2p and 2p+1 of stream (key, tag, unit).
+__device__ __forceinline__ Words philox_pair(uint64_t p, uint32_t unit, uint32_t tag,
+                                             uint32_t key0, uint32_t key1) {
+    return philox4x32_10((uint32_t)p, unit, tag, (uint32_t)(p >> 32), key0, key1);
+}
+
+// Top 24 bits of a word as a float in [0, 1): exact, and 1 - u is exact too.
+__device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
+
+// ---------------------------------------------------------------------------
+// sin(2 pi u) and cos(2 pi u) for the azimuth.  Exact quadrant reduction in
+// turns (4u and the remainder are exact for u on the 2^-24 lattice or any
+// float in [0, 1)), then Taylor polynomials of sin and cos of 2 pi r on
+// |r| <= 1/8 (truncation below 2e-9, i.e. under half an ulp), Horner in FMA.
+// ---------------------------------------------------------------------------
+namespace detail {
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double p2 = kTwoPi * kTwoPi;
+constexpr float kS1 = (float)kTwoPi;
+constexpr float kS3 = (float)(-kTwoPi * p2 / 6.0);
+constexpr float kS5 = (float)(kTwoPi * p2 * p2 / 120.0);
+constexpr float kS7 = (float)(-kTwoPi * p2 * p2 * p2 / 5040.0);
+constexpr float kS9 = (float)(kTwoPi * p2 * p2 * p2 * p2 / 362880.0);
+constexpr float kC2 = (float)(-p2 / 2.0);
+constexpr float kC4 = (float)(p2 * p2 / 24.0);
+constexpr float kC6 = (float)(-p2 * p2 * p2 / 720.0);
+constexpr float kC8 = (float)(p2 * p2 * p2 * p2 / 40320.0);
+constexpr float kC10 = (float)(-p2 * p2 * p2 * p2 * p2 / 3628800.0);
+}  // namespace detail
+
+__device__ __forceinline__ void sincos_turns(float u, float* s, float* c) {
+    using namespace detail;
+    const float q = __builtin_rintf(4.0f * u);
+    const float r = __builtin_fmaf(q, -0.25f, u);
+    const float r2 = r * r;
+    float ps = __builtin_fmaf(kS9, r2, kS7);
+    ps = __builtin_fmaf(ps, r2, kS5);
+    ps = __builtin_fmaf(ps, r2, kS3);
+    ps = __builtin_fmaf(ps, r2, kS1);
+    const float sr = ps * r;
+    float pc = __builtin_fmaf(kC10, r2, kC8);
+    pc = __builtin_fmaf(pc, r2, kC6);
+    pc = __builtin_fmaf(pc, r2, kC4);
+    pc = __builtin_fmaf(pc, r2, kC2);
+    const float cr = __builtin_fmaf(pc, r2, 1.0f);
+    const int qi = (int)q;
+    const float ss = (qi & 1) ? cr : sr;
+    const float cc = (qi & 1) ? sr : cr;
+    *s = (qi & 2) ? -ss : ss;
+    *c = ((qi + 1) & 2) ? -cc : cc;
+}
+
+// Hardware reciprocal, reciprocal square root and square root (about 1 ulp).
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+constexpr float kInvPi = 0.318309886183790671538f;
+
+// ---------------------------------------------------------------------------
+// Step 1 of the general sampler: warp wi by M^-1 = diag(ax, ay, 1) and
+// normalise.  Besides ws = (wsx, wsy, zs) this keeps 1 + zs and 1 - zs in
+// cancellation-free forms: with q = (ax wx)^2 + (ay wy)^2 and l = |M^-1 wi|,
+// 1 + zs = (l + wz) / l and 1 - zs = q / (l (l + wz)).
+// ---------------------------------------------------------------------------
+struct Stretched {
+    float wsx, wsy, zs;
+    float opz;  // 1 + zs
+    float omz;  // 1 - zs
+    float il;   // 1 / l
+};
+
+__device__ __forceinline__ Stretched stretch(float wx, float wy, float wz, float ax, float ay) {
+    const float px = ax * wx;
+    const float py = ay * wy;
+    const float q = __builtin_fmaf(px, px, py * py);
+    const float l2 = __builtin_fmaf(wz, wz, q);
+    const float il = rsq(l2);
+    const float l = l2 * il;
+    const float lpz = l + wz;
+    Stretched s;
+    s.wsx = px * il;
+    s.wsy = py * il;
+    s.zs = wz * il;
+    s.opz = lpz * il;
+    s.omz = q * il * rcp(lpz);
+    s.il = il;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Step 2 with the spherical cap (Sec. 3.3): c uniform on the cap z in
+// (-zs, 1] (u2 = 0 at the apex, azimuth 2 pi u1), half vector hs = c + ws,
+// left unnormalised.  The cap height z = (1 - u2)(1 + zs) - zs enters only
+// through z + zs = (1 - u2)(1 + zs) and 1 - z^2 = u2 (1 + zs) (z + zs + 1 - zs),
+// which avoids the cancellations of forming z and 1 - z^2 directly.
+// ---------------------------------------------------------------------------
+struct CapSample {
+    float hsx, hsy, hsz;  // unnormalised half vector in the hemisphere space
+    float st, cp, sp;     // sin(theta_c), cos(phi), sin(phi)
+};
+
+__device__ __forceinline__ CapSample cap_sample(const Stretched& s, float u1, float u2) {
+    CapSample r;
+    const float a = 1.0f - u2;
+    r.hsz = a * s.opz;
+    const float s2 = u2 * s.opz * (r.hsz + s.omz);
+    r.st = fsqrt(s2);
+    sincos_turns(u1, &r.sp, &r.cp);
+    r.hsx = __builtin_fmaf(r.st, r.cp, s.wsx);
+    r.hsy = __builtin_fmaf(r.st, r.sp, s.wsy);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Step 3: warp the normal back with M^-T = diag(ax, ay, 1) and normalise.
+// The VNDF pdf at that normal follows from Eq. (1) in the hemisphere space:
+// M^T h = hs / L with L = |M^-T hs|, ws . hs_n = |hs| / 2 (since |c| = |ws| =
+// 1), so pdf = L^3 / (pi ax ay (1 + zs) |hs|^2).  It equals
+// G1(wi) max(0, wi.h) D(h) / wz.
+// ---------------------------------------------------------------------------
+struct Normal {
+    float hx, hy, hz;
+    float vx, vy, vz;  // M^-T hs
+    float iL;          // 1 / |M^-T hs|
+};
+
+__device__ __forceinline__ Normal unstretch(float hsx, float hsy, float hsz, float ax, float ay) {
+    Normal n;
+    n.vx = ax * hsx;
+    n.vy = ay * hsy;
+    n.vz = hsz;
+    const float L2 = __builtin_fmaf(n.vx, n.vx, __builtin_fmaf(n.vy, n.vy, n.vz * n.vz));
+    n.iL = rsq(L2);
+    n.hx = n.vx * n.iL;
+    n.hy = n.vy * n.iL;
+    n.hz = n.vz * n.iL;
+    return n;
+}
+
+__device__ __forceinline__ float cap_pdf(const Stretched& s, const CapSample& c, const Normal& n,
+                                         float ax, float ay) {
+    const float L2 = __builtin_fmaf(n.vx, n.vx, __builtin_fmaf(n.vy, n.vy, n.vz * n.vz));
+    const float hs2 = __builtin_fmaf(c.hsx, c.hsx, __builtin_fmaf(c.hsy, c.hsy, c.hsz * c.hsz));
+    const float L3 = L2 * L2 * n.iL;
+    return L3 * kInvPi * rcp(ax * ay * s.opz * hs2);
+}
+
+// Heitz's 2018 cross-section sampler (Sec. 2), the comparison baseline, in the
+// hemisphere space: orthonormal basis around ws, polar disk sample, warp of
+// the second coordinate by s = (1 + zs) / 2, reprojection.  Returns the unit
+// hemisphere normal and its height ti above the disk (ws . wm = ti).
+struct DiskSample {
+    float mx, my, mz, ti;
+};
+
+__device__ __forceinline__ DiskSample disk2018_sample(const Stretched& s, float u1, float u2) {
+    const float tmp = __builtin_fmaf(s.wsx, s.wsx, s.wsy * s.wsy);
+    float w1x = 1.0f, w1y = 0.0f;
+    if (tmp > 0.0f) {
+        const float it = rsq(tmp);
+        w1x = -s.wsy * it;
+        w1y = s.wsx * it;
+    }
+    // w2 = ws x w1 with w1 = (w1x, w1y, 0)
+    const float w2x = -s.zs * w1y;
+    const float w2y = s.zs * w1x;
+    const float w2z = __builtin_fmaf(s.wsx, w1y, -s.wsy * w1x);
+    float sp, cp;
+    sincos_turns(u1, &sp, &cp);
+    const float r = fsqrt(u2);
+    const float t1 = r * cp;
+    float t2 = r * sp;
+    const float hs = 0.5f * s.opz;
+    const float omt = 1.0f - t1 * t1;
+    t2 = __builtin_fmaf(0.5f * s.omz, fsqrt(omt), hs * t2);
+    const float ti = fsqrt(fmaxf(omt - t2 * t2, 0.0f));
+    DiskSample d;
+    d.mx = __builtin_fmaf(t1, w1x, __builtin_fmaf(t2, w2x, ti * s.wsx));
+    d.my = __builtin_fmaf(t1, w1y, __builtin_fmaf(t2, w2y, ti * s.wsy));
+    d.mz = __builtin_fmaf(t2, w2z, ti * s.zs);
+    d.ti = ti;
+    return d;
+}
+
+// pdf of a unit hemisphere normal m seen from ws, at h = M^-T m / |M^-T m|:
+// (ws . m) / (pi (1 + zs) / 2) * L^3 / (ax ay), L = |M^-T m|.
+__device__ __forceinline__ float disk_pdf(const Stretched& s, const DiskSample& d,
+                                          const Normal& n, float ax, float ay) {
+    const float L2 = __builtin_fmaf(n.vx, n.vx, __builtin_fmaf(n.vy, n.vy, n.vz * n.vz));
+    const float L3 = L2 * L2 * n.iL;
+    const float dot = __builtin_fmaf(s.wsx, d.mx, __builtin_fmaf(s.wsy, d.my, s.zs * d.mz));
+    return fmaxf(dot, 0.0f) * 2.0f * kInvPi * L3 * rcp(ax * ay * s.opz);
+}
+
+// ---------------------------------------------------------------------------
+// Compensated accumulation.  Knuth's TwoSum folds an addend into (s, c) with
+// the rounding error of every addition kept in c; merge() combines two such
+// pairs (used across lanes, waves and blocks in a fixed order).
+// ---------------------------------------------------------------------------
+struct Comp {
+    float s, c;
+};
+
+__device__ __forceinline__ void comp_add(Comp& a, float x) {
+    const float t = a.s + x;
+    const float bp = t - a.s;
+    const float ap = t - bp;
+    a.c += (a.s - ap) + (x - bp);
+    a.s = t;
+}
+
+__device__ __forceinline__ Comp comp_merge(const Comp& a, const Comp& b) {
+    Comp r;
+    const float t = a.s + b.s;
+    const float bp = t - a.s;
+    const float ap = t - bp;
+    r.c = (a.c + b.c) + ((a.s - ap) + (b.s - bp));
+    r.s = t;
+    return r;
+}
+
+}  // namespace capvndf

@@ -1,0 +1,428 @@
+// Streaming VNDF sampling and pdf kernels, random-number hooks, the
+// register-resident microbenchmark and the streaming-bandwidth probe.
+//
+// Layout: structure of arrays in HBM.  The vector path gives each lane four
+// consecutive tuples, so every array is read and written with one 16-byte
+// access per lane (fully coalesced dwordx4, non-temporal: nothing is reused),
+// and the lane's four tuples take exactly two Philox blocks.
+#include "common.hpp"
+#include "device_math.hpp"
+
+namespace capvndf {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ f4 load4(const float* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+}
+__device__ __forceinline__ void store4(float* p, f4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+}
+
+// One tuple: general sampler with the chosen hemisphere routine.  Inputs
+// outside the domain are replaced by harmless ones and the outputs selected
+// afterwards, so the vector path stays branch-free.
+template <int METHOD, bool WITH_PDF>
+__device__ __forceinline__ void sample_one(float wx, float wy, float wz, float ax, float ay,
+                                           float u1, float u2, float& hx, float& hy, float& hz,
+                                           float& pdf) {
+    const bool ok = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f);
+    if (!ok) {
+        wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f;
+    }
+    const Stretched s = stretch(wx, wy, wz, ax, ay);
+    float p = 0.0f;
+    Normal n;
+    if (METHOD == CAPVNDF_CAP) {
+        const CapSample c = cap_sample(s, u1, u2);
+        n = unstretch(c.hsx, c.hsy, c.hsz, ax, ay);
+        if (WITH_PDF) p = cap_pdf(s, c, n, ax, ay);
+    } else {
+        const DiskSample d = disk2018_sample(s, u1, u2);
+        n = unstretch(d.mx, d.my, d.mz, ax, ay);
+        if (WITH_PDF) p = disk_pdf(s, d, n, ax, ay);
+    }
+    hx = ok ? n.hx : 0.0f;
+    hy = ok ? n.hy : 0.0f;
+    hz = ok ? n.hz : 1.0f;
+    pdf = ok ? p : 0.0f;
+}
+
+__device__ __forceinline__ void stream_u(uint64_t k, uint32_t key0, uint32_t key1, float& u1,
+                                         float& u2) {
+    const Words w = philox_pair(k >> 1, 0u, kTagSample, key0, key1);
+    const bool odd = (k & 1u) != 0;
+    u1 = unit24(odd ? w.w2 : w.w0);
+    u2 = unit24(odd ? w.w3 : w.w1);
+}
+
+// Vector path: lane t owns tuples 4t .. 4t+3 (index_base even, arrays 16-byte
+// aligned).  A lane whose four tuples straddle n finishes them one by one.
+template <int METHOD, bool EXPLICIT_U, bool WITH_PDF>
+__global__ __launch_bounds__(kBlock) void k_sample_v4(
+    int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
+    const float* __restrict__ wiz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ u1p, const float* __restrict__ u2p, uint64_t index_base,
+    uint32_t key0, uint32_t key1, float* __restrict__ hx, float* __restrict__ hy,
+    float* __restrict__ hz, float* __restrict__ pdf) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = t * 4;
+    if (i0 >= n) return;
+    if (i0 + 4 <= n) {
+        const f4 x = load4(wix + i0), y = load4(wiy + i0), z = load4(wiz + i0);
+        const f4 a = load4(ax + i0), b = load4(ay + i0);
+        f4 r1, r2;
+        if (EXPLICIT_U) {
+            r1 = load4(u1p + i0);
+            r2 = load4(u2p + i0);
+        } else {
+            const uint64_t pair = (index_base >> 1) + (uint64_t)(2 * t);
+            const Words w0 = philox_pair(pair, 0u, kTagSample, key0, key1);
+            const Words w1 = philox_pair(pair + 1, 0u, kTagSample, key0, key1);
+            r1 = f4{unit24(w0.w0), unit24(w0.w2), unit24(w1.w0), unit24(w1.w2)};
+            r2 = f4{unit24(w0.w1), unit24(w0.w3), unit24(w1.w1), unit24(w1.w3)};
+        }
+        f4 ox, oy, oz, op;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float hxj, hyj, hzj, pj;
+            sample_one<METHOD, WITH_PDF>(x[j], y[j], z[j], a[j], b[j], r1[j], r2[j], hxj, hyj,
+                                         hzj, pj);
+            ox[j] = hxj; oy[j] = hyj; oz[j] = hzj; op[j] = pj;
+        }
+        store4(hx + i0, ox);
+        store4(hy + i0, oy);
+        store4(hz + i0, oz);
+        if (WITH_PDF) store4(pdf + i0, op);
+    } else {
+        for (int64_t i = i0; i < n; ++i) {
+            float r1, r2;
+            if (EXPLICIT_U) {
+                r1 = u1p[i]; r2 = u2p[i];
+            } else {
+                stream_u(index_base + (uint64_t)i, key0, key1, r1, r2);
+            }
+            float hxi, hyi, hzi, pi;
+            sample_one<METHOD, WITH_PDF>(wix[i], wiy[i], wiz[i], ax[i], ay[i], r1, r2, hxi, hyi,
+                                         hzi, pi);
+            hx[i] = hxi; hy[i] = hyi; hz[i] = hzi;
+            if (WITH_PDF) pdf[i] = pi;
+        }
+    }
+}
+
+// Scalar path (any 4-byte alignment, any index_base): one tuple per lane.
+template <int METHOD, bool EXPLICIT_U, bool WITH_PDF>
+__global__ __launch_bounds__(kBlock) void k_sample_scalar(
+    int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
+    const float* __restrict__ wiz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ u1p, const float* __restrict__ u2p, uint64_t index_base,
+    uint32_t key0, uint32_t key1, float* __restrict__ hx, float* __restrict__ hy,
+    float* __restrict__ hz, float* __restrict__ pdf) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    float r1, r2;
+    if (EXPLICIT_U) {
+        r1 = u1p[i]; r2 = u2p[i];
+    } else {
+        stream_u(index_base + (uint64_t)i, key0, key1, r1, r2);
+    }
+    float hxi, hyi, hzi, pi;
+    sample_one<METHOD, WITH_PDF>(wix[i], wiy[i], wiz[i], ax[i], ay[i], r1, r2, hxi, hyi, hzi,
+                                 pi);
+    hx[i] = hxi; hy[i] = hyi; hz[i] = hzi;
+    if (WITH_PDF) pdf[i] = pi;
+}
+
+// pdf of Eq. (1) at a given unit h: G1(wi) = 2 w_z / (l + w_z) with
+// l = |M^-1 wi|, D(h) = 1 / (pi ax ay k^2) with k = |M^T h|^2, so
+// pdf = 2 (wi.h) / ((l + w_z) pi ax ay k^2).
+__device__ __forceinline__ float pdf_one(float wx, float wy, float wz, float hx, float hy,
+                                         float hz, float ax, float ay) {
+    const bool ok0 = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f) && (hz > 0.0f);
+    if (!ok0) {
+        wz = 1.0f; ax = 1.0f; ay = 1.0f; hz = 1.0f;
+    }
+    const float d = __builtin_fmaf(wx, hx, __builtin_fmaf(wy, hy, wz * hz));
+    const float px = ax * wx, py = ay * wy;
+    const float l = fsqrt(__builtin_fmaf(px, px, __builtin_fmaf(py, py, wz * wz)));
+    const float iax = rcp(ax), iay = rcp(ay);
+    const float sx = hx * iax, sy = hy * iay;
+    const float k = __builtin_fmaf(sx, sx, __builtin_fmaf(sy, sy, hz * hz));
+    const float p = 2.0f * kInvPi * d * rcp((l + wz) * ax * ay * k * k);
+    return (ok0 && d > 0.0f) ? p : 0.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pdf_v4(
+    int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
+    const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
+    const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
+    float* __restrict__ pdf) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = t * 4;
+    if (i0 >= n) return;
+    if (i0 + 4 <= n) {
+        const f4 x = load4(wix + i0), y = load4(wiy + i0), z = load4(wiz + i0);
+        const f4 hx = load4(hxp + i0), hy = load4(hyp + i0), hz = load4(hzp + i0);
+        const f4 a = load4(ax + i0), b = load4(ay + i0);
+        f4 o;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[j] = pdf_one(x[j], y[j], z[j], hx[j], hy[j], hz[j], a[j], b[j]);
+        store4(pdf + i0, o);
+    } else {
+        for (int64_t i = i0; i < n; ++i)
+            pdf[i] = pdf_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pdf_scalar(
+    int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
+    const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
+    const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
+    float* __restrict__ pdf) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    pdf[i] = pdf_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_uniforms(int64_t n, uint64_t k0, uint32_t tag,
+                                                     uint32_t unit, uint32_t key0,
+                                                     uint32_t key1, float* __restrict__ u1,
+                                                     float* __restrict__ u2) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = k0 + (uint64_t)i;
+    const Words w = philox_pair(k >> 1, unit, tag, key0, key1);
+    const bool odd = (k & 1u) != 0;
+    u1[i] = unit24(odd ? w.w2 : w.w0);
+    u2[i] = unit24(odd ? w.w3 : w.w1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_philox_blocks(int64_t n,
+                                                          const uint32_t* __restrict__ ctr,
+                                                          uint32_t key0, uint32_t key1,
+                                                          uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const Words w = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3],
+                                  key0, key1);
+    out[4 * i] = w.w0;
+    out[4 * i + 1] = w.w1;
+    out[4 * i + 2] = w.w2;
+    out[4 * i + 3] = w.w3;
+}
+
+// Register-resident sampler benchmark: per lane one view azimuth and
+// roughness pair, then `iters` calls with Weyl-sequence uniforms and a view
+// elevation that moves each call (so the stretch cannot be hoisted).
+template <int METHOD>
+__global__ __launch_bounds__(kBlock) void k_microbench(int64_t lanes, int32_t iters,
+                                                       uint32_t key0, uint32_t key1,
+                                                       uint32_t* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= lanes) return;
+    const Words w = philox_pair((uint64_t)t, 0u, 5u, key0, key1);
+    float sphi, cphi;
+    sincos_turns(unit24(w.w0), &sphi, &cphi);
+    // alpha = 10^(-3 U): log-uniform in [1e-3, 1]
+    const float ax = __builtin_amdgcn_exp2f(-9.965784284662087f * unit24(w.w1));
+    const float ay = __builtin_amdgcn_exp2f(-9.965784284662087f * unit24(w.w2));
+    float u1 = unit24(w.w3);
+    float u2 = unit24(w.w3 ^ w.w0);
+    float mu = unit24(w.w2 ^ w.w1);
+    float acc = 0.0f;
+    for (int32_t j = 0; j < iters; ++j) {
+        u1 += 0.6180339887f;
+        u1 -= __builtin_floorf(u1);
+        u2 += 0.7548776662f;
+        u2 -= __builtin_floorf(u2);
+        mu += 0.5698402910f;
+        mu -= __builtin_floorf(mu);
+        const float cz = __builtin_fmaf(mu, 0.999f, 1e-3f);
+        const float sz = fsqrt(__builtin_fmaf(-cz, cz, 1.0f));
+        float hx, hy, hz, p;
+        sample_one<METHOD, false>(sz * cphi, sz * sphi, cz, ax, ay, u1, u2, hx, hy, hz, p);
+        acc += hx + hy + hz;
+    }
+    out[t] = __float_as_uint(acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_stream_probe(
+    int64_t n, const float* __restrict__ in0, const float* __restrict__ in1,
+    const float* __restrict__ in2, const float* __restrict__ in3,
+    const float* __restrict__ in4, float* __restrict__ out0, float* __restrict__ out1,
+    float* __restrict__ out2, float* __restrict__ out3) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t i0 = t * 4;
+    if (i0 >= n) return;
+    if (i0 + 4 <= n) {
+        const f4 a = load4(in0 + i0), b = load4(in1 + i0), c = load4(in2 + i0);
+        const f4 d = load4(in3 + i0), e = load4(in4 + i0);
+        store4(out0 + i0, a + e);
+        store4(out1 + i0, b);
+        store4(out2 + i0, c);
+        store4(out3 + i0, d);
+    } else {
+        for (int64_t i = i0; i < n; ++i) {
+            out0[i] = in0[i] + in4[i];
+            out1[i] = in1[i];
+            out2[i] = in2[i];
+            out3[i] = in3[i];
+        }
+    }
+}
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+template <int METHOD, bool EU, bool WP>
+void launch_sample(bool vec, int64_t n, const float* wix, const float* wiy, const float* wiz,
+                   const float* ax, const float* ay, const float* u1, const float* u2,
+                   uint64_t index_base, uint32_t k0, uint32_t k1, float* hx, float* hy, float* hz,
+                   float* pdf, hipStream_t st) {
+    if (vec) {
+        hipLaunchKernelGGL((k_sample_v4<METHOD, EU, WP>), dim3(grid_for((n + 3) / 4)),
+                           dim3(kBlock), 0, st, n, wix, wiy, wiz, ax, ay, u1, u2, index_base, k0,
+                           k1, hx, hy, hz, pdf);
+    } else {
+        hipLaunchKernelGGL((k_sample_scalar<METHOD, EU, WP>), dim3(grid_for(n)), dim3(kBlock), 0,
+                           st, n, wix, wiy, wiz, ax, ay, u1, u2, index_base, k0, k1, hx, hy, hz,
+                           pdf);
+    }
+}
+
+template <int METHOD>
+void dispatch_sample(bool vec, bool eu, bool wp, int64_t n, const float* wix, const float* wiy,
+                     const float* wiz, const float* ax, const float* ay, const float* u1,
+                     const float* u2, uint64_t ib, uint32_t k0, uint32_t k1, float* hx,
+                     float* hy, float* hz, float* pdf, hipStream_t st) {
+    if (eu && wp)
+        launch_sample<METHOD, true, true>(vec, n, wix, wiy, wiz, ax, ay, u1, u2, ib, k0, k1, hx, hy, hz, pdf, st);
+    else if (eu)
+        launch_sample<METHOD, true, false>(vec, n, wix, wiy, wiz, ax, ay, u1, u2, ib, k0, k1, hx, hy, hz, pdf, st);
+    else if (wp)
+        launch_sample<METHOD, false, true>(vec, n, wix, wiy, wiz, ax, ay, u1, u2, ib, k0, k1, hx, hy, hz, pdf, st);
+    else
+        launch_sample<METHOD, false, false>(vec, n, wix, wiy, wiz, ax, ay, u1, u2, ib, k0, k1, hx, hy, hz, pdf, st);
+}
+
+}  // namespace
+}  // namespace capvndf
+
+using namespace capvndf;
+
+extern "C" int32_t vndf_sample(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                               const float* ax, const float* ay, const float* u1, const float* u2,
+                               uint64_t seed, uint64_t index_base, int32_t method, float* hx,
+                               float* hy, float* hz, float* pdf, void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_sample: n = %lld < 0", (long long)n);
+    if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018)
+        return fail(CAPVNDF_ERR_BAD_METHOD, "vndf_sample: unknown method %d", method);
+    if ((u1 == nullptr) != (u2 == nullptr))
+        return fail(CAPVNDF_ERR_NULL_PTR, "vndf_sample: give both u1 and u2 or neither");
+    if (n == 0) return CAPVNDF_OK;
+    const void* req[] = {wix, wiy, wiz, ax, ay, hx, hy, hz};
+    const char* names[] = {"wix", "wiy", "wiz", "ax", "ay", "hx", "hy", "hz"};
+    for (int i = 0; i < 8; ++i)
+        if (int32_t rc = check_array(req[i], names[i])) return rc;
+    if (u1 != nullptr) {
+        if (int32_t rc = check_array(u1, "u1")) return rc;
+        if (int32_t rc = check_array(u2, "u2")) return rc;
+    }
+    if (pdf != nullptr)
+        if (int32_t rc = check_array(pdf, "pdf")) return rc;
+    bool vec = (index_base % 2) == 0;
+    const void* all[] = {wix, wiy, wiz, ax, ay, hx, hy, hz, u1, u2, pdf};
+    for (const void* p : all)
+        if (p != nullptr && !aligned_to(p, 16)) vec = false;
+    const bool eu = u1 != nullptr, wp = pdf != nullptr;
+    const hipStream_t st = as_stream(stream);
+    if (method == CAPVNDF_CAP)
+        dispatch_sample<CAPVNDF_CAP>(vec, eu, wp, n, wix, wiy, wiz, ax, ay, u1, u2, index_base,
+                                     key_lo(seed), key_hi(seed), hx, hy, hz, pdf, st);
+    else
+        dispatch_sample<CAPVNDF_DISK2018>(vec, eu, wp, n, wix, wiy, wiz, ax, ay, u1, u2,
+                                          index_base, key_lo(seed), key_hi(seed), hx, hy, hz,
+                                          pdf, st);
+    return check_launch("vndf_sample launch");
+}
+
+extern "C" int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                            const float* hx, const float* hy, const float* hz, const float* ax,
+                            const float* ay, float* pdf, void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_pdf: n = %lld < 0", (long long)n);
+    if (n == 0) return CAPVNDF_OK;
+    const void* req[] = {wix, wiy, wiz, hx, hy, hz, ax, ay, pdf};
+    const char* names[] = {"wix", "wiy", "wiz", "hx", "hy", "hz", "ax", "ay", "pdf"};
+    bool vec = true;
+    for (int i = 0; i < 9; ++i) {
+        if (int32_t rc = check_array(req[i], names[i])) return rc;
+        if (!aligned_to(req[i], 16)) vec = false;
+    }
+    const hipStream_t st = as_stream(stream);
+    if (vec)
+        hipLaunchKernelGGL(k_pdf_v4, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0, st, n, wix,
+                           wiy, wiz, hx, hy, hz, ax, ay, pdf);
+    else
+        hipLaunchKernelGGL(k_pdf_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix, wiy,
+                           wiz, hx, hy, hz, ax, ay, pdf);
+    return check_launch("vndf_pdf launch");
+}
+
+extern "C" int32_t capvndf_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, uint64_t k0,
+                                    int64_t n, float* u1, float* u2, void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "capvndf_uniforms: n < 0");
+    if (n == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(u1, "u1")) return rc;
+    if (int32_t rc = check_array(u2, "u2")) return rc;
+    hipLaunchKernelGGL(k_uniforms, dim3(grid_for(n)), dim3(kBlock), 0, as_stream(stream), n, k0,
+                       tag, unit, key_lo(seed), key_hi(seed), u1, u2);
+    return check_launch("capvndf_uniforms launch");
+}
+
+extern "C" int32_t capvndf_philox_blocks(int64_t n, const uint32_t* ctr, uint32_t key0,
+                                         uint32_t key1, uint32_t* out, void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "capvndf_philox_blocks: n < 0");
+    if (n == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(ctr, "ctr")) return rc;
+    if (int32_t rc = check_array(out, "out")) return rc;
+    hipLaunchKernelGGL(k_philox_blocks, dim3(grid_for(n)), dim3(kBlock), 0, as_stream(stream), n,
+                       ctr, key0, key1, out);
+    return check_launch("capvndf_philox_blocks launch");
+}
+
+extern "C" int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters, uint64_t seed,
+                                   uint32_t* out, void* stream) {
+    if (lanes < 0 || iters < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_microbench: bad size");
+    if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018)
+        return fail(CAPVNDF_ERR_BAD_METHOD, "vndf_microbench: unknown method %d", method);
+    if (lanes == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(out, "out")) return rc;
+    const hipStream_t st = as_stream(stream);
+    if (method == CAPVNDF_CAP)
+        hipLaunchKernelGGL(k_microbench<CAPVNDF_CAP>, dim3(grid_for(lanes)), dim3(kBlock), 0, st,
+                           lanes, iters, key_lo(seed), key_hi(seed), out);
+    else
+        hipLaunchKernelGGL(k_microbench<CAPVNDF_DISK2018>, dim3(grid_for(lanes)), dim3(kBlock), 0,
+                           st, lanes, iters, key_lo(seed), key_hi(seed), out);
+    return check_launch("vndf_microbench launch");
+}
+
+extern "C" int32_t capvndf_stream_probe(int64_t n, const float* in0, const float* in1,
+                                        const float* in2, const float* in3, const float* in4,
+                                        float* out0, float* out1, float* out2, float* out3,
+                                        void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "capvndf_stream_probe: n < 0");
+    if (n == 0) return CAPVNDF_OK;
+    const void* req[] = {in0, in1, in2, in3, in4, out0, out1, out2, out3};
+    for (const void* p : req) {
+        if (int32_t rc = check_array(p, "stream probe array")) return rc;
+        if (!aligned_to(p, 16))
+            return fail(CAPVNDF_ERR_MISALIGNED, "capvndf_stream_probe: arrays must be 16-byte aligned");
+    }
+    hipLaunchKernelGGL(k_stream_probe, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0,
+                       as_stream(stream), n, in0, in1, in2, in3, in4, out0, out1, out2, out3);
+    return check_launch("capvndf_stream_probe launch");
+}

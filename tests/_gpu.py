@@ -1,0 +1,77 @@
+"""Helpers shared by the GPU parity tests: device transfer and the tolerance
+rules the comparisons use.
+
+Tolerance of sampled normals and pdfs (FP32 GPU vs FP64 oracle on the same
+FP32 inputs and the same uniforms).  The half vector hs = c + ws of the cap
+construction is the sum of two unit vectors, so its components carry absolute
+rounding errors of O(2^-24) however small hs is.  The normal is
+h = M^-T hs / L with L = |M^-T hs| (M^-T = diag(ax, ay, 1)), so those errors
+reach h as O(2^-24 / L) and reach the pdf (which goes as L^3 / |hs|^2) as a
+relative O(2^-24 / L).  The condition number kappa = 1 / L is computed from the
+oracle's normal: with h_std = M^T h / |M^T h|, |hs| = 2 ws . h_std and
+L = |hs| / |M^T h|.  Rule: every sample has err <= max(2e-6, C 2^-24 kappa),
+and every sample with kappa <= 5 has err <= 2e-6 (C = 64 for h, 128 for the
+pdf).
+
+Heitz's disk sampler (the timing baseline) builds the hemisphere normal from
+its height above the disk, ti = sqrt(1 - t1^2 - t2^2) = ws . h_std, whose
+argument cancels at the rim: ti carries a relative error of O(2^-24 / ti^2),
+which its pdf inherits.  Its pdf is checked with kappa = 1 / L + 1 / ti^2 and
+without the 2e-6 clause (that target is the cap method's; the baseline's
+literal FP32 arithmetic reaches about 3e-6 on well-conditioned samples).
+"""
+
+import numpy as np
+import torch
+
+EPS32 = 2.0 ** -24
+
+
+def to_dev(arrs, dev="cuda"):
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in arrs.items()}
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def kappa(h_ref, wx, wy, wz, ax, ay):
+    """1 / |M^-T hs| of the cap construction at the oracle's normal."""
+    ax = np.asarray(ax, dtype=np.float64)
+    ay = np.asarray(ay, dtype=np.float64)
+    mt = np.stack([h_ref[:, 0] / ax, h_ref[:, 1] / ay, h_ref[:, 2]], axis=1)
+    mtn = np.linalg.norm(mt, axis=1)
+    hstd = mt / mtn[:, None]
+    ws = np.stack([np.asarray(wx, np.float64) * ax, np.asarray(wy, np.float64) * ay,
+                   np.asarray(wz, np.float64)], axis=1)
+    ws /= np.linalg.norm(ws, axis=1, keepdims=True)
+    hs_norm = 2.0 * np.einsum("ij,ij->i", hstd, ws)
+    return mtn / hs_norm
+
+
+def kappa_disk_pdf(h_ref, wx, wy, wz, ax, ay):
+    """1 / L + 1 / ti^2 for the disk sampler's pdf (ti = |hs| / 2)."""
+    k = kappa(h_ref, wx, wy, wz, ax, ay)
+    ax = np.asarray(ax, dtype=np.float64)
+    ay = np.asarray(ay, dtype=np.float64)
+    mt = np.stack([h_ref[:, 0] / ax, h_ref[:, 1] / ay, h_ref[:, 2]], axis=1)
+    hstd = mt / np.linalg.norm(mt, axis=1, keepdims=True)
+    ws = np.stack([np.asarray(wx, np.float64) * ax, np.asarray(wy, np.float64) * ay,
+                   np.asarray(wz, np.float64)], axis=1)
+    ws /= np.linalg.norm(ws, axis=1, keepdims=True)
+    ti = np.einsum("ij,ij->i", hstd, ws)
+    return k + 1.0 / (ti * ti)
+
+
+def check_conditioned(err, kap, c, name, strict_well=True):
+    lim = np.maximum(2e-6, c * EPS32 * kap)
+    bad = err > lim
+    assert not bad.any(), f"{name}: {bad.sum()} samples over the limit, worst " \
+        f"{err[bad].max():.3e} at kappa {kap[bad][np.argmax(err[bad])]:.3e}"
+    well = kap <= 5.0
+    if strict_well:
+        assert np.all(err[well] <= 2e-6), f"{name}: well-conditioned max {err[well].max():.3e}"
+    ratio = err / (EPS32 * kap)
+    print(f"{name}: max err {err.max():.3e}, max err/(eps kappa) {ratio.max():.2f}, "
+          f"fraction > 2e-6 {(err > 2e-6).mean():.2e}, max kappa {kap.max():.3e}")
+    return float((err > 2e-6).mean())

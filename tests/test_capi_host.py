@@ -1,0 +1,108 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/capvndf.h, and rejects bad arguments on
+the host before any HIP call."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "capvndf.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2306_05044_amd as cv
+    if not os.path.exists(cv.LIB_PATH):
+        pytest.fail("libcapvndf.so is not built (run __graft_entry__.build())")
+    return cv.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("vndf_sample", "vndf_pdf", "albedo_estimate", "albedo_estimate_backward",
+                     "albedo_workspace_size", "albedo_batch_plan_create", "albedo_batch_run",
+                     "albedo_batch_plan_destroy", "capvndf_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    raw = ctypes.CDLL(__import__("paper_2306_05044_amd").LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_binding_covers_the_header():
+    import paper_2306_05044_amd as cv
+    assert set(_declared_functions()) == set(cv.exported_symbols())
+
+
+def test_version(lib):
+    assert lib.capvndf_version() == 10000
+
+
+def _err(lib):
+    return lib.capvndf_last_error().decode()
+
+
+def test_sample_argument_errors(lib):
+    P = ctypes.c_void_p
+    fake = P(0x1000)  # never dereferenced: validation fails first
+    args = [fake] * 5
+    assert lib.vndf_sample(-1, *args, None, None, 0, 0, 0, fake, fake, fake, None, None) == -2
+    assert "n = -1" in _err(lib)
+    assert lib.vndf_sample(8, *args, None, None, 0, 0, 7, fake, fake, fake, None, None) == -4
+    assert lib.vndf_sample(8, *args, fake, None, 0, 0, 0, fake, fake, fake, None, None) == -1
+    assert lib.vndf_sample(8, None, fake, fake, fake, fake, None, None, 0, 0, 0, fake, fake, fake,
+                           None, None) == -1
+    assert "wix is NULL" in _err(lib)
+    mis = P(0x1002)
+    assert lib.vndf_sample(8, mis, fake, fake, fake, fake, None, None, 0, 0, 0, fake, fake, fake,
+                           None, None) == -3
+    # n == 0 enqueues nothing and succeeds even with NULL arrays
+    assert lib.vndf_sample(0, None, None, None, None, None, None, None, 0, 0, 0, None, None, None,
+                           None, None) == 0
+    assert lib.vndf_pdf(-5, *[None] * 9, None) == -2
+    assert lib.vndf_pdf(0, *[None] * 9, None) == 0
+
+
+def test_albedo_argument_errors(lib):
+    P = ctypes.c_void_p
+    fake = P(0x1000)
+    assert lib.albedo_workspace_size(-1, 10, 0) == 0
+    assert lib.albedo_workspace_size(4096, 1 << 20, 0) == 4096 * 64 * 2 * 2 * 4
+    assert lib.albedo_workspace_size(4096, 1 << 20, 1) == 4096 * 64 * 3 * 2 * 4
+    assert lib.albedo_workspace_size(3, 1, 0) == 3 * 1 * 2 * 2 * 4
+    five = [fake] * 5
+    assert lib.albedo_estimate(-1, *five, 10, 0, fake, fake, fake, 1 << 20, None) == -2
+    assert lib.albedo_estimate(4, *five, -3, 0, fake, fake, fake, 1 << 20, None) == -2
+    assert lib.albedo_estimate(4, *five, 1 << 40, 0, fake, fake, fake, 1 << 20, None) == -2
+    assert lib.albedo_estimate(4, *five, 100, 0, fake, fake, fake, 8, None) == -5
+    assert "workspace" in _err(lib)
+    assert lib.albedo_estimate(4, *five, 100, 0, fake, fake, None, 0, None) == -5
+    assert lib.albedo_estimate(0, *[None] * 5, 100, 0, None, None, None, 0, None) == 0
+    assert lib.albedo_estimate_backward(4, *five, 100, 0, None, None, fake, fake, fake, fake, 8,
+                                        None) == -5
+    out = P()
+    ns = (ctypes.c_int64 * 2)(10, 20)
+    assert lib.albedo_batch_plan_create(0, *five, None, ns, 0, 1, fake, fake, fake, fake, None,
+                                        None, ctypes.byref(out)) == -2
+    assert lib.albedo_batch_plan_create(2, *five, None, None, 0, 1, fake, fake, fake, fake, None,
+                                        None, ctypes.byref(out)) == -1
+    bad = (ctypes.c_int64 * 2)(10, -20)
+    assert lib.albedo_batch_plan_create(2, *five, None, bad, 0, 1, fake, fake, fake, fake, None,
+                                        None, ctypes.byref(out)) == -2
+    assert lib.albedo_batch_plan_create(2, *five, None, ns, 0, 2, fake, fake, fake, fake, None,
+                                        None, ctypes.byref(out)) == -7
+    assert lib.albedo_batch_run(None, None) == -1
+    lib.albedo_batch_plan_destroy(None)  # no-op

@@ -1,0 +1,161 @@
+"""GPU parity of the albedo estimator, its pathwise adjoint, the autograd
+Function and the batched plan, against the FP64 oracle on the same Philox
+streams.  Albedo within 1e-4 absolute; gradients within
+1e-4 + 1e-3 |g| of the oracle's dual-number gradient."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from _gpu import host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+cv = pytest.importorskip("paper_2306_05044_amd")
+
+ATOL_A = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cv.load_library()
+
+
+def _oracle_sums(g, n, seed, units=None):
+    wo = (g["wx"], g["wy"], g["wz"])
+    a1 = oracle.albedo(wo, g["ax"], g["ay"], n, seed, f0=1.0, units=units)
+    a5 = oracle.albedo(wo, g["ax"], g["ay"], n, seed, f0=0.0, units=units)
+    return a1, a5
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4097, 1 << 14, (1 << 14) + 1, 70001])
+def test_lut_subgrid(n):
+    g = workloads.lut_grid(16, 16)
+    t = to_dev(g)
+    s1, s5 = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2)
+    a1, a5 = _oracle_sums(g, n, 2)
+    e1 = np.abs(host(s1) - a1).max()
+    e5 = np.abs(host(s5) - a5).max()
+    print(f"n={n}: max |err| S1 {e1:.2e} S5 {e5:.2e}")
+    assert e1 <= ATOL_A and e5 <= ATOL_A
+    # both Fresnel values from the one stream
+    for f0 in (0.04, 1.0):
+        a = f0 * host(s1) + (1 - f0) * host(s5)
+        ref = oracle.albedo((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], n, 2, f0=f0)
+        assert np.abs(a - ref).max() <= ATOL_A
+
+
+def test_lut_edges():
+    wx = torch.tensor([0.0, 0.0, 0.6, 0.0], device="cuda")
+    wy = torch.zeros(4, device="cuda")
+    wz = torch.tensor([1.0, -1.0, 0.8, 1.0], device="cuda")
+    ax = torch.tensor([0.5, 0.5, 0.0, 1.0], device="cuda")
+    s1, s5 = cv.albedo_estimate(wx, wy, wz, ax, ax.clone(), 1000, 1)
+    assert host(s1)[1] == 0 and host(s1)[2] == 0 and host(s5)[1] == 0
+    assert host(s1)[0] > 0 and host(s1)[3] > 0
+    s1, s5 = cv.albedo_estimate(wx, wy, wz, ax, ax.clone(), 0, 1)
+    assert torch.all(s1 == 0) and torch.all(s5 == 0)
+    z = torch.zeros(0, device="cuda")
+    s1, s5 = cv.albedo_estimate(z, z, z, z, z, 100, 1)
+    assert s1.numel() == 0
+
+
+def test_lut_full_size_sampled():
+    """64 x 64 cells x 2^20 samples (the LUT workload); 6 cells vs oracle."""
+    g = workloads.lut_grid(64, 64)
+    t = to_dev(g)
+    n = 1 << 20
+    s1, s5 = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2)
+    torch.cuda.synchronize()
+    S1, S5 = host(s1), host(s5)
+    assert np.all(S1 >= 0) and np.all(S1 <= 1.0 + 1e-6) and np.all(S5 >= 0) and np.all(S5 <= S1)
+    cells = np.array([0, 63, 64 * 31 + 7, 64 * 40 + 50, 4032, 4095])
+    sub = {k: v[cells] for k, v in g.items()}
+    a1, a5 = _oracle_sums(sub, n, 2, units=cells)
+    assert np.abs(S1[cells] - a1).max() <= ATOL_A
+    assert np.abs(S5[cells] - a5).max() <= ATOL_A
+    # normal incidence row (mu = 1) at alpha = 1: 1 - ln 2 within MC error
+    c = 64 * 63 + 63
+    assert abs(S1[c] - (1 - np.log(2))) < 4 * 0.366 / np.sqrt(n)
+
+
+def _grad_cells(n_side, seed=3):
+    gg = workloads.grad_grid(n_side, seed=seed)
+    wx, wy, wz = workloads.view_from_angles(gg["theta"], gg["phi"])
+    return {"wx": wx, "wy": wy, "wz": wz, "ax": gg["ax"], "ay": gg["ay"]}
+
+
+def _check_grad(got, ref, name):
+    diff = np.abs(got - ref)
+    lim = 1e-4 + 1e-3 * np.abs(ref)
+    assert np.all(diff <= lim), f"{name}: worst {np.max(diff / lim):.2f}x of the limit"
+
+
+@pytest.mark.parametrize("n", [1 << 12, 4097])
+def test_backward_subgrid(n):
+    g = _grad_cells(8)
+    t = to_dev(g)
+    f0 = np.where(np.arange(64) % 2 == 0, 1.0, 0.04).astype(np.float32)
+    gf = torch.from_numpy(f0).cuda()
+    up = torch.linspace(0.5, 2.0, 64, device="cuda")
+    gx, gy, gt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3,
+                                             f0=gf, grad_albedo=up)
+    A, rx, ry, rt = oracle.albedo_grad((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], n, 3, f0=f0)
+    u = host(up).astype(np.float64)
+    _check_grad(host(gx), u * rx, "d/d alpha_x")
+    _check_grad(host(gy), u * ry, "d/d alpha_y")
+    _check_grad(host(gt), u * rt, "d/d theta_o")
+
+
+def test_backward_full_size_sampled():
+    """32 x 32 anisotropic cells x 2^18 samples; 4 cells vs the oracle."""
+    g = _grad_cells(32)
+    t = to_dev(g)
+    n = 1 << 18
+    gx, gy, gt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
+    torch.cuda.synchronize()
+    assert torch.all(torch.isfinite(gx)) and torch.all(torch.isfinite(gy))
+    cells = np.array([0, 33, 517, 1023])
+    sub = {k: v[cells] for k, v in g.items()}
+    _, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
+                                       n, 3, units=cells)
+    _check_grad(host(gx)[cells], rx, "full d/d alpha_x")
+    _check_grad(host(gy)[cells], ry, "full d/d alpha_y")
+    _check_grad(host(gt)[cells], rt, "full d/d theta_o")
+
+
+def test_autograd_function():
+    gg = workloads.grad_grid(6, seed=11)
+    ax = torch.from_numpy(gg["ax"]).cuda().requires_grad_(True)
+    ay = torch.from_numpy(gg["ay"]).cuda().requires_grad_(True)
+    th = torch.from_numpy(gg["theta"]).cuda().requires_grad_(True)
+    ph = torch.from_numpy(gg["phi"]).cuda()
+    f0 = torch.full_like(ph, 0.04)
+    n = 1 << 12
+    a = cv.albedo(ax, ay, th, ph, f0, n, 5)
+    w = torch.linspace(-1, 1, a.numel(), device="cuda")
+    (a * w).sum().backward()
+    st = torch.sin(th.detach())
+    wo = [host(x) for x in (st * torch.cos(ph), st * torch.sin(ph), torch.cos(th.detach()))]
+    A, rx, ry, rt = oracle.albedo_grad(wo, gg["ax"], gg["ay"], n, 5, f0=0.04)
+    assert np.abs(host(a.detach()) - A).max() <= ATOL_A
+    W = host(w).astype(np.float64)
+    _check_grad(host(ax.grad), W * rx, "autograd alpha_x")
+    _check_grad(host(ay.grad), W * ry, "autograd alpha_y")
+    _check_grad(host(th.grad), W * rt, "autograd theta_o")
+
+
+def test_estimator_determinism():
+    g = workloads.lut_grid(8, 8)
+    t = to_dev(g)
+    a = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 50000, 9)
+    b = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 50000, 9)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    c = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 50000, 9)
+    d = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 50000, 9)
+    for x, y in zip(c, d):
+        assert torch.equal(x, y)

@@ -1,0 +1,123 @@
+"""GPU parity of the batched persistent estimator (graph-replayed) and its
+per-request baseline against the FP64 oracle, replay stability, and the
+autotuner."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from _gpu import host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+cv = pytest.importorskip("paper_2306_05044_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cv.load_library()
+
+
+def _jobs(n_jobs, seed, lo=4, hi=15):
+    j = workloads.batch_jobs(n_jobs, seed=seed, log2_min=lo, log2_max=hi)
+    j["n"][0] = 0      # an empty job
+    j["n"][1] = 1      # a single sample
+    j["n"][2] = 3      # odd count
+    return j
+
+
+def _check(plan, j, f0, with_grad):
+    wo = (j["wx"], j["wy"], j["wz"])
+    A, rx, ry, rt = oracle.albedo_grad(wo, j["ax"], j["ay"], j["n"], 4, f0=f0)
+    assert np.abs(host(plan.albedo) - A).max() <= 1e-4
+    if with_grad:
+        for got, ref in ((plan.grad_ax, rx), (plan.grad_ay, ry), (plan.grad_theta_o, rt)):
+            d = np.abs(host(got) - ref)
+            assert np.all(d <= 1e-4 + 1e-3 * np.abs(ref)), np.max(d / (1e-4 + 1e-3 * np.abs(ref)))
+
+
+@pytest.mark.parametrize("tiling", [None, (256, 8, 2), (512, 16, 4), (256, 64, 16)])
+def test_batch_matches_oracle(tiling):
+    j = _jobs(97, seed=5)
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    f0 = torch.from_numpy(np.where(np.arange(97) % 3 == 0, 0.04, 1.0).astype(np.float32)).cuda()
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, f0=f0,
+                        with_grad=True, tiling=tiling)
+    plan.run()
+    torch.cuda.synchronize()
+    _check(plan, j, host(f0).astype(np.float64), True)
+    info = plan.info()
+    assert info["total_samples"] == int(j["n"].sum())
+    plan.close()
+
+
+def test_batch_forward_only():
+    j = _jobs(50, seed=6)
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=False)
+    plan.run()
+    torch.cuda.synchronize()
+    _check(plan, j, 1.0, False)
+
+
+def test_replays_and_per_request_baseline():
+    j = _jobs(64, seed=7)
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True)
+    plan.run()
+    torch.cuda.synchronize()
+    first = [o.clone() for o in (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o)]
+    for r in range(4):
+        for o in (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o):
+            o.fill_(123.0)
+        x = torch.randn(1 << 16, device="cuda")
+        _ = (x * 2).sum().item()          # unrelated eager work between replays
+        plan.run()
+        torch.cuda.synchronize()
+        for a, b in zip(first, (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o)):
+            assert torch.equal(a, b), f"replay {r} differs"
+    plan.run_per_request()
+    torch.cuda.synchronize()
+    _check(plan, j, 1.0, True)
+    for a, b in zip(first, (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o)):
+        assert torch.allclose(a, b, rtol=1e-5, atol=2e-6)
+
+
+def test_full_batch_sampled():
+    """4096 uneven jobs (2^10 .. 2^22 samples); 24 jobs checked by the oracle."""
+    j = workloads.batch_jobs(4096, seed=4)
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True)
+    plan.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    small = np.flatnonzero(j["n"] <= (1 << 16))
+    large = np.flatnonzero(j["n"] >= (1 << 21))
+    idx = np.concatenate([rng.choice(small, 20, replace=False), rng.choice(large, 4, replace=False)])
+    sub = {k: v[idx] for k, v in j.items()}
+    A, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
+                                       sub["n"], 4, units=idx)
+    assert np.abs(host(plan.albedo)[idx] - A).max() <= 1e-4
+    for got, ref in ((plan.grad_ax, rx), (plan.grad_ay, ry), (plan.grad_theta_o, rt)):
+        d = np.abs(host(got)[idx] - ref)
+        assert np.all(d <= 1e-4 + 1e-3 * np.abs(ref))
+    assert torch.all(torch.isfinite(plan.grad_ax))
+
+
+def test_autotune_small(tmp_path, monkeypatch):
+    monkeypatch.setenv("CAPVNDF_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    j = _jobs(32, seed=8, lo=8, hi=14)
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    best, ms = cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
+    assert best[0] in (256, 512) and best[1] % 8 == 0 and ms > 0
+    text = (tmp_path / "tune.txt").read_text().split()
+    assert [int(x) for x in text[1:4]] == list(best)
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
+    assert plan.info()["tiling"] == best   # picked up from the cache
+    plan.run()
+    torch.cuda.synchronize()
+    _check(plan, j, 1.0, True)

@@ -1,0 +1,225 @@
+"""GPU parity of the sampler path (C ABI through the Python binding) against
+the FP64 oracle: Philox words bit-exact, normals and pdfs within the
+conditioning-aware FP32 rule, the pdf entry point, edge cases, and the
+full-size streaming configuration on sampled outputs."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from _gpu import check_conditioned, host, kappa, kappa_disk_pdf, to_dev
+
+pytestmark = pytest.mark.gpu
+
+cv = pytest.importorskip("paper_2306_05044_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cv.load_library()
+
+
+def _kat_rows():
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                w = [int(x, 16) for x in line.split()]
+                rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def test_philox_known_answers_on_gpu():
+    for ctr, key, expected in _kat_rows():
+        c = torch.tensor(np.array(ctr, dtype=np.uint32).view(np.int32), device="cuda").reshape(1, 4)
+        out = host(cv.capvndf_philox_blocks(c, key[0], key[1])).view(np.uint32).ravel()
+        assert [int(x) for x in out] == expected
+
+
+@pytest.mark.parametrize("seed,tag,unit,k0,n", [
+    (0, 2, 0, 0, 65536), (1, 3, 7, 12345, 4099), (0xDEADBEEFCAFE, 3, 4095, (1 << 33) - 3, 1001),
+    (5, 2, 0, 1, 1)])
+def test_uniform_streams_bit_exact(seed, tag, unit, k0, n):
+    u1, u2 = cv.capvndf_uniforms(seed, tag, unit, k0, n)
+    r1, r2 = oracle.uniforms(seed, tag, unit, k0, n)
+    assert np.array_equal(host(u1).astype(np.float64), r1)
+    assert np.array_equal(host(u2).astype(np.float64), r2)
+
+
+def _compare(d, hx, hy, hz, pdf, h_ref, p_ref, name, method=0):
+    h = np.stack([host(hx), host(hy), host(hz)], axis=1).astype(np.float64)
+    args = (h_ref, d["wx"], d["wy"], d["wz"], d["ax"], d["ay"])
+    kap = kappa(*args)
+    herr = np.linalg.norm(h - h_ref, axis=1)
+    fh = check_conditioned(herr, kap, 64, name + " h")
+    fp = None
+    if pdf is not None:
+        perr = np.abs(host(pdf).astype(np.float64) / p_ref - 1.0)
+        kp = kap if method == 0 else kappa_disk_pdf(*args)
+        fp = check_conditioned(perr, kp, 128, name + " pdf", strict_well=(method == 0))
+    return fh, fp
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_small_config_parity(method):
+    """65,536 isotropic tuples, Philox seed 0, all elements compared."""
+    d = workloads.tuples_small(65536, seed=0)
+    t = to_dev(d)
+    hx, hy, hz, pdf = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=0,
+                                     method=method)
+    h_ref, p_ref = oracle.vndf_sample((d["wx"], d["wy"], d["wz"]), d["ax"], d["ay"], seed=0,
+                                      method=method)
+    fh, fp = _compare(d, hx, hy, hz, pdf, h_ref, p_ref, f"method {method}", method)
+    print(f"method {method}: fraction > 2e-6: h {fh:.2e}, pdf {fp:.2e}")
+    # the same numbers through caller-given uniforms are bit-identical
+    u1, u2 = cv.capvndf_uniforms(0, 2, 0, 0, 65536)
+    e = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], u1=u1, u2=u2, method=method)
+    for a, b in zip((hx, hy, hz, pdf), e):
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 63, 64, 65, 255, 1023, 4097])
+def test_ragged_sizes_and_paths(n):
+    d = workloads.tuples_streaming(n + 8, seed=21)
+    t = to_dev(d)
+    ref = cv.vndf_sample(t["wx"][:n], t["wy"][:n], t["wz"][:n], t["ax"][:n], t["ay"][:n], seed=9,
+                         index_base=6)
+    h_ref, p_ref = oracle.vndf_sample((d["wx"][:n], d["wy"][:n], d["wz"][:n]), d["ax"][:n],
+                                      d["ay"][:n], seed=9, index_base=6)
+    sub = {k: v[:n] for k, v in d.items()}
+    _compare(sub, *ref, h_ref, p_ref, f"n={n}")
+    # misaligned views (offset by one element) take the scalar path: same bits
+    mis = {k: v[1:n + 1] for k, v in t.items()}
+    got = cv.vndf_sample(mis["wx"], mis["wy"], mis["wz"], mis["ax"], mis["ay"], seed=9,
+                         index_base=7)
+    h_m, p_m = oracle.vndf_sample(tuple(d[k][1:n + 1] for k in ("wx", "wy", "wz")),
+                                  d["ax"][1:n + 1], d["ay"][1:n + 1], seed=9, index_base=7)
+    _compare({k: v[1:n + 1] for k, v in d.items()}, *got, h_m, p_m, f"n={n} misaligned")
+    # odd index_base with aligned arrays: scalar path, same stream positions
+    got2 = cv.vndf_sample(t["wx"][:n], t["wy"][:n], t["wz"][:n], t["ax"][:n], t["ay"][:n],
+                          seed=9, index_base=7)
+    h_o, _ = oracle.vndf_sample((d["wx"][:n], d["wy"][:n], d["wz"][:n]), d["ax"][:n],
+                                d["ay"][:n], seed=9, index_base=7)
+    assert np.max(np.linalg.norm(np.stack([host(x) for x in got2[:3]], 1) - h_o, axis=1)) < 1e-4
+
+
+def test_vector_and_scalar_paths_agree_bitwise():
+    d = workloads.tuples_streaming(4096 + 1, seed=3)
+    t = to_dev(d)
+    a = cv.vndf_sample(t["wx"][:4096], t["wy"][:4096], t["wz"][:4096], t["ax"][:4096],
+                       t["ay"][:4096], seed=4)
+    # copy into misaligned storage: same values, scalar path
+    buf = {k: torch.zeros(4097, device="cuda") for k in t}
+    for k in t:
+        buf[k][1:].copy_(t[k][:4096])
+    b = cv.vndf_sample(buf["wx"][1:], buf["wy"][1:], buf["wz"][1:], buf["ax"][1:], buf["ay"][1:],
+                       seed=4)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_empty_and_no_pdf():
+    z = torch.zeros(0, device="cuda")
+    out = cv.vndf_sample(z, z, z, z, z)
+    assert all(o.numel() == 0 for o in out)
+    d = workloads.tuples_small(1000, seed=5)
+    t = to_dev(d)
+    a = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=3)
+    b = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=3, with_pdf=False)
+    assert b[3] is None
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_domain_edges(method):
+    wz = torch.tensor([1.0, 0.0, -0.5, 1.0, 1.0, float("nan"), 1.0, 1e-3, 1.0, 1.0], device="cuda")
+    wx = torch.tensor([0.0, 1.0, 0.8, 0.0, 0.0, 0.0, 0.0, 0.9999995, 0.0, 0.0], device="cuda")
+    wy = torch.zeros_like(wz)
+    ax = torch.tensor([0.5, 0.5, 0.5, 0.0, 0.5, 0.5, -1.0, 1e-3, 1e-3, 1.0], device="cuda")
+    ay = torch.tensor([0.5, 0.5, 0.5, 0.5, 0.0, 0.5, 0.5, 1e-3, 1.0, 1e-3], device="cuda")
+    hx, hy, hz, pdf = cv.vndf_sample(wx, wy, wz, ax, ay, seed=1, method=method)
+    H = np.stack([host(hx), host(hy), host(hz)], 1)
+    P = host(pdf)
+    for i in (1, 2, 3, 4, 5, 6):
+        assert tuple(H[i]) == (0.0, 0.0, 1.0) and P[i] == 0.0
+    for i in (0, 7, 8, 9):
+        assert np.all(np.isfinite(H[i])) and P[i] > 0 and abs(np.linalg.norm(H[i]) - 1) < 1e-6
+
+
+def test_pdf_entry_point():
+    """vndf_pdf at the GPU's FP32 normals vs the oracle's Eq. (1) at the same
+    FP32 values; relative tolerance max(2e-6, 8 eps / (wi.h))."""
+    d = workloads.tuples_streaming(65536 + 3, seed=8)
+    t = to_dev(d)
+    hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=2)
+    pdf = cv.vndf_pdf(t["wx"], t["wy"], t["wz"], hx, hy, hz, t["ax"], t["ay"])
+    H = [host(x).astype(np.float64) for x in (hx, hy, hz)]
+    ref = oracle.vndf_pdf((d["wx"], d["wy"], d["wz"]), H, d["ax"], d["ay"])
+    w = np.stack([d[k].astype(np.float64) for k in ("wx", "wy", "wz")], 1)
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
+    rel = np.abs(host(pdf) / ref - 1.0)
+    lim = np.maximum(2e-6, 8 * 2.0 ** -24 / dot)
+    assert np.all(rel <= lim), (rel / lim).max()
+    # zero outside the domain
+    neg = -t["wz"][:16].clone()
+    p0 = cv.vndf_pdf(t["wx"][:16].clone(), t["wy"][:16].clone(), neg, hx[:16].clone(),
+                     hy[:16].clone(), hz[:16].clone(), t["ax"][:16].clone(), t["ay"][:16].clone())
+    assert torch.all(p0 == 0)
+
+
+def test_determinism():
+    d = workloads.tuples_streaming(1 << 16, seed=1)
+    t = to_dev(d)
+    a = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=1)
+    b = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=1)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_streaming_full_size_sampled(method):
+    """2^26 anisotropic tuples in the benchmark's launch configuration; 2^16
+    sampled outputs against the oracle, invariants on all of them."""
+    n = 1 << 26
+    d = workloads.tuples_streaming(n, seed=1)
+    t = to_dev(d)
+    del d
+    hx, hy, hz, pdf = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=1,
+                                     method=method)
+    torch.cuda.synchronize()
+    norm = torch.sqrt(hx.double() ** 2 + hy.double() ** 2 + hz.double() ** 2)
+    assert torch.all(torch.isfinite(pdf)) and torch.all(pdf > 0)
+    assert torch.max(torch.abs(norm - 1.0)).item() < 2e-6
+    assert torch.all(hz > 0)
+    # wi . h >= 0 up to the conditioning of each sample (kappa from the GPU's h)
+    wn = torch.rsqrt(t["wx"].double() ** 2 + t["wy"].double() ** 2 + t["wz"].double() ** 2)
+    dot = (t["wx"] * hx + t["wy"] * hy + t["wz"] * hz).double() * wn
+    ax, ay = t["ax"].double(), t["ay"].double()
+    mx, my, mz = hx.double() / ax, hy.double() / ay, hz.double()
+    mn = torch.sqrt(mx * mx + my * my + mz * mz)
+    sx, sy, sz = ax * t["wx"].double(), ay * t["wy"].double(), t["wz"].double()
+    sn = torch.sqrt(sx * sx + sy * sy + sz * sz)
+    ti = (mx * sx + my * sy + mz * sz) / (mn * sn)
+    kap = mn / (2.0 * ti.clamp_min(1e-30))
+    assert torch.all(dot >= -64 * 2.0 ** -24 * kap - 1e-7)
+    del wn, dot, ax, ay, mx, my, mz, mn, sx, sy, sz, sn, ti, kap
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(n, size=1 << 16, replace=False))
+    it = torch.from_numpy(idx).cuda()
+    sub = {k: host(v[it]) for k, v in t.items()}
+    u1 = np.empty(len(idx))
+    u2 = np.empty(len(idx))
+    for j, k in enumerate(idx):
+        a, b = oracle.uniforms(1, 2, 0, int(k), 1)
+        u1[j], u2[j] = a[0], b[0]
+    h_ref, p_ref = oracle.vndf_sample((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
+                                      u1=u1, u2=u2, method=method)
+    fh, fp = _compare(sub, hx[it], hy[it], hz[it], pdf[it], h_ref, p_ref, "full size", method)
+    print(f"full size method {method}: fraction > 2e-6: h {fh:.2e}, pdf {fp:.2e}")
