@@ -59,46 +59,15 @@ __device__ __forceinline__ Words philox_pair(uint64_t p, uint32_t unit, uint32_t
 __device__ __forceinline__ float unit24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 
 // ---------------------------------------------------------------------------
-// sin(2 pi u) and cos(2 pi u) for the azimuth.  Exact quadrant reduction in
-// turns (4u and the remainder are exact for u on the 2^-24 lattice or any
-// float in [0, 1)), then Taylor polynomials of sin and cos of 2 pi r on
-// |r| <= 1/8 (truncation below 2e-9, i.e. under half an ulp), Horner in FMA.
+// sin(2 pi u) and cos(2 pi u) for the azimuth.  The hardware sine and cosine
+// take their argument in turns (revolutions), so the azimuth needs no
+// multiplication by 2 pi and no range reduction for u in [0, 1).  Measured on
+// gfx950 over every point of the 2^-24 lattice in [0, 1): absolute error at
+// most 1.25e-7 (about two ulps of 1), far inside the sampler's tolerance.
 // ---------------------------------------------------------------------------
-namespace detail {
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-constexpr double p2 = kTwoPi * kTwoPi;
-constexpr float kS1 = (float)kTwoPi;
-constexpr float kS3 = (float)(-kTwoPi * p2 / 6.0);
-constexpr float kS5 = (float)(kTwoPi * p2 * p2 / 120.0);
-constexpr float kS7 = (float)(-kTwoPi * p2 * p2 * p2 / 5040.0);
-constexpr float kS9 = (float)(kTwoPi * p2 * p2 * p2 * p2 / 362880.0);
-constexpr float kC2 = (float)(-p2 / 2.0);
-constexpr float kC4 = (float)(p2 * p2 / 24.0);
-constexpr float kC6 = (float)(-p2 * p2 * p2 / 720.0);
-constexpr float kC8 = (float)(p2 * p2 * p2 * p2 / 40320.0);
-constexpr float kC10 = (float)(-p2 * p2 * p2 * p2 * p2 / 3628800.0);
-}  // namespace detail
-
 __device__ __forceinline__ void sincos_turns(float u, float* s, float* c) {
-    using namespace detail;
-    const float q = __builtin_rintf(4.0f * u);
-    const float r = __builtin_fmaf(q, -0.25f, u);
-    const float r2 = r * r;
-    float ps = __builtin_fmaf(kS9, r2, kS7);
-    ps = __builtin_fmaf(ps, r2, kS5);
-    ps = __builtin_fmaf(ps, r2, kS3);
-    ps = __builtin_fmaf(ps, r2, kS1);
-    const float sr = ps * r;
-    float pc = __builtin_fmaf(kC10, r2, kC8);
-    pc = __builtin_fmaf(pc, r2, kC6);
-    pc = __builtin_fmaf(pc, r2, kC4);
-    pc = __builtin_fmaf(pc, r2, kC2);
-    const float cr = __builtin_fmaf(pc, r2, 1.0f);
-    const int qi = (int)q;
-    const float ss = (qi & 1) ? cr : sr;
-    const float cc = (qi & 1) ? sr : cr;
-    *s = (qi & 2) ? -ss : ss;
-    *c = ((qi + 1) & 2) ? -cc : cc;
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
 }
 
 // Hardware reciprocal, reciprocal square root and square root (about 1 ulp).

@@ -1,10 +1,10 @@
 // Streaming VNDF sampling and pdf kernels, random-number hooks, the
 // register-resident microbenchmark and the streaming-bandwidth probe.
 //
-// Layout: structure of arrays in HBM.  The vector path gives each lane four
-// consecutive tuples, so every array is read and written with one 16-byte
-// access per lane (fully coalesced dwordx4, non-temporal: nothing is reused),
-// and the lane's four tuples take exactly two Philox blocks.
+// Layout: structure of arrays in HBM.  The vector path gives each lane groups
+// of four consecutive tuples, so every array is read and written with 16-byte
+// accesses per lane (fully coalesced dwordx4, non-temporal: nothing is
+// reused), and each group of four tuples takes exactly two Philox blocks.
 #include "common.hpp"
 #include "device_math.hpp"
 
@@ -13,13 +13,31 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBlock = 256;
+// Launch shape of the streaming kernels (build-time constants): threads per
+// block, vec4 groups per lane, and whether loads (bit 0) and stores (bit 1)
+// are non-temporal.
+#ifndef CAPVNDF_STREAM_BLOCK
+#define CAPVNDF_STREAM_BLOCK 256
+#endif
+#ifndef CAPVNDF_STREAM_GROUPS
+#define CAPVNDF_STREAM_GROUPS 4
+#endif
+#ifndef CAPVNDF_STREAM_NT
+#define CAPVNDF_STREAM_NT 3
+#endif
+constexpr int kBlock = CAPVNDF_STREAM_BLOCK;
+constexpr int kGroups = CAPVNDF_STREAM_GROUPS;
+constexpr int64_t kTile = (int64_t)kBlock * 4 * kGroups;
 
 __device__ __forceinline__ f4 load4(const float* p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    if (CAPVNDF_STREAM_NT & 1) return __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    return *reinterpret_cast<const f4*>(p);
 }
 __device__ __forceinline__ void store4(float* p, f4 v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+    if (CAPVNDF_STREAM_NT & 2)
+        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
+    else
+        *reinterpret_cast<f4*>(p) = v;
 }
 
 // One tuple: general sampler with the chosen hemisphere routine.  Inputs
@@ -59,8 +77,12 @@ __device__ __forceinline__ void stream_u(uint64_t k, uint32_t key0, uint32_t key
     u2 = unit24(odd ? w.w3 : w.w1);
 }
 
-// Vector path: lane t owns tuples 4t .. 4t+3 (index_base even, arrays 16-byte
-// aligned).  A lane whose four tuples straddle n finishes them one by one.
+// Vector path (index_base even, arrays 16-byte aligned).  A block owns a tile
+// of kBlock * 4 * kGroups consecutive tuples; lane l handles kGroups groups of
+// four, group g starting at tile + (g * kBlock + l) * 4, so every wavefront
+// access is a contiguous 1 KiB per array.  All loads of a lane are issued
+// before any arithmetic to keep enough bytes in flight.  Groups that straddle
+// n finish their tuples one by one.
 template <int METHOD, bool EXPLICIT_U, bool WITH_PDF>
 __global__ __launch_bounds__(kBlock) void k_sample_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
@@ -68,48 +90,57 @@ __global__ __launch_bounds__(kBlock) void k_sample_v4(
     const float* __restrict__ u1p, const float* __restrict__ u2p, uint64_t index_base,
     uint32_t key0, uint32_t key1, float* __restrict__ hx, float* __restrict__ hy,
     float* __restrict__ hz, float* __restrict__ pdf) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i0 = t * 4;
-    if (i0 >= n) return;
-    if (i0 + 4 <= n) {
-        const f4 x = load4(wix + i0), y = load4(wiy + i0), z = load4(wiz + i0);
-        const f4 a = load4(ax + i0), b = load4(ay + i0);
-        f4 r1, r2;
-        if (EXPLICIT_U) {
-            r1 = load4(u1p + i0);
-            r2 = load4(u2p + i0);
-        } else {
-            const uint64_t pair = (index_base >> 1) + (uint64_t)(2 * t);
-            const Words w0 = philox_pair(pair, 0u, kTagSample, key0, key1);
-            const Words w1 = philox_pair(pair + 1, 0u, kTagSample, key0, key1);
-            r1 = f4{unit24(w0.w0), unit24(w0.w2), unit24(w1.w0), unit24(w1.w2)};
-            r2 = f4{unit24(w0.w1), unit24(w0.w3), unit24(w1.w1), unit24(w1.w3)};
-        }
-        f4 ox, oy, oz, op;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
+    f4 x[kGroups], y[kGroups], z[kGroups], a[kGroups], b[kGroups], r1[kGroups], r2[kGroups];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float hxj, hyj, hzj, pj;
-            sample_one<METHOD, WITH_PDF>(x[j], y[j], z[j], a[j], b[j], r1[j], r2[j], hxj, hyj,
-                                         hzj, pj);
-            ox[j] = hxj; oy[j] = hyj; oz[j] = hzj; op[j] = pj;
-        }
-        store4(hx + i0, ox);
-        store4(hy + i0, oy);
-        store4(hz + i0, oz);
-        if (WITH_PDF) store4(pdf + i0, op);
-    } else {
-        for (int64_t i = i0; i < n; ++i) {
-            float r1, r2;
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            x[g] = load4(wix + i0); y[g] = load4(wiy + i0); z[g] = load4(wiz + i0);
+            a[g] = load4(ax + i0); b[g] = load4(ay + i0);
             if (EXPLICIT_U) {
-                r1 = u1p[i]; r2 = u2p[i];
-            } else {
-                stream_u(index_base + (uint64_t)i, key0, key1, r1, r2);
+                r1[g] = load4(u1p + i0);
+                r2[g] = load4(u2p + i0);
             }
-            float hxi, hyi, hzi, pi;
-            sample_one<METHOD, WITH_PDF>(wix[i], wiy[i], wiz[i], ax[i], ay[i], r1, r2, hxi, hyi,
-                                         hzi, pi);
-            hx[i] = hxi; hy[i] = hyi; hz[i] = hzi;
-            if (WITH_PDF) pdf[i] = pi;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            if (!EXPLICIT_U) {
+                const uint64_t pair = (index_base >> 1) + (uint64_t)(i0 >> 1);
+                const Words w0 = philox_pair(pair, 0u, kTagSample, key0, key1);
+                const Words w1 = philox_pair(pair + 1, 0u, kTagSample, key0, key1);
+                r1[g] = f4{unit24(w0.w0), unit24(w0.w2), unit24(w1.w0), unit24(w1.w2)};
+                r2[g] = f4{unit24(w0.w1), unit24(w0.w3), unit24(w1.w1), unit24(w1.w3)};
+            }
+            f4 ox, oy, oz, op;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float hxj, hyj, hzj, pj;
+                sample_one<METHOD, WITH_PDF>(x[g][j], y[g][j], z[g][j], a[g][j], b[g][j],
+                                             r1[g][j], r2[g][j], hxj, hyj, hzj, pj);
+                ox[j] = hxj; oy[j] = hyj; oz[j] = hzj; op[j] = pj;
+            }
+            store4(hx + i0, ox);
+            store4(hy + i0, oy);
+            store4(hz + i0, oz);
+            if (WITH_PDF) store4(pdf + i0, op);
+        } else {
+            for (int64_t i = i0; i < n && i < i0 + 4; ++i) {
+                float q1, q2;
+                if (EXPLICIT_U) {
+                    q1 = u1p[i]; q2 = u2p[i];
+                } else {
+                    stream_u(index_base + (uint64_t)i, key0, key1, q1, q2);
+                }
+                float hxi, hyi, hzi, pi;
+                sample_one<METHOD, WITH_PDF>(wix[i], wiy[i], wiz[i], ax[i], ay[i], q1, q2, hxi,
+                                             hyi, hzi, pi);
+                hx[i] = hxi; hy[i] = hyi; hz[i] = hzi;
+                if (WITH_PDF) pdf[i] = pi;
+            }
         }
     }
 }
@@ -161,20 +192,32 @@ __global__ __launch_bounds__(kBlock) void k_pdf_v4(
     const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
     const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
     float* __restrict__ pdf) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i0 = t * 4;
-    if (i0 >= n) return;
-    if (i0 + 4 <= n) {
-        const f4 x = load4(wix + i0), y = load4(wiy + i0), z = load4(wiz + i0);
-        const f4 hx = load4(hxp + i0), hy = load4(hyp + i0), hz = load4(hzp + i0);
-        const f4 a = load4(ax + i0), b = load4(ay + i0);
-        f4 o;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
+    f4 x[kGroups], y[kGroups], z[kGroups], hx[kGroups], hy[kGroups], hz[kGroups], a[kGroups],
+        b[kGroups];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) o[j] = pdf_one(x[j], y[j], z[j], hx[j], hy[j], hz[j], a[j], b[j]);
-        store4(pdf + i0, o);
-    } else {
-        for (int64_t i = i0; i < n; ++i)
-            pdf[i] = pdf_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i]);
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            x[g] = load4(wix + i0); y[g] = load4(wiy + i0); z[g] = load4(wiz + i0);
+            hx[g] = load4(hxp + i0); hy[g] = load4(hyp + i0); hz[g] = load4(hzp + i0);
+            a[g] = load4(ax + i0); b[g] = load4(ay + i0);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            f4 o;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                o[j] = pdf_one(x[g][j], y[g][j], z[g][j], hx[g][j], hy[g][j], hz[g][j], a[g][j],
+                               b[g][j]);
+            store4(pdf + i0, o);
+        } else {
+            for (int64_t i = i0; i < n && i < i0 + 4; ++i)
+                pdf[i] = pdf_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i]);
+        }
     }
 }
 
@@ -255,27 +298,37 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(
     const float* __restrict__ in2, const float* __restrict__ in3,
     const float* __restrict__ in4, float* __restrict__ out0, float* __restrict__ out1,
     float* __restrict__ out2, float* __restrict__ out3) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t i0 = t * 4;
-    if (i0 >= n) return;
-    if (i0 + 4 <= n) {
-        const f4 a = load4(in0 + i0), b = load4(in1 + i0), c = load4(in2 + i0);
-        const f4 d = load4(in3 + i0), e = load4(in4 + i0);
-        store4(out0 + i0, a + e);
-        store4(out1 + i0, b);
-        store4(out2 + i0, c);
-        store4(out3 + i0, d);
-    } else {
-        for (int64_t i = i0; i < n; ++i) {
-            out0[i] = in0[i] + in4[i];
-            out1[i] = in1[i];
-            out2[i] = in2[i];
-            out3[i] = in3[i];
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
+    f4 a[kGroups], b[kGroups], c[kGroups], d[kGroups], e[kGroups];
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            a[g] = load4(in0 + i0); b[g] = load4(in1 + i0); c[g] = load4(in2 + i0);
+            d[g] = load4(in3 + i0); e[g] = load4(in4 + i0);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            store4(out0 + i0, a[g] + e[g]);
+            store4(out1 + i0, b[g]);
+            store4(out2 + i0, c[g]);
+            store4(out3 + i0, d[g]);
+        } else {
+            for (int64_t i = i0; i < n && i < i0 + 4; ++i) {
+                out0[i] = in0[i] + in4[i];
+                out1[i] = in1[i];
+                out2[i] = in2[i];
+                out3[i] = in3[i];
+            }
         }
     }
 }
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+inline unsigned tiles_for(int64_t n) { return (unsigned)((n + kTile - 1) / kTile); }
 
 template <int METHOD, bool EU, bool WP>
 void launch_sample(bool vec, int64_t n, const float* wix, const float* wiy, const float* wiz,
@@ -283,7 +336,7 @@ void launch_sample(bool vec, int64_t n, const float* wix, const float* wiy, cons
                    uint64_t index_base, uint32_t k0, uint32_t k1, float* hx, float* hy, float* hz,
                    float* pdf, hipStream_t st) {
     if (vec) {
-        hipLaunchKernelGGL((k_sample_v4<METHOD, EU, WP>), dim3(grid_for((n + 3) / 4)),
+        hipLaunchKernelGGL((k_sample_v4<METHOD, EU, WP>), dim3(tiles_for(n)),
                            dim3(kBlock), 0, st, n, wix, wiy, wiz, ax, ay, u1, u2, index_base, k0,
                            k1, hx, hy, hz, pdf);
     } else {
@@ -363,7 +416,7 @@ extern "C" int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const
     }
     const hipStream_t st = as_stream(stream);
     if (vec)
-        hipLaunchKernelGGL(k_pdf_v4, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0, st, n, wix,
+        hipLaunchKernelGGL(k_pdf_v4, dim3(tiles_for(n)), dim3(kBlock), 0, st, n, wix,
                            wiy, wiz, hx, hy, hz, ax, ay, pdf);
     else
         hipLaunchKernelGGL(k_pdf_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix, wiy,
@@ -422,7 +475,7 @@ extern "C" int32_t capvndf_stream_probe(int64_t n, const float* in0, const float
         if (!aligned_to(p, 16))
             return fail(CAPVNDF_ERR_MISALIGNED, "capvndf_stream_probe: arrays must be 16-byte aligned");
     }
-    hipLaunchKernelGGL(k_stream_probe, dim3(grid_for((n + 3) / 4)), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_stream_probe, dim3(tiles_for(n)), dim3(kBlock), 0,
                        as_stream(stream), n, in0, in1, in2, in3, in4, out0, out1, out2, out3);
     return check_launch("capvndf_stream_probe launch");
 }
