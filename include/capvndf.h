@@ -103,11 +103,12 @@ int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz
                  const float* ay, float* pdf, void* stream);
 
 /*
- * albedo_workspace_size -- bytes of device workspace that albedo_estimate
- * (with_grad = 0) or albedo_estimate_backward (with_grad = 1) needs for
- * ncells cells of nsamples samples each.  Returns 0 for invalid sizes.
+ * albedo_workspace_size -- bytes of device workspace needed for ncells cells
+ * of nsamples samples each by albedo_estimate (mode 0),
+ * albedo_estimate_backward (mode 1) or albedo_value_and_grad (mode 2; enough
+ * with or without gradients).  Returns 0 for invalid sizes or modes.
  */
-size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t with_grad);
+size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t mode);
 
 /*
  * albedo_estimate -- directional albedo per cell: the Monte Carlo estimator
@@ -165,6 +166,28 @@ int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* 
                                  void* stream);
 
 /*
+ * albedo_value_and_grad -- A(F0) per cell for the cell's own F0 (the same
+ * estimator and Philox streams as albedo_estimate) and, when the three
+ * gradient outputs are given, dA/d alpha_x, dA/d alpha_y and dA/d theta_o
+ * (definitions as in albedo_estimate_backward) from the same pass over the
+ * samples.  Each cell's value depends only on its own parameters, so these
+ * three arrays are the whole Jacobian: a caller that needs the gradient of a
+ * loss multiplies them by dL/dA instead of running the backward pass.
+ *
+ *   (cell inputs, nsamples, seed as albedo_estimate)
+ *   f0          [ncells] Fresnel F0 per cell (NULL = 1)
+ *   albedo      [ncells] out: A(F0)
+ *   grad_ax, grad_ay, grad_theta_o [ncells] out, all NULL for values only
+ *   workspace   albedo_workspace_size(ncells, nsamples, 2) bytes
+ * Errors: as albedo_estimate; NULL_PTR if only some gradient outputs are given.
+ */
+int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy,
+                              const float* woz, const float* ax, const float* ay,
+                              int64_t nsamples, uint64_t seed, const float* f0, float* albedo,
+                              float* grad_ax, float* grad_ay, float* grad_theta_o,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Batched estimation of many jobs with uneven sample counts (forward value
  * A_j(F0_j) plus, with with_grad, dA_j/d alpha_x, dA_j/d alpha_y and
  * dA_j/d theta_o), in one persistent launch plus a fixed-order finishing pass,
@@ -211,8 +234,8 @@ int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, const float* w
 int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream);
 
 /* Same jobs and outputs as albedo_batch_run, launched the per-request way:
- * two kernels (estimate + finish) per job for the value and two more per job
- * for the gradient, no graph.  The baseline the batch is measured against. */
+ * per job one albedo_value_and_grad-style estimate kernel plus its finishing
+ * kernel, no graph.  The baseline the batch is measured against. */
 int32_t albedo_batch_run_per_request(capvndf_batch_plan* plan, void* stream);
 
 /* Tiling and chunk statistics of a plan. */

@@ -7,7 +7,8 @@ the current stream) into the C ABI declared in ``include/capvndf.h``.  There is
 no CPU fallback: without the built library every call raises.
 
 Names mirror the C entry points: ``vndf_sample``, ``vndf_pdf``,
-``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_workspace_size``,
+``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_value_and_grad``,
+``albedo_workspace_size``,
 ``BatchPlan`` (``albedo_batch_plan_create`` / ``albedo_batch_run`` /
 ``albedo_batch_run_per_request``), ``albedo_batch_autotune``, and the hooks
 ``capvndf_uniforms``, ``capvndf_philox_blocks``, ``vndf_microbench`` and
@@ -64,6 +65,8 @@ _SIGNATURES = {
                         _I32),
     "albedo_estimate_backward": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, _P, _P, _P,
                                   ctypes.c_size_t, _P], _I32),
+    "albedo_value_and_grad": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, _P, _P, _P,
+                               ctypes.c_size_t, _P], _I32),
     "albedo_batch_plan_create": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _I32, _P, _P, _P, _P,
                                   ctypes.POINTER(Tiling), _P, ctypes.POINTER(_P)], _I32),
     "albedo_batch_run": ([_P, _P], _I32),
@@ -182,8 +185,9 @@ def vndf_pdf(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
     return pdf
 
 
-def albedo_workspace_size(ncells: int, nsamples: int, with_grad: bool) -> int:
-    return int(load_library().albedo_workspace_size(ncells, nsamples, 1 if with_grad else 0))
+def albedo_workspace_size(ncells: int, nsamples: int, mode: int) -> int:
+    """Workspace bytes: mode 0 albedo_estimate, 1 backward, 2 value_and_grad."""
+    return int(load_library().albedo_workspace_size(ncells, nsamples, int(mode)))
 
 
 def _workspace(nbytes, device):
@@ -197,7 +201,7 @@ def albedo_estimate(wox, woy, woz, ax, ay, nsamples, seed, workspace=None, strea
     for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay).items():
         _dev(t, k)
     _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay)
-    nbytes = albedo_workspace_size(n, nsamples, False)
+    nbytes = albedo_workspace_size(n, nsamples, 0)
     ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
     s1 = torch.empty_like(wox)
     s5 = torch.empty_like(wox)
@@ -216,7 +220,7 @@ def albedo_estimate_backward(wox, woy, woz, ax, ay, nsamples, seed, f0=None, gra
                      grad_albedo=grad_albedo).items():
         _dev(t, k)
     _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0, grad_albedo=grad_albedo)
-    nbytes = albedo_workspace_size(n, nsamples, True)
+    nbytes = albedo_workspace_size(n, nsamples, 1)
     ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
     gx, gy, gt = (torch.empty_like(wox) for _ in range(3))
     rc = lib.albedo_estimate_backward(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
@@ -225,6 +229,26 @@ def albedo_estimate_backward(wox, woy, woz, ax, ay, nsamples, seed, f0=None, gra
                                       _stream(stream))
     _check("albedo_estimate_backward", rc)
     return gx, gy, gt
+
+
+def albedo_value_and_grad(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_grad=True,
+                          workspace=None, stream=None):
+    """(A(F0), dA/d alpha_x, dA/d alpha_y, dA/d theta_o) per cell from one pass;
+    the gradients are None when with_grad is False."""
+    lib = load_library()
+    n = wox.numel()
+    for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0).items():
+        _dev(t, k)
+    _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
+    nbytes = albedo_workspace_size(n, nsamples, 2)
+    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    a = torch.empty_like(wox)
+    g = [torch.empty_like(wox) for _ in range(3)] if with_grad else [None, None, None]
+    rc = lib.albedo_value_and_grad(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
+                                   nsamples, seed, _ptr(f0), _ptr(a), *[_ptr(x) for x in g],
+                                   _ptr(ws), ws.numel() * 4, _stream(stream))
+    _check("albedo_value_and_grad", rc)
+    return (a, *g)
 
 
 class BatchPlan:

@@ -1,10 +1,12 @@
 """Differentiable directional albedo: a torch.autograd.Function over the
 estimator of Appendix A (L == 1) and its pathwise adjoint.
 
-Forward runs ``albedo_estimate`` (both Fresnel sums from one stream) and
-combines them for the per-cell F0; backward runs ``albedo_estimate_backward``,
-which recomputes every sample from its Philox counter (no samples are saved,
-only the inputs and the seed).
+A cell's albedo depends only on that cell's parameters, so the Jacobian is
+diagonal: three numbers per cell.  When any input needs a gradient, forward
+runs ``albedo_value_and_grad``, which produces the value and those three
+derivatives in one pass over the samples, and backward scales them by the
+incoming gradient.  Otherwise forward runs the value-only kernel.  Nothing
+but the inputs' derivatives is saved (no samples).
 """
 
 from __future__ import annotations
@@ -22,32 +24,28 @@ class AlbedoFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, ax, ay, theta_o, phi_o, f0, nsamples, seed):
-        from . import albedo_estimate
+        from . import albedo_value_and_grad
         # view direction from its spherical angles (argument marshalling)
         st = torch.sin(theta_o)
-        wox = (st * torch.cos(phi_o)).contiguous()
-        woy = (st * torch.sin(phi_o)).contiguous()
-        woz = torch.cos(theta_o).contiguous()
-        axc, ayc, f0c = ax.contiguous(), ay.contiguous(), f0.contiguous()
-        s1, s5 = albedo_estimate(wox.reshape(-1), woy.reshape(-1), woz.reshape(-1),
-                                 axc.reshape(-1), ayc.reshape(-1), int(nsamples), int(seed))
-        f = f0c.reshape(-1)
-        a = f * s1 + (1.0 - f) * s5
-        ctx.save_for_backward(wox, woy, woz, axc, ayc, f0c)
-        ctx.nsamples = int(nsamples)
-        ctx.seed = int(seed)
-        return a.reshape(ax.shape)
+        wox = (st * torch.cos(phi_o)).contiguous().reshape(-1)
+        woy = (st * torch.sin(phi_o)).contiguous().reshape(-1)
+        woz = torch.cos(theta_o).contiguous().reshape(-1)
+        need = any(ctx.needs_input_grad[:3])
+        a, gx, gy, gt = albedo_value_and_grad(
+            wox, woy, woz, ax.contiguous().reshape(-1), ay.contiguous().reshape(-1),
+            int(nsamples), int(seed), f0=f0.contiguous().reshape(-1), with_grad=need)
+        shape = ax.shape
+        if need:
+            ctx.save_for_backward(gx.reshape(shape), gy.reshape(shape), gt.reshape(shape))
+        return a.reshape(shape)
 
     @staticmethod
     def backward(ctx, grad_a):
-        from . import albedo_estimate_backward
-        wox, woy, woz, ax, ay, f0 = ctx.saved_tensors
-        g = grad_a.contiguous().reshape(-1).to(torch.float32)
-        gx, gy, gt = albedo_estimate_backward(
-            wox.reshape(-1), woy.reshape(-1), woz.reshape(-1), ax.reshape(-1), ay.reshape(-1),
-            ctx.nsamples, ctx.seed, f0=f0.reshape(-1), grad_albedo=g)
-        shape = ax.shape
-        return (gx.reshape(shape), gy.reshape(shape), gt.reshape(shape), None, None, None, None)
+        jx, jy, jt = ctx.saved_tensors
+        g = grad_a.to(torch.float32)
+        return (g * jx if ctx.needs_input_grad[0] else None,
+                g * jy if ctx.needs_input_grad[1] else None,
+                g * jt if ctx.needs_input_grad[2] else None, None, None, None, None)
 
 
 def albedo(ax, ay, theta_o, phi_o, f0, nsamples, seed):

@@ -135,10 +135,15 @@ __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t
 // ---------------------------------------------------------------------------
 // Uniform-N kernels (one cell per group of `cpc` consecutive blocks).
 // ---------------------------------------------------------------------------
+// MODE 0: two sums (G2/G1 and G2/G1 (1 - wo.h)^5) for albedo_estimate;
+// MODE 1: one sum of F G2/G1 with the cell's F0.
+template <int MODE>
 __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
-    const float* __restrict__ ax, const float* __restrict__ ay, uint64_t nsamples, int32_t cpc,
-    uint32_t unit_base, uint32_t k0, uint32_t k1, float* __restrict__ partial) {
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
+    uint64_t nsamples, int32_t cpc, uint32_t unit_base, uint32_t k0, uint32_t k1,
+    float* __restrict__ partial) {
+    constexpr int NACC = MODE == 0 ? 2 : 1;
     const int64_t b = blockIdx.x;
     const int64_t cell = b / cpc;
     const int64_t chunk = b - cell * cpc;
@@ -149,10 +154,21 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
     const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
     if (c.ok)
         pairs_fwd<kLutBlock>(c, pbeg, pend, nsamples, unit_base + (uint32_t)cell, k0, k1, acc);
-    block_reduce_store<2, kLutBlock>(acc, partial + b * 4);
+    if (MODE == 0) {
+        block_reduce_store<2, kLutBlock>(acc, partial + b * 2 * NACC);
+    } else {
+        // A(F0) = F0 S1 + (1 - F0) S5, folded per lane
+        const float f0 = f0p ? f0p[cell] : 1.0f;
+        const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
+        Comp w[1] = {Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f}};
+        block_reduce_store<1, kLutBlock>(w, partial + b * 2 * NACC);
+    }
 }
 
-__global__ __launch_bounds__(kLutBlock) void k_albedo_bwd(
+// Adjoint of A(F0); WITH_VALUE also reduces the value itself (4 sums: A,
+// dA/d alpha_x, dA/d alpha_y, dA/d theta_o), otherwise the 3 gradient sums.
+template <bool WITH_VALUE>
+__global__ __launch_bounds__(kLutBlock) void k_albedo_adj(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
     uint64_t nsamples, int32_t cpc, uint32_t unit_base, uint32_t k0, uint32_t k1,
@@ -168,8 +184,12 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_bwd(
     const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
     if (c.ok)
         pairs_adj<kLutBlock>(c, f0, pbeg, pend, nsamples, unit_base + (uint32_t)cell, k0, k1, out);
-    Comp g[3] = {out[1], out[2], out[3]};
-    block_reduce_store<3, kLutBlock>(g, partial + b * 6);
+    if (WITH_VALUE) {
+        block_reduce_store<4, kLutBlock>(out, partial + b * 8);
+    } else {
+        Comp g[3] = {out[1], out[2], out[3]};
+        block_reduce_store<3, kLutBlock>(g, partial + b * 6);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -248,17 +268,6 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(
     for (int a = 0; a < NACC; ++a) outs[a][u] = (r[a].s + r[a].c) * sc;
 }
 
-// albedo[j] = F0 s1[j] + (1 - F0) s5[j] (per-request baseline only).
-__global__ __launch_bounds__(kFinishBlock) void k_combine_f0(int64_t n, const float* __restrict__ s1,
-                                                             const float* __restrict__ s5,
-                                                             const float* __restrict__ f0p,
-                                                             float* __restrict__ out) {
-    const int64_t j = (int64_t)blockIdx.x * kFinishBlock + threadIdx.x;
-    if (j >= n) return;
-    const float f0 = f0p ? f0p[j] : 1.0f;
-    out[j] = __builtin_fmaf(f0, s1[j], (1.0f - f0) * s5[j]);
-}
-
 inline unsigned finish_grid(int64_t n) { return (unsigned)((n + kFinishBlock - 1) / kFinishBlock); }
 
 inline int64_t lut_chunks_per_cell(int64_t nsamples) {
@@ -293,9 +302,10 @@ size_t lut_workspace(int64_t ncells, int64_t nsamples, int nacc) {
 
 using namespace capvndf;
 
-extern "C" size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t with_grad) {
+extern "C" size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t mode) {
     if (ncells < 0 || nsamples < 0 || nsamples >= ((int64_t)1 << 40)) return 0;
-    return lut_workspace(ncells, nsamples, with_grad ? 3 : 2);
+    if (mode < 0 || mode > 2) return 0;
+    return lut_workspace(ncells, nsamples, mode == 0 ? 2 : (mode == 1 ? 3 : 4));
 }
 
 extern "C" int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy,
@@ -316,9 +326,9 @@ extern "C" int32_t albedo_estimate(int64_t ncells, const float* wox, const float
     const int64_t cpc = lut_chunks_per_cell(nsamples);
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
-    hipLaunchKernelGGL(k_albedo_fwd, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox,
-                       woy, woz, ax, ay, (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed),
-                       key_hi(seed), part);
+    hipLaunchKernelGGL(k_albedo_fwd<0>, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox,
+                       woy, woz, ax, ay, nullptr, (uint64_t)nsamples, (int32_t)cpc, 0u,
+                       key_lo(seed), key_hi(seed), part);
     if (int32_t rc = check_launch("albedo_estimate launch")) return rc;
     hipLaunchKernelGGL(k_finish<2>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
                        part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr, s_f1,
@@ -352,14 +362,65 @@ extern "C" int32_t albedo_estimate_backward(int64_t ncells, const float* wox, co
     const int64_t cpc = lut_chunks_per_cell(nsamples);
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
-    hipLaunchKernelGGL(k_albedo_bwd, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox,
-                       woy, woz, ax, ay, f0, (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed),
-                       key_hi(seed), part);
+    hipLaunchKernelGGL(k_albedo_adj<false>, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st,
+                       wox, woy, woz, ax, ay, f0, (uint64_t)nsamples, (int32_t)cpc, 0u,
+                       key_lo(seed), key_hi(seed), part);
     if (int32_t rc = check_launch("albedo_estimate_backward launch")) return rc;
     hipLaunchKernelGGL(k_finish<3>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
                        part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, grad_albedo,
                        grad_ax, grad_ay, grad_theta_o, nullptr);
     return check_launch("albedo_estimate_backward finish launch");
+}
+
+extern "C" int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy,
+                                         const float* woz, const float* ax, const float* ay,
+                                         int64_t nsamples, uint64_t seed, const float* f0,
+                                         float* albedo, float* grad_ax, float* grad_ay,
+                                         float* grad_theta_o, void* workspace,
+                                         size_t workspace_bytes, void* stream) {
+    if (int32_t rc = check_cells("albedo_value_and_grad", ncells, nsamples, wox, woy, woz, ax, ay))
+        return rc;
+    if (ncells == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(albedo, "albedo")) return rc;
+    const int ngrad = (grad_ax != nullptr) + (grad_ay != nullptr) + (grad_theta_o != nullptr);
+    if (ngrad != 0 && ngrad != 3)
+        return fail(CAPVNDF_ERR_NULL_PTR,
+                    "albedo_value_and_grad: give all three gradient outputs or none");
+    const bool grad = ngrad == 3;
+    if (grad) {
+        if (int32_t rc = check_array(grad_ax, "grad_ax")) return rc;
+        if (int32_t rc = check_array(grad_ay, "grad_ay")) return rc;
+        if (int32_t rc = check_array(grad_theta_o, "grad_theta_o")) return rc;
+    }
+    if (f0 != nullptr)
+        if (int32_t rc = check_array(f0, "f0")) return rc;
+    const size_t need = lut_workspace(ncells, nsamples, grad ? 4 : 1);
+    if (workspace_bytes < need || workspace == nullptr)
+        return fail(CAPVNDF_ERR_WORKSPACE,
+                    "albedo_value_and_grad: workspace of %zu bytes needed, %zu given", need,
+                    workspace == nullptr ? (size_t)0 : workspace_bytes);
+    if (!aligned_to(workspace, 16))
+        return fail(CAPVNDF_ERR_MISALIGNED, "albedo_value_and_grad: workspace must be 16-byte aligned");
+    const int64_t cpc = lut_chunks_per_cell(nsamples);
+    const hipStream_t st = as_stream(stream);
+    float* part = static_cast<float*>(workspace);
+    const dim3 grid((unsigned)(ncells * cpc)), block(kLutBlock);
+    if (grad) {
+        hipLaunchKernelGGL(k_albedo_adj<true>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
+                           (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed), key_hi(seed), part);
+        if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
+        hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                           part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr,
+                           albedo, grad_ax, grad_ay, grad_theta_o);
+    } else {
+        hipLaunchKernelGGL(k_albedo_fwd<1>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
+                           (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed), key_hi(seed), part);
+        if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
+        hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                           part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr,
+                           albedo, nullptr, nullptr, nullptr);
+    }
+    return check_launch("albedo_value_and_grad finish launch");
 }
 
 // ===========================================================================
@@ -385,9 +446,7 @@ struct capvndf_batch_plan {
     int32_t* d_job_chunks = nullptr;
     int64_t* d_nsamp = nullptr;
     float* d_partial = nullptr;
-    float* d_s1 = nullptr;  // per-request baseline scratch
-    float* d_s5 = nullptr;
-    float* d_req_ws = nullptr;
+    float* d_req_ws = nullptr;  // per-request baseline scratch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -589,9 +648,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     const size_t o_jc = carve(sizeof(int32_t) * (size_t)(njobs + 1));
     const size_t o_ns = carve(sizeof(int64_t) * (size_t)njobs);
     const size_t o_pa = carve(sizeof(float) * 2 * nacc * (size_t)std::max<int64_t>(nchunks, 1));
-    const size_t o_s1 = carve(sizeof(float) * (size_t)njobs);
-    const size_t o_s5 = carve(sizeof(float) * (size_t)njobs);
-    const size_t o_rw = carve(sizeof(float) * 6 * (size_t)max_cpc);
+    const size_t o_rw = carve(sizeof(float) * 8 * (size_t)max_cpc);
     capvndf_batch_plan* p = new capvndf_batch_plan();
     if (int32_t rc = check_hip(hipMalloc(&p->dmem, off), "hipMalloc (batch plan)")) {
         p->dmem = nullptr;
@@ -606,8 +663,6 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     p->d_job_chunks = reinterpret_cast<int32_t*>(base + o_jc);
     p->d_nsamp = reinterpret_cast<int64_t*>(base + o_ns);
     p->d_partial = reinterpret_cast<float*>(base + o_pa);
-    p->d_s1 = reinterpret_cast<float*>(base + o_s1);
-    p->d_s5 = reinterpret_cast<float*>(base + o_s5);
     p->d_req_ws = reinterpret_cast<float*>(base + o_rw);
     int32_t rc = CAPVNDF_OK;
     if (nchunks > 0) {
@@ -685,24 +740,23 @@ extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* str
     for (int64_t j = 0; j < p->njobs; ++j) {
         const int64_t n = p->nsamp_host[j];
         const int64_t cpc = lut_chunks_per_cell(n);
-        hipLaunchKernelGGL(k_albedo_fwd, dim3((unsigned)cpc), dim3(kLutBlock), 0, st, p->wox + j,
-                           p->woy + j, p->woz + j, p->ax + j, p->ay + j, (uint64_t)n, (int32_t)cpc,
-                           (uint32_t)j, k0, k1, p->d_req_ws);
-        hipLaunchKernelGGL(k_finish<2>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1, p->d_req_ws,
-                           (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr, p->d_s1 + j,
-                           p->d_s5 + j, nullptr, nullptr);
+        const float* f0 = p->f0 ? p->f0 + j : nullptr;
         if (p->with_grad) {
-            hipLaunchKernelGGL(k_albedo_bwd, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
-                               p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j,
-                               p->f0 ? p->f0 + j : nullptr, (uint64_t)n, (int32_t)cpc, (uint32_t)j,
-                               k0, k1, p->d_req_ws);
-            hipLaunchKernelGGL(k_finish<3>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
+            hipLaunchKernelGGL(k_albedo_adj<true>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
+                               p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
+                               (uint64_t)n, (int32_t)cpc, (uint32_t)j, k0, k1, p->d_req_ws);
+            hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
                                p->d_req_ws, (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr,
-                               p->gax + j, p->gay + j, p->gth + j, nullptr);
+                               p->albedo + j, p->gax + j, p->gay + j, p->gth + j);
+        } else {
+            hipLaunchKernelGGL(k_albedo_fwd<1>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
+                               p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
+                               (uint64_t)n, (int32_t)cpc, (uint32_t)j, k0, k1, p->d_req_ws);
+            hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
+                               p->d_req_ws, (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr,
+                               p->albedo + j, nullptr, nullptr, nullptr);
         }
     }
-    hipLaunchKernelGGL(k_combine_f0, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
-                       p->njobs, p->d_s1, p->d_s5, p->f0, p->albedo);
     return check_launch("albedo_batch_run_per_request launch");
 }
 

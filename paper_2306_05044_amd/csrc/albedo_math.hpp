@@ -8,7 +8,9 @@
 // cos theta_l), D and the cosines cancel: weight = F(wo.h) G2 / G1(wo), and
 // for the height-correlated G2 = Go Gl / (Go + Gl - Go Gl) this is
 // F Gl / (Go + Gl (1 - Go)).  In the hemisphere space G1(w) = 2 zs / (1 + zs)
-// with zs the z of M^-1 w / |M^-1 w|.
+// with zs the z of M^-1 w / |M^-1 w|.  Writing Gl this way and multiplying
+// through by m = |M^-1 wl| gives the form evaluated here, with one division:
+//   g = G2 / G1(wo) = 2 wl_z / (Go m + (2 - Go) wl_z).
 #pragma once
 
 #include "device_math.hpp"
@@ -21,6 +23,7 @@ struct CellConst {
     float ax, ay;
     Stretched s;       // stretched view direction
     float go;          // G1(wo)
+    float tgo;         // 2 - G1(wo)
     float tx, ty, tz;  // meridian tangent dwo/dtheta_o
     bool ok;           // inside the domain
 };
@@ -39,6 +42,7 @@ __device__ __forceinline__ CellConst cell_setup(float wx, float wy, float wz, fl
     c.ay = ay;
     c.s = stretch(c.ox, c.oy, c.oz, ax, ay);
     c.go = 2.0f * c.s.zs * rcp(c.s.opz);
+    c.tgo = 2.0f - c.go;
     const float rho2 = __builtin_fmaf(c.ox, c.ox, c.oy * c.oy);
     if (rho2 > 0.0f) {
         const float ir = rsq(rho2);
@@ -65,16 +69,13 @@ __device__ __forceinline__ FwdTerm albedo_fwd(const CellConst& c, float u1, floa
     const float wly = __builtin_fmaf(x2, n.hy, -c.oy);
     const float wlz = __builtin_fmaf(x2, n.hz, -c.oz);
     const float plx = c.ax * wlx, ply = c.ay * wly;
-    const float m2 = __builtin_fmaf(plx, plx, __builtin_fmaf(ply, ply, wlz * wlz));
-    const float zl = wlz * rsq(m2);
-    const float gl = 2.0f * zl * rcp(1.0f + zl);
-    const float den = __builtin_fmaf(gl, 1.0f - c.go, c.go);
-    const float g = gl * rcp(den);
-    const float m = 1.0f - x;
-    const float mm = m * m;
+    const float m = fsqrt(__builtin_fmaf(plx, plx, __builtin_fmaf(ply, ply, wlz * wlz)));
+    const float g = 2.0f * wlz * rcp(__builtin_fmaf(c.go, m, c.tgo * wlz));
+    const float mx = 1.0f - x;
+    const float mm = mx * mx;
     FwdTerm r;
     r.g = wlz > 0.0f ? g : 0.0f;
-    r.m5 = mm * mm * m;
+    r.m5 = mm * mm * mx;
     return r;
 }
 
@@ -109,27 +110,27 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     const float wlz = __builtin_fmaf(x2, hz, -c.oz);
     const float plx = c.ax * wlx, ply = c.ay * wly;
     const float pp = __builtin_fmaf(plx, plx, ply * ply);
-    const float im = rsq(__builtin_fmaf(wlz, wlz, pp));
-    const float zl = wlz * im;
-    const float i1z = rcp(1.0f + zl);
-    const float gl = 2.0f * zl * i1z;
-    const float omg = 1.0f - c.go;
-    const float ig = rcp(__builtin_fmaf(gl, omg, c.go));
-    const float g = gl * ig;
-    const float m = 1.0f - x;
-    const float mm = m * m;
+    const float m2 = __builtin_fmaf(wlz, wlz, pp);
+    const float im = rsq(m2);
+    const float ml = m2 * im;  // |M^-1 wl|
+    const float iD = rcp(__builtin_fmaf(c.go, ml, c.tgo * wlz));
+    const float g = 2.0f * wlz * iD;
+    const float mx = 1.0f - x;
+    const float mm = mx * mx;
     const float m4 = mm * mm;
     const float f1 = 1.0f - f0;
-    const float F = __builtin_fmaf(f1, m4 * m, f0);
+    const float F = __builtin_fmaf(f1, m4 * mx, f0);
 
-    // reverse sweep, seeded with dw = 1
-    float dx = -5.0f * f1 * m4 * g;                            // through F(x)
-    const float dgl = F * ig * __builtin_fmaf(-g, omg, 1.0f);  // dg/dGl = Go / den^2
-    const float dgo = -F * g * ig * (1.0f - gl);               // dg/dGo
-    const float e = dgl * 2.0f * i1z * i1z * im * im * im;     // dzl * |pl|^-3
-    const float dwlz = e * pp;
+    // reverse sweep, seeded with dw = 1; g = 2 wl_z / D, D = Go m + (2 - Go) wl_z:
+    // dg/dwl_z = 2 Go m / D^2, dg/dm = -2 Go wl_z / D^2, dg/dGo = -2 wl_z (m - wl_z) / D^2,
+    // and m = |(plx, ply, wl_z)|.
+    float dx = -5.0f * f1 * m4 * g;              // through F(x)
+    const float t2 = 2.0f * iD * iD;
+    const float e = F * t2 * c.go * im;          // F dg/dm / m, up to the sign
+    const float dwlz = e * pp;                   // F (dg/dwl_z + dg/dm wl_z / m)
     const float ew = -e * wlz;
     const float dplx = ew * plx, dply = ew * ply;
+    const float dgo = -F * t2 * wlz * (ml - wlz);
     float dax = dplx * wlx;
     float day = dply * wly;
     const float dwlx = dplx * c.ax, dwly = dply * c.ay;

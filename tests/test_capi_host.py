@@ -83,6 +83,8 @@ def test_albedo_argument_errors(lib):
     assert lib.albedo_workspace_size(4096, 1 << 20, 0) == 4096 * 64 * 2 * 2 * 4
     assert lib.albedo_workspace_size(4096, 1 << 20, 1) == 4096 * 64 * 3 * 2 * 4
     assert lib.albedo_workspace_size(3, 1, 0) == 3 * 1 * 2 * 2 * 4
+    assert lib.albedo_workspace_size(4096, 1 << 20, 2) == 4096 * 64 * 4 * 2 * 4
+    assert lib.albedo_workspace_size(16, 1 << 20, 3) == 0
     five = [fake] * 5
     assert lib.albedo_estimate(-1, *five, 10, 0, fake, fake, fake, 1 << 20, None) == -2
     assert lib.albedo_estimate(4, *five, -3, 0, fake, fake, fake, 1 << 20, None) == -2
@@ -93,6 +95,13 @@ def test_albedo_argument_errors(lib):
     assert lib.albedo_estimate(0, *[None] * 5, 100, 0, None, None, None, 0, None) == 0
     assert lib.albedo_estimate_backward(4, *five, 100, 0, None, None, fake, fake, fake, fake, 8,
                                         None) == -5
+    # value_and_grad: partial gradient outputs, small workspace
+    assert lib.albedo_value_and_grad(4, *five, 100, 0, None, fake, fake, None, None, fake,
+                                     1 << 20, None) == -1
+    assert lib.albedo_value_and_grad(4, *five, 100, 0, None, fake, fake, fake, fake, fake, 8,
+                                     None) == -5
+    assert lib.albedo_value_and_grad(4, *five, 100, 0, None, None, None, None, None, fake, 1 << 20,
+                                     None) == -1
     out = P()
     ns = (ctypes.c_int64 * 2)(10, 20)
     assert lib.albedo_batch_plan_create(0, *five, None, ns, 0, 1, fake, fake, fake, fake, None,

@@ -128,6 +128,31 @@ def test_backward_full_size_sampled():
     _check_grad(host(gt)[cells], rt, "full d/d theta_o")
 
 
+@pytest.mark.parametrize("n", [1 << 12, 4097, 1])
+def test_value_and_grad(n):
+    g = _grad_cells(8, seed=13)
+    t = to_dev(g)
+    f0 = np.where(np.arange(64) % 3 == 0, 0.04, 1.0).astype(np.float32)
+    gf = torch.from_numpy(f0).cuda()
+    a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 6,
+                                             f0=gf)
+    A, rx, ry, rt = oracle.albedo_grad((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], n, 6, f0=f0)
+    assert np.abs(host(a) - A).max() <= ATOL_A
+    _check_grad(host(gx), rx, "value_and_grad alpha_x")
+    _check_grad(host(gy), ry, "value_and_grad alpha_y")
+    _check_grad(host(gt), rt, "value_and_grad theta_o")
+    # value only: same value bits as the F0 combination of one stream
+    a2, n1, n2, n3 = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 6,
+                                              f0=gf, with_grad=False)
+    assert n1 is None and n2 is None and n3 is None
+    assert np.abs(host(a2) - A).max() <= ATOL_A
+    # the backward entry point gives the same gradients (different summation order)
+    bx, by, bt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 6,
+                                             f0=gf)
+    for u, v in ((gx, bx), (gy, by), (gt, bt)):
+        assert torch.allclose(u, v, rtol=1e-5, atol=1e-6)
+
+
 def test_autograd_function():
     gg = workloads.grad_grid(6, seed=11)
     ax = torch.from_numpy(gg["ax"]).cuda().requires_grad_(True)
