@@ -25,6 +25,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# A test may point the wrapper at another build of the oracle (the mutation
+# test builds deliberately broken copies and checks that the pins fail).
+_LIB_OVERRIDE = os.environ.get("CAPVNDF_ORACLE_LIB")
+# Thread count used when a call passes nthreads=0 (0 = all hardware threads).
+_THREADS = int(os.environ.get("CAPVNDF_ORACLE_THREADS", "0"))
 
 TAG_SAMPLE = 2
 TAG_ALBEDO = 3
@@ -55,9 +60,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build()
-    lib = ctypes.CDLL(_LIB)
+    if _LIB_OVERRIDE:
+        lib = ctypes.CDLL(_LIB_OVERRIDE)
+    else:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
     lib.orc_philox4x32_10.argtypes = [_u32, _u32, _u32]
     lib.orc_philox4x32_10.restype = None
     lib.orc_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
@@ -104,6 +112,10 @@ def _f64(a, n=None):
     if n is not None:
         a = np.broadcast_to(a, (n,)).copy() if a.ndim == 0 or a.shape != (n,) else a
     return a
+
+
+def _nt(nthreads):
+    return nthreads if nthreads else _THREADS
 
 
 def _p(a):
@@ -163,7 +175,7 @@ def vndf_sample(wi, ax, ay, u1=None, u2=None, seed=0, index_base=0, method=CAP,
     pdf = np.zeros(n)
     rc = _load().orc_vndf_sample(n, *[_p(c) for c in wi], _p(ax), _p(ay), _p(u1), _p(u2),
                                  seed, index_base, method, *[_p(c) for c in h], _p(pdf),
-                                 nthreads)
+                                 _nt(nthreads))
     if rc != 0:
         raise ValueError("orc_vndf_sample failed")
     return np.stack(h, axis=-1), pdf
@@ -178,7 +190,7 @@ def vndf_pdf(wi, h, ax, ay, nthreads=0):
     ay = _f64(ay, n)
     pdf = np.zeros(n)
     rc = _load().orc_vndf_pdf(n, *[_p(c) for c in wi], *[_p(c) for c in h], _p(ax), _p(ay),
-                              _p(pdf), nthreads)
+                              _p(pdf), _nt(nthreads))
     if rc != 0:
         raise ValueError("orc_vndf_pdf failed")
     return pdf
@@ -245,7 +257,7 @@ def albedo(wo, ax, ay, nsamples, seed, f0=1.0, units=None, method=CAP, nthreads=
     out = np.zeros(n)
     rc = _load().orc_albedo(n, *[_p(c) for c in wo], _p(ax), _p(ay), ns.ctypes.data_as(_i64),
                             None if un is None else un.ctypes.data_as(_u32), seed, _p(f0),
-                            method, _p(out), nthreads)
+                            method, _p(out), _nt(nthreads))
     if rc != 0:
         raise ValueError("orc_albedo failed")
     return out
@@ -258,7 +270,7 @@ def albedo_grad(wo, ax, ay, nsamples, seed, f0=1.0, units=None, nthreads=0):
     rc = _load().orc_albedo_grad(n, *[_p(c) for c in wo], _p(ax), _p(ay),
                                  ns.ctypes.data_as(_i64),
                                  None if un is None else un.ctypes.data_as(_u32), seed,
-                                 _p(f0), *[_p(c) for c in outs], nthreads)
+                                 _p(f0), *[_p(c) for c in outs], _nt(nthreads))
     if rc != 0:
         raise ValueError("orc_albedo_grad failed")
     return tuple(outs)
@@ -271,7 +283,7 @@ def albedo_fd(wo, ax, ay, nsamples, seed, f0=1.0, step=1e-4, units=None, nthread
     rc = _load().orc_albedo_fd(n, *[_p(c) for c in wo], _p(ax), _p(ay),
                                ns.ctypes.data_as(_i64),
                                None if un is None else un.ctypes.data_as(_u32), seed,
-                               _p(f0), float(step), *[_p(c) for c in outs], nthreads)
+                               _p(f0), float(step), *[_p(c) for c in outs], _nt(nthreads))
     if rc != 0:
         raise ValueError("orc_albedo_fd failed")
     return tuple(outs)

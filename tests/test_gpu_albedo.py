@@ -153,6 +153,27 @@ def test_value_and_grad(n):
         assert torch.allclose(u, v, rtol=1e-5, atol=1e-6)
 
 
+def test_backward_vs_central_differences():
+    """The configuration's check against FP64 central differences with step
+    1e-4: the GPU gradient must sit as close to FD(1e-4) as the exact
+    (dual-number) gradient does, plus the parity tolerance.  (FD(1e-4) itself
+    is off by up to ~1e-3 where samples cross the horizon within the step.)"""
+    g = _grad_cells(32)
+    rng = np.random.default_rng(2)
+    cells = rng.choice(1024, 16, replace=False)
+    sub = {k: v[cells] for k, v in g.items()}
+    t = to_dev(sub)
+    n = 1 << 14
+    # the GPU entry point takes cells 0..15 as units 0..15, so compare on those units
+    gx, gy, gt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
+    wo = (sub["wx"], sub["wy"], sub["wz"])
+    _, rx, ry, rt = oracle.albedo_grad(wo, sub["ax"], sub["ay"], n, 3)
+    fd = oracle.albedo_fd(wo, sub["ax"], sub["ay"], n, 3, step=1e-4)
+    for got, exact, f in zip((gx, gy, gt), (rx, ry, rt), fd):
+        gap = np.abs(exact - f)
+        assert np.all(np.abs(host(got) - f) <= gap + 1e-4 + 1e-3 * np.abs(exact))
+
+
 def test_autograd_function():
     gg = workloads.grad_grid(6, seed=11)
     ax = torch.from_numpy(gg["ax"]).cuda().requires_grad_(True)
