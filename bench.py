@@ -86,6 +86,31 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def alu_roofline(kind, samples, ms):
+    """VALU roofline of an estimator kernel: lane-instructions per sample from
+    the committed counter summary (if taken on the current sources) times the
+    samples of one launch, over its launch time, against 256 CUs x 128 FP32
+    lanes/clock x 2.4 GHz."""
+    path = os.path.join(ROOT, "profiles", "albedo_valu_counters.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for name in ("albedo.hip", "albedo_math.hpp", "device_math.hpp"):
+        with open(os.path.join(ROOT, "paper_2306_05044_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("source_digest") != h.hexdigest()[:16]:
+        return None
+    ips = rec["valu_lane_instr_per_sample"][kind]
+    peak = rec["peak_lane_instr_per_s"] / 1e12
+    achieved = ips * samples / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
+            "unit": "T VALU lane-instr/s", "frac": round(achieved / peak, 4),
+            "lane_instr_per_sample": round(ips, 1)}
+
+
 def cpu_baseline(d):
     """FP64 oracle on the host cores: the full 2^26-tuple workload of the
     streaming configuration (cap sampler + pdf, Philox uniforms)."""
@@ -217,7 +242,9 @@ def main():
             "bwd_gsamples_per_s": round(samples / ms_b / 1e6, 2),
             "fwd_bwd_gsamples_per_s": round(samples / ms_vg / 1e6, 2),
             "max_abs_err_vs_oracle": float(f"{err:.3e}"),
-            "err_checked_cells": int(len(cells))}
+            "err_checked_cells": int(len(cells)),
+            "roofline_fwd": alu_roofline("forward_two_sums", samples, ms_f),
+            "roofline_fwd_bwd": alu_roofline("value_and_grad", samples, ms_vg)}
         del c, ws
     if "grad" in only:
         log("differentiable albedo 32 x 32 x 2^18 through the autograd Function")
@@ -237,12 +264,20 @@ def main():
         out["albedo_grad"] = {"cells": 1024, "samples_per_cell": 1 << 18,
                               "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4)}
     if "batch" in only:
-        log("batched estimator: 4096 uneven jobs, forward + adjoint")
+        log("batched estimator: 4096 uneven jobs, forward + adjoint (autotuned tiling)")
         j = workloads.batch_jobs(4096, seed=4)
         c = {k: torch.from_numpy(v).to(dev) for k, v in j.items() if k != "n"}
-        plan = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
-                            with_grad=True)
+        t0 = time.perf_counter()
+        best, best_ms = cv.albedo_batch_autotune(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"],
+                                                 j["n"], 4, with_grad=True)
+        tune_s = time.perf_counter() - t0
         steps = max(3, args.steps // 10)
+        plan0 = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
+                             with_grad=True, tiling=(256, 32, 8))
+        ms_default, _ = timed(plan0.run, steps, 2)
+        plan0.close()
+        plan = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
+                            with_grad=True, tiling=best)
         ms_b, _ = timed(plan.run, steps, 2)
         ref = [o.clone() for o in (plan.albedo, plan.grad_ax)]
         ms_r, _ = timed(plan.run_per_request, max(2, steps // 2), 1)
@@ -252,6 +287,8 @@ def main():
                           "tiling": info["tiling"], "chunks": info["nchunks"],
                           "graph_ms": round(ms_b, 4), "per_request_ms": round(ms_r, 4),
                           "speedup": round(ms_r / ms_b, 3),
+                          "default_tiling_ms": round(ms_default, 4),
+                          "autotune_s": round(tune_s, 2),
                           "gsamples_per_s_fwd_adj": round(info["total_samples"] / ms_b / 1e6, 2),
                           "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}")}
         plan.close()
