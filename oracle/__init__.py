@@ -101,6 +101,11 @@ def _load():
                                   ctypes.c_uint64, _d, ctypes.c_double, _d, _d, _d,
                                   ctypes.c_int32]
     lib.orc_albedo_fd.restype = ctypes.c_int32
+    lib.orc_radiance.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _d, _i64, _u32,
+                                 ctypes.c_uint64, _d, ctypes.c_int32, _d, ctypes.c_int32]
+    lib.orc_radiance.restype = ctypes.c_int32
+    lib.orc_radiance_at.argtypes = [ctypes.c_int64, _d, _d, _d, _d, ctypes.c_int32, _d]
+    lib.orc_radiance_at.restype = None
     lib.orc_hardware_threads.argtypes = []
     lib.orc_hardware_threads.restype = ctypes.c_int32
     _lib = lib
@@ -287,3 +292,34 @@ def albedo_fd(wo, ax, ay, nsamples, seed, f0=1.0, step=1e-4, units=None, nthread
     if rc != 0:
         raise ValueError("orc_albedo_fd failed")
     return tuple(outs)
+
+
+def _lobes(lobes):
+    lb = np.ascontiguousarray(np.asarray(lobes, dtype=np.float64).reshape(-1, 5))
+    return lb, lb.shape[0]
+
+
+def radiance_at(w, lobes):
+    """Synthetic radiance L(w) = sum_k lambda_k exp(kappa_k (mu_k . w - 1)) at unit w;
+    lobes is an array of rows (mu_x, mu_y, mu_z, kappa, lambda)."""
+    w = [_f64(c) for c in w]
+    n = w[0].shape[0]
+    lb, k = _lobes(lobes)
+    out = np.zeros(n)
+    _load().orc_radiance_at(n, *[_p(c) for c in w], _p(lb), k, _p(out))
+    return out
+
+
+def radiance(wo, ax, ay, nsamples, seed, lobes, f0=1.0, units=None, nthreads=0):
+    """Direct illumination per cell (Appendix A estimator with the lobe
+    radiance), over the Philox stream (seed, tag 3, unit = units[c] or c)."""
+    wo, n, ax, ay, ns, un, f0 = _cells(wo, ax, ay, nsamples, units, f0)
+    lb, k = _lobes(lobes)
+    out = np.zeros(n)
+    rc = _load().orc_radiance(n, *[_p(c) for c in wo], _p(ax), _p(ay), _p(f0),
+                              ns.ctypes.data_as(_i64),
+                              None if un is None else un.ctypes.data_as(_u32), seed, _p(lb), k,
+                              _p(out), _nt(nthreads))
+    if rc != 0:
+        raise ValueError("orc_radiance failed")
+    return out

@@ -22,7 +22,9 @@
 //     (directional albedo), weight f_r |cos theta_b| / PDF evaluated
 //     literally (no algebraic simplification);
 //   * its gradient by forward-mode dual numbers (exact derivative of this
-//     same program) and by central finite differences.
+//     same program) and by central finite differences;
+//   * the same estimator with a non-constant incident radiance (a sum of
+//     spherical-Gaussian lobes), i.e. the direct-illumination integral.
 //
 // Readings where the paper is silent (each also listed in the design doc):
 //   * u1 drives the azimuth and u2 the height, exactly as the cap listing.
@@ -389,6 +391,35 @@ double cell_albedo(const Vec3<double>& wo, double ax, double ay, int64_t n, uint
     return acc.result() / (double)n;
 }
 
+// Synthetic incident radiance: a sum of spherical-Gaussian lobes,
+// L(w) = sum_k lambda_k exp(kappa_k (mu_k . w - 1)) for unit w (a lobe with
+// kappa = 0 is a constant term).  Lobe k is params[5k .. 5k+4] =
+// (mu_x, mu_y, mu_z, kappa, lambda) with mu unit.
+double radiance(const Vec3<double>& w, const double* params, int nlobes) {
+    double l = 0.0;
+    for (int k = 0; k < nlobes; ++k) {
+        const double* p = params + 5 * k;
+        const double c = p[0] * w.x + p[1] * w.y + p[2] * w.z;
+        l += p[4] * std::exp(p[3] * (c - 1.0));
+    }
+    return l;
+}
+
+// One term of the direct-illumination estimator (Appendix A): sample wm from
+// the VNDF seen from wa, reflect, and return L(wb) f_r(wb, wa) |cos theta_b| /
+// PDF(wb, wa).
+double radiance_term(const Vec3<double>& wa, double ax, double ay, double u1, double u2,
+                     double f0, const double* params, int nlobes) {
+    Vec3<double> wm = sample_vndf(u1, u2, wa, ax, ay, 0);
+    double c = dot(wm, wa);
+    Vec3<double> wb{2.0 * c * wm.x - wa.x, 2.0 * c * wm.y - wa.y, 2.0 * c * wm.z - wa.z};
+    if (!(wb.z > 0.0)) return 0.0;
+    double fr = brdf_ggx(wa, wb, ax, ay, f0);
+    double pdf = smith_g1(wm, wa, ax, ay) * ggx_ndf(wm, ax, ay) / (4.0 * wa.z);
+    if (!(pdf > 0.0)) return 0.0;
+    return radiance(normalize(wb), params, nlobes) * fr * wb.z / pdf;
+}
+
 }  // namespace
 
 extern "C" {
@@ -572,6 +603,36 @@ int32_t orc_albedo_fd(int64_t ncells, const double* wox, const double* woy, cons
                       cell_albedo(at(theta - step), a, b, n, seed, unit, f0[c], 0)) / (2.0 * step);
     });
     return 0;
+}
+
+// Direct illumination per cell: (1/N) sum of radiance_term over the Philox
+// stream (seed, tag 3, unit = units[c] or c), Neumaier-summed.
+int32_t orc_radiance(int64_t ncells, const double* wox, const double* woy, const double* woz,
+                     const double* ax, const double* ay, const double* f0,
+                     const int64_t* nsamples, const uint32_t* units, uint64_t seed,
+                     const double* lobes, int32_t nlobes, double* out, int32_t nthreads) {
+    if (ncells < 0 || nlobes < 0) return -1;
+    parallel_for(ncells, nthreads, [&](int64_t c) {
+        uint32_t unit = units ? units[c] : (uint32_t)c;
+        out[c] = 0.0;
+        int64_t n = nsamples[c];
+        if (n <= 0 || !(woz[c] > 0.0) || !(ax[c] > 0.0) || !(ay[c] > 0.0)) return;
+        Vec3<double> wo = unit_view(wox[c], woy[c], woz[c]);
+        NeumaierSum<double> acc;
+        for (int64_t k = 0; k < n; ++k) {
+            double u1, u2;
+            stream_uniforms(seed, kTagAlbedo, unit, (uint64_t)k, &u1, &u2);
+            acc.add(radiance_term(wo, ax[c], ay[c], u1, u2, f0[c], lobes, nlobes));
+        }
+        out[c] = acc.result() / (double)n;
+    });
+    return 0;
+}
+
+// The radiance L(w) of the lobe set at n unit directions.
+void orc_radiance_at(int64_t n, const double* wx, const double* wy, const double* wz,
+                     const double* lobes, int32_t nlobes, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = radiance(Vec3<double>{wx[i], wy[i], wz[i]}, lobes, nlobes);
 }
 
 int32_t orc_hardware_threads(void) {

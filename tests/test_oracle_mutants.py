@@ -17,7 +17,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_sampler.py", "tests/test_oracle_pdf.py",
-        "tests/test_oracle_albedo.py"]
+        "tests/test_oracle_albedo.py", "tests/test_oracle_radiance.py"]
 
 # (name, text in oracle.cpp, replacement)
 MUTANTS = [
@@ -52,6 +52,9 @@ MUTANTS = [
      "return Vec3<double>{wo.z * wo.x / rho, wo.z * wo.y / rho, rho};"),
     ("disk warp weight", "T s = (T(1.0) + wi.z) / 2.0;", "T s = (T(1.0) - wi.z) / 2.0;"),
     ("disk basis", "w1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};", "w1 = Vec3<T>{wi.y * inv, wi.x * inv, T(0.0)};"),
+    ("lobe exponent", "l += p[4] * std::exp(p[3] * (c - 1.0));", "l += p[4] * std::exp(p[3] * (1.0 - c));"),
+    ("radiance at the view", "return radiance(normalize(wb), params, nlobes) * fr * wb.z / pdf;",
+     "return radiance(wa, params, nlobes) * fr * wb.z / pdf;"),
 ]
 
 
