@@ -28,7 +28,7 @@ METRIC = ("Gsamples/s VNDF (cap vs 2018 disk) + albedo-LUT fwd+bwd time at "
 N_STREAM = 1 << 26
 BYTES_PER_SAMPLE = 36  # 5 FP32 inputs read + 4 FP32 outputs written
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("stream", "disk", "probe", "micro", "lut", "grad", "batch")
+SECTIONS = ("stream", "disk", "probe", "micro", "lut", "grad", "batch", "radiance")
 
 
 def log(msg):
@@ -292,6 +292,34 @@ def main():
                           "gsamples_per_s_fwd_adj": round(info["total_samples"] / ms_b / 1e6, 2),
                           "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}")}
         plan.close()
+
+    if "radiance" in only:
+        import oracle
+        log("direct illumination 64 x 64 x 2^20 under 4 spherical-Gaussian lobes")
+        g = workloads.lut_grid(64, 64)
+        c = {k: torch.from_numpy(v).to(dev) for k, v in g.items()}
+        n = 1 << 20
+        lobes_np = np.array([[0.0, 0.0, 1.0, 4.0, 2.0], [0.6, 0.0, 0.8, 30.0, 5.0],
+                             [-0.5, 0.5, 0.70710678, 10.0, 1.5], [0.0, 0.0, 1.0, 0.0, 0.3]],
+                            dtype=np.float32)
+        lobes = torch.from_numpy(lobes_np).to(dev)
+        ws = torch.empty(cv.albedo_workspace_size(4096, n, 0) // 4 + 4, device=dev)
+
+        def rad():
+            return cv.radiance_estimate(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], n, 2, lobes,
+                                        workspace=ws)
+        ms_r, _ = timed(rad, max(3, args.steps // 10), 2)
+        r = rad()
+        torch.cuda.synchronize()
+        cells = np.array([5, 2900, 4095])
+        sub = {k: v[cells] for k, v in g.items()}
+        ref = oracle.radiance((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"], n, 2,
+                              lobes_np.astype(np.float64), units=cells)
+        out["direct_illumination"] = {
+            "cells": 4096, "samples_per_cell": n, "lobes": 4, "ms": round(ms_r, 4),
+            "gsamples_per_s": round(4096 * n / ms_r / 1e6, 2),
+            "max_abs_err_vs_oracle": float(f"{np.abs(r.cpu().numpy()[cells] - ref).max():.3e}"),
+            "err_checked_cells": int(len(cells))}
 
     result = {"metric": METRIC, "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",

@@ -188,6 +188,30 @@ int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy
                               void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * radiance_estimate -- direct illumination per cell: the Monte Carlo
+ * estimator of Appendix A ("Importance Sampling Using the GGX VNDF") with an
+ * incident radiance L(w_b) that is a sum of spherical-Gaussian lobes,
+ *   L(w) = sum_k lambda_k exp(kappa_k (mu_k . w - 1)),
+ * i.e. (1/N) sum F(wo.h) G2/G1 L(wl) over the same samples (Philox tag 3,
+ * unit = cell index) as albedo_estimate.  A constant radiance (kappa = 0)
+ * gives lambda times the albedo.
+ *
+ *   (cell inputs, nsamples, seed as albedo_estimate)
+ *   f0          [ncells] Fresnel F0 per cell (NULL = 1)
+ *   lobes       device FP32 [5 * nlobes]: (mu_x, mu_y, mu_z, kappa, lambda)
+ *               per lobe, mu unit, kappa >= 0 (the lobe's FP32 relative
+ *               error grows as kappa * 2^-24)
+ *   nlobes      0 .. 8 (0 gives zero radiance)
+ *   radiance    [ncells] out
+ *   workspace   albedo_workspace_size(ncells, nsamples, 0) bytes suffice
+ * Errors: as albedo_estimate; BAD_SIZE for nlobes outside [0, 8].
+ */
+int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy, const float* woz,
+                          const float* ax, const float* ay, const float* f0, int64_t nsamples,
+                          uint64_t seed, const float* lobes, int32_t nlobes, float* radiance,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/*
  * Batched estimation of many jobs with uneven sample counts (forward value
  * A_j(F0_j) plus, with with_grad, dA_j/d alpha_x, dA_j/d alpha_y and
  * dA_j/d theta_o), in one persistent launch plus a fixed-order finishing pass,

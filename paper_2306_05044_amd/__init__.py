@@ -8,7 +8,7 @@ no CPU fallback: without the built library every call raises.
 
 Names mirror the C entry points: ``vndf_sample``, ``vndf_pdf``,
 ``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_value_and_grad``,
-``albedo_workspace_size``,
+``albedo_workspace_size``, ``radiance_estimate``,
 ``BatchPlan`` (``albedo_batch_plan_create`` / ``albedo_batch_run`` /
 ``albedo_batch_run_per_request``), ``albedo_batch_autotune``, and the hooks
 ``capvndf_uniforms``, ``capvndf_philox_blocks``, ``vndf_microbench`` and
@@ -67,6 +67,8 @@ _SIGNATURES = {
                                   ctypes.c_size_t, _P], _I32),
     "albedo_value_and_grad": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, _P, _P, _P,
                                ctypes.c_size_t, _P], _I32),
+    "radiance_estimate": ([_I64, _P, _P, _P, _P, _P, _P, _I64, _U64, _P, _I32, _P, _P,
+                           ctypes.c_size_t, _P], _I32),
     "albedo_batch_plan_create": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _I32, _P, _P, _P, _P,
                                   ctypes.POINTER(Tiling), _P, ctypes.POINTER(_P)], _I32),
     "albedo_batch_run": ([_P, _P], _I32),
@@ -249,6 +251,27 @@ def albedo_value_and_grad(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_g
                                    _ptr(ws), ws.numel() * 4, _stream(stream))
     _check("albedo_value_and_grad", rc)
     return (a, *g)
+
+
+def radiance_estimate(wox, woy, woz, ax, ay, nsamples, seed, lobes, f0=None, workspace=None,
+                      stream=None):
+    """Direct illumination per cell under spherical-Gaussian lobes; lobes is a
+    float32 GPU tensor of shape (nlobes, 5): (mu_x, mu_y, mu_z, kappa, lambda)."""
+    lib = load_library()
+    n = wox.numel()
+    for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0, lobes=lobes).items():
+        _dev(t, k)
+    _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
+    if lobes.dim() != 2 or lobes.shape[1] != 5:
+        raise ValueError("lobes must have shape (nlobes, 5)")
+    nbytes = albedo_workspace_size(n, nsamples, 0)
+    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    out = torch.empty_like(wox)
+    rc = lib.radiance_estimate(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), _ptr(f0),
+                               nsamples, seed, _ptr(lobes), lobes.shape[0], _ptr(out), _ptr(ws),
+                               ws.numel() * 4, _stream(stream))
+    _check("radiance_estimate", rc)
+    return out
 
 
 class BatchPlan:

@@ -192,6 +192,42 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_adj(
     }
 }
 
+// Direct illumination: one sum of F G2/G1 L(wl) per cell.
+__global__ __launch_bounds__(kLutBlock) void k_radiance(
+    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
+    const float* __restrict__ lobep, int32_t nlobes, uint64_t nsamples, int32_t cpc,
+    uint32_t k0, uint32_t k1, float* __restrict__ partial) {
+    const int64_t b = blockIdx.x;
+    const int64_t cell = b / cpc;
+    const int64_t chunk = b - cell * cpc;
+    const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
+    const float f0 = f0p ? f0p[cell] : 1.0f;
+    const Lobes lobes = load_lobes(lobep, nlobes);
+    Comp acc[1] = {Comp{0.0f, 0.0f}};
+    const uint64_t npairs = (nsamples + 1) / 2;
+    const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
+    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+    if (c.ok) {
+        const uint32_t unit = (uint32_t)cell;
+        for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)kLutBlock * kGroup) {
+            float part = 0.0f;
+#pragma unroll 2
+            for (int j = 0; j < kGroup; ++j) {
+                const uint64_t p = p0 + (uint64_t)j * kLutBlock;
+                if (p < pend) {
+                    const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
+                    part += radiance_term(c, f0, lobes, unit24(w.w0), unit24(w.w1));
+                    if (2 * p + 1 < nsamples)
+                        part += radiance_term(c, f0, lobes, unit24(w.w2), unit24(w.w3));
+                }
+            }
+            comp_add(acc[0], part);
+        }
+    }
+    block_reduce_store<1, kLutBlock>(acc, partial + b * 2);
+}
+
 // ---------------------------------------------------------------------------
 // Batched persistent kernel: block b walks its static range of chunks
 // [block_chunks[b], block_chunks[b+1]); each chunk is (job, pair range).
@@ -421,6 +457,40 @@ extern "C" int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const
                            albedo, nullptr, nullptr, nullptr);
     }
     return check_launch("albedo_value_and_grad finish launch");
+}
+
+extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy,
+                                     const float* woz, const float* ax, const float* ay,
+                                     const float* f0, int64_t nsamples, uint64_t seed,
+                                     const float* lobes, int32_t nlobes, float* radiance,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
+    if (int32_t rc = check_cells("radiance_estimate", ncells, nsamples, wox, woy, woz, ax, ay))
+        return rc;
+    if (nlobes < 0 || nlobes > kMaxLobes)
+        return fail(CAPVNDF_ERR_BAD_SIZE, "radiance_estimate: nlobes must be in [0, %d]", kMaxLobes);
+    if (ncells == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(radiance, "radiance")) return rc;
+    if (nlobes > 0)
+        if (int32_t rc = check_array(lobes, "lobes")) return rc;
+    if (f0 != nullptr)
+        if (int32_t rc = check_array(f0, "f0")) return rc;
+    const size_t need = lut_workspace(ncells, nsamples, 1);
+    if (workspace_bytes < need || workspace == nullptr)
+        return fail(CAPVNDF_ERR_WORKSPACE, "radiance_estimate: workspace of %zu bytes needed, %zu given",
+                    need, workspace == nullptr ? (size_t)0 : workspace_bytes);
+    if (!aligned_to(workspace, 16))
+        return fail(CAPVNDF_ERR_MISALIGNED, "radiance_estimate: workspace must be 16-byte aligned");
+    const int64_t cpc = lut_chunks_per_cell(nsamples);
+    const hipStream_t st = as_stream(stream);
+    float* part = static_cast<float*>(workspace);
+    hipLaunchKernelGGL(k_radiance, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox, woy,
+                       woz, ax, ay, f0, lobes, nlobes, (uint64_t)nsamples, (int32_t)cpc,
+                       key_lo(seed), key_hi(seed), part);
+    if (int32_t rc = check_launch("radiance_estimate launch")) return rc;
+    hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                       part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr, radiance,
+                       nullptr, nullptr, nullptr);
+    return check_launch("radiance_estimate finish launch");
 }
 
 // ===========================================================================

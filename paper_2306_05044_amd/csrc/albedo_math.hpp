@@ -79,6 +79,65 @@ __device__ __forceinline__ FwdTerm albedo_fwd(const CellConst& c, float u1, floa
     return r;
 }
 
+// Synthetic incident radiance for the direct-illumination estimator: up to
+// kMaxLobes spherical-Gaussian lobes L(w) = sum lambda exp(kappa (mu.w - 1)),
+// held per lane (uniform values) with kappa pre-scaled by log2(e) for the
+// hardware base-2 exponential.
+constexpr int kMaxLobes = 8;
+
+struct Lobes {
+    float mx[kMaxLobes], my[kMaxLobes], mz[kMaxLobes], k2[kMaxLobes], lam[kMaxLobes];
+    int n;
+};
+
+__device__ __forceinline__ Lobes load_lobes(const float* __restrict__ p, int n) {
+    Lobes l;
+    l.n = n;
+#pragma unroll
+    for (int k = 0; k < kMaxLobes; ++k) {
+        const bool on = k < n;
+        l.mx[k] = on ? p[5 * k] : 0.0f;
+        l.my[k] = on ? p[5 * k + 1] : 0.0f;
+        l.mz[k] = on ? p[5 * k + 2] : 1.0f;
+        l.k2[k] = on ? p[5 * k + 3] * 1.4426950408889634f : 0.0f;
+        l.lam[k] = on ? p[5 * k + 4] : 0.0f;
+    }
+    return l;
+}
+
+__device__ __forceinline__ float lobe_radiance(const Lobes& l, float wx, float wy, float wz) {
+    float r = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxLobes; ++k) {
+        if (k < l.n) {
+            const float c = __builtin_fmaf(l.mx[k], wx, __builtin_fmaf(l.my[k], wy, l.mz[k] * wz));
+            r = __builtin_fmaf(l.lam[k], __builtin_amdgcn_exp2f(__builtin_fmaf(l.k2[k], c, -l.k2[k])), r);
+        }
+    }
+    return r;
+}
+
+// Direct-illumination term (Appendix A estimator with radiance L):
+// F(wo.h) G2/G1 L(wl), 0 below the horizon.
+__device__ __forceinline__ float radiance_term(const CellConst& c, float f0, const Lobes& lobes,
+                                               float u1, float u2) {
+    const CapSample cs = cap_sample(c.s, u1, u2);
+    const Normal n = unstretch(cs.hsx, cs.hsy, cs.hsz, c.ax, c.ay);
+    const float x = __builtin_fmaf(c.ox, n.hx, __builtin_fmaf(c.oy, n.hy, c.oz * n.hz));
+    const float x2 = x + x;
+    const float wlx = __builtin_fmaf(x2, n.hx, -c.ox);
+    const float wly = __builtin_fmaf(x2, n.hy, -c.oy);
+    const float wlz = __builtin_fmaf(x2, n.hz, -c.oz);
+    const float plx = c.ax * wlx, ply = c.ay * wly;
+    const float m = fsqrt(__builtin_fmaf(plx, plx, __builtin_fmaf(ply, ply, wlz * wlz)));
+    const float g = 2.0f * wlz * rcp(__builtin_fmaf(c.go, m, c.tgo * wlz));
+    const float mx = 1.0f - x;
+    const float mm = mx * mx;
+    const float F = __builtin_fmaf(1.0f - f0, mm * mm * mx, f0);
+    const float L = lobe_radiance(lobes, wlx, wly, wlz);
+    return wlz > 0.0f ? F * g * L : 0.0f;
+}
+
 // Adjoint term for A = mean of w = F g: the weight w and its derivatives at
 // fixed (u1, u2).  dax/day/dth hold the direct dependences on alpha and on
 // wo (already projected on the meridian tangent); dwsx/dwsy/dzs are the

@@ -102,6 +102,9 @@ def test_albedo_argument_errors(lib):
                                      None) == -5
     assert lib.albedo_value_and_grad(4, *five, 100, 0, None, None, None, None, None, fake, 1 << 20,
                                      None) == -1
+    assert lib.radiance_estimate(4, *five, None, 100, 0, fake, 9, fake, fake, 1 << 20, None) == -2
+    assert lib.radiance_estimate(4, *five, None, 100, 0, None, 2, fake, fake, 1 << 20, None) == -1
+    assert lib.radiance_estimate(4, *five, None, 100, 0, fake, 2, fake, fake, 4, None) == -5
     out = P()
     ns = (ctypes.c_int64 * 2)(10, 20)
     assert lib.albedo_batch_plan_create(0, *five, None, ns, 0, 1, fake, fake, fake, fake, None,
