@@ -103,6 +103,25 @@ int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz
                  const float* ay, float* pdf, void* stream);
 
 /*
+ * vndf_inverse -- inverse of the cap sampler (vndf_sample with CAPVNDF_CAP):
+ * the uniforms (u1, u2) that produce a given visible normal h seen from wi.
+ * By the reflection law and the half-vector relation of Sec. 3.2 the
+ * hemisphere normal n = M^T h / |M^T h| reflects wi_std into the cap point
+ * c = 2 (n . wi_std) n - wi_std, whose height and azimuth invert the cap
+ * parameterisation of Sec. 3.3.  Useful to map normals back to primary
+ * sample space (e.g. to reuse or mutate paths).
+ *
+ *   n; wix,wiy,wiz [n]; hx,hy,hz unit visible normals [n]; ax, ay [n];
+ *   u1, u2 [n] out: in [0, 1); both -1 outside the domain (w_z <= 0,
+ *   alpha <= 0, h_z <= 0 or wi.h <= 0).  u1 is undefined at the apex of the
+ *   cap (u2 = 0) and returned as atan2 gives it there.
+ * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, HIP.
+ */
+int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                     const float* hx, const float* hy, const float* hz, const float* ax,
+                     const float* ay, float* u1, float* u2, void* stream);
+
+/*
  * albedo_workspace_size -- bytes of device workspace needed for ncells cells
  * of nsamples samples each by albedo_estimate (mode 0),
  * albedo_estimate_backward (mode 1) or albedo_value_and_grad (mode 2; enough

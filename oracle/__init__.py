@@ -106,6 +106,9 @@ def _load():
     lib.orc_radiance.restype = ctypes.c_int32
     lib.orc_radiance_at.argtypes = [ctypes.c_int64, _d, _d, _d, _d, ctypes.c_int32, _d]
     lib.orc_radiance_at.restype = None
+    lib.orc_vndf_inverse.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d,
+                                     ctypes.c_int32]
+    lib.orc_vndf_inverse.restype = ctypes.c_int32
     lib.orc_hardware_threads.argtypes = []
     lib.orc_hardware_threads.restype = ctypes.c_int32
     _lib = lib
@@ -323,3 +326,19 @@ def radiance(wo, ax, ay, nsamples, seed, lobes, f0=1.0, units=None, nthreads=0):
     if rc != 0:
         raise ValueError("orc_radiance failed")
     return out
+
+
+def vndf_inverse(wi, h, ax, ay, nthreads=0):
+    """Inverse of the cap sampler through the reflection law (Sec. 3.2):
+    (u1, u2) with u = -1 outside the domain."""
+    wi = [_f64(c) for c in wi]
+    n = wi[0].shape[0]
+    h = [_f64(c) for c in h]
+    u1 = np.zeros(n)
+    u2 = np.zeros(n)
+    rc = _load().orc_vndf_inverse(n, *[_p(c) for c in wi], *[_p(c) for c in h],
+                                  _p(_f64(ax, n)), _p(_f64(ay, n)), _p(u1), _p(u2),
+                                  _nt(nthreads))
+    if rc != 0:
+        raise ValueError("orc_vndf_inverse failed")
+    return u1, u2

@@ -635,6 +635,36 @@ void orc_radiance_at(int64_t n, const double* wx, const double* wy, const double
     for (int64_t i = 0; i < n; ++i) out[i] = radiance(Vec3<double>{wx[i], wy[i], wz[i]}, lobes, nlobes);
 }
 
+// Inverse of the cap sampler (Sec. 3.2): from a normal h seen from wi, the
+// hemisphere normal h_std = M^T h / |M^T h| reflects wi_std = M^-1 wi /
+// |M^-1 wi| into the cap point c = 2 (h_std . wi_std) h_std - wi_std
+// (reflection law); the cap's height z = (1 - u2)(1 + z_i) - z_i and azimuth
+// 2 pi u1 then give (u1, u2).  Outside the domain (w_z <= 0, alpha <= 0,
+// h_z <= 0 or wi . h <= 0) both outputs are -1.
+int32_t orc_vndf_inverse(int64_t n, const double* wix, const double* wiy, const double* wiz,
+                         const double* hx, const double* hy, const double* hz, const double* ax,
+                         const double* ay, double* u1, double* u2, int32_t nthreads) {
+    if (n < 0) return -1;
+    parallel_for(n, nthreads, [&](int64_t i) {
+        Vec3<double> wi{wix[i], wiy[i], wiz[i]};
+        Vec3<double> h{hx[i], hy[i], hz[i]};
+        double a = ax[i], b = ay[i];
+        if (!(wi.z > 0.0) || !(a > 0.0) || !(b > 0.0) || !(h.z > 0.0) || !(dot(wi, h) > 0.0)) {
+            u1[i] = -1.0; u2[i] = -1.0;
+            return;
+        }
+        Vec3<double> h_std = normalize(Vec3<double>{h.x / a, h.y / b, h.z});
+        Vec3<double> wi_std = normalize(Vec3<double>{wi.x * a, wi.y * b, wi.z});
+        double d = dot(h_std, wi_std);
+        Vec3<double> c{2.0 * d * h_std.x - wi_std.x, 2.0 * d * h_std.y - wi_std.y,
+                       2.0 * d * h_std.z - wi_std.z};
+        u2[i] = 1.0 - (c.z + wi_std.z) / (1.0 + wi_std.z);
+        double t = std::atan2(c.y, c.x) / (2.0 * kPi);
+        u1[i] = t < 0.0 ? t + 1.0 : t;
+    });
+    return 0;
+}
+
 int32_t orc_hardware_threads(void) {
     return (int32_t)std::max(1u, std::thread::hardware_concurrency());
 }

@@ -6,7 +6,7 @@ Method: Dupuy and Benyoub, "Sampling Visible GGX Normals with Spherical Caps"
 the current stream) into the C ABI declared in ``include/capvndf.h``.  There is
 no CPU fallback: without the built library every call raises.
 
-Names mirror the C entry points: ``vndf_sample``, ``vndf_pdf``,
+Names mirror the C entry points: ``vndf_sample``, ``vndf_pdf``, ``vndf_inverse``,
 ``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_value_and_grad``,
 ``albedo_workspace_size``, ``radiance_estimate``,
 ``BatchPlan`` (``albedo_batch_plan_create`` / ``albedo_batch_run`` /
@@ -60,6 +60,7 @@ _SIGNATURES = {
     "capvndf_last_error": ([], ctypes.c_char_p),
     "vndf_sample": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _U64, _I32, _P, _P, _P, _P, _P], _I32),
     "vndf_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "vndf_inverse": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "albedo_workspace_size": ([_I64, _I64, _I32], ctypes.c_size_t),
     "albedo_estimate": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, ctypes.c_size_t, _P],
                         _I32),
@@ -185,6 +186,21 @@ def vndf_pdf(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
                       _ptr(ay), _ptr(pdf), _stream(stream))
     _check("vndf_pdf", rc)
     return pdf
+
+
+def vndf_inverse(wix, wiy, wiz, hx, hy, hz, ax, ay, stream=None):
+    """Uniforms (u1, u2) that the cap sampler maps to the given normals."""
+    lib = load_library()
+    n = wix.numel()
+    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, hx=hx, hy=hy, hz=hz, ax=ax, ay=ay).items():
+        _dev(t, k)
+    _same_len(n, wiy=wiy, wiz=wiz, hx=hx, hy=hy, hz=hz, ax=ax, ay=ay)
+    u1 = torch.empty_like(wix)
+    u2 = torch.empty_like(wix)
+    rc = lib.vndf_inverse(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(hx), _ptr(hy), _ptr(hz),
+                          _ptr(ax), _ptr(ay), _ptr(u1), _ptr(u2), _stream(stream))
+    _check("vndf_inverse", rc)
+    return u1, u2
 
 
 def albedo_workspace_size(ncells: int, nsamples: int, mode: int) -> int:

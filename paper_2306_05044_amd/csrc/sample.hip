@@ -231,6 +231,82 @@ __global__ __launch_bounds__(kBlock) void k_pdf_scalar(
     pdf[i] = pdf_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i]);
 }
 
+// Inverse of the cap sampler (Sec. 3.2): the hemisphere normal
+// n = M^T h / |M^T h| reflects ws into the cap point c = 2 (n . ws) n - ws
+// (reflection law); then 1 - u2 = (c_z + zs) / (1 + zs), i.e.
+// u2 = (1 + zs - 2 (n . ws) n_z) / (1 + zs), and u1 = atan2(c_y, c_x) / (2 pi)
+// in [0, 1).  Outside the domain both are -1.
+__device__ __forceinline__ void inverse_one(float wx, float wy, float wz, float hx, float hy,
+                                            float hz, float ax, float ay, float& u1, float& u2) {
+    const float d0 = __builtin_fmaf(wx, hx, __builtin_fmaf(wy, hy, wz * hz));
+    const bool ok = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f) && (hz > 0.0f) && (d0 > 0.0f);
+    if (!ok) {
+        wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f; hx = 0.0f; hy = 0.0f; hz = 1.0f;
+    }
+    const Stretched s = stretch(wx, wy, wz, ax, ay);
+    const float mx = hx * rcp(ax), my = hy * rcp(ay);
+    const float im = rsq(__builtin_fmaf(mx, mx, __builtin_fmaf(my, my, hz * hz)));
+    const float nx = mx * im, ny = my * im, nz = hz * im;
+    const float d2 = 2.0f * __builtin_fmaf(nx, s.wsx, __builtin_fmaf(ny, s.wsy, nz * s.zs));
+    const float cx = __builtin_fmaf(d2, nx, -s.wsx);
+    const float cy = __builtin_fmaf(d2, ny, -s.wsy);
+    const float v2 = __builtin_fmaf(-d2, nz, s.opz) * rcp(s.opz);
+    float t = atan2f(cy, cx) * 0.159154943091895336f;
+    t = t < 0.0f ? t + 1.0f : t;
+    t = t >= 1.0f ? 0.0f : t;
+    u1 = ok ? t : -1.0f;
+    u2 = ok ? fmaxf(v2, 0.0f) : -1.0f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_inverse_v4(
+    int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
+    const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
+    const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
+    float* __restrict__ u1p, float* __restrict__ u2p) {
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
+    f4 x[kGroups], y[kGroups], z[kGroups], hx[kGroups], hy[kGroups], hz[kGroups], a[kGroups],
+        b[kGroups];
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            x[g] = load4(wix + i0); y[g] = load4(wiy + i0); z[g] = load4(wiz + i0);
+            hx[g] = load4(hxp + i0); hy[g] = load4(hyp + i0); hz[g] = load4(hzp + i0);
+            a[g] = load4(ax + i0); b[g] = load4(ay + i0);
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g) {
+        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        if (i0 + 4 <= n) {
+            f4 o1, o2;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float q1, q2;
+                inverse_one(x[g][j], y[g][j], z[g][j], hx[g][j], hy[g][j], hz[g][j], a[g][j],
+                            b[g][j], q1, q2);
+                o1[j] = q1; o2[j] = q2;
+            }
+            store4(u1p + i0, o1);
+            store4(u2p + i0, o2);
+        } else {
+            for (int64_t i = i0; i < n && i < i0 + 4; ++i)
+                inverse_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i], u1p[i],
+                            u2p[i]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_inverse_scalar(
+    int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
+    const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
+    const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
+    float* __restrict__ u1p, float* __restrict__ u2p) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    inverse_one(wix[i], wiy[i], wiz[i], hxp[i], hyp[i], hzp[i], ax[i], ay[i], u1p[i], u2p[i]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_uniforms(int64_t n, uint64_t k0, uint32_t tag,
                                                      uint32_t unit, uint32_t key0,
                                                      uint32_t key1, float* __restrict__ u1,
@@ -422,6 +498,28 @@ extern "C" int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const
         hipLaunchKernelGGL(k_pdf_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix, wiy,
                            wiz, hx, hy, hz, ax, ay, pdf);
     return check_launch("vndf_pdf launch");
+}
+
+extern "C" int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                                const float* hx, const float* hy, const float* hz, const float* ax,
+                                const float* ay, float* u1, float* u2, void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_inverse: n = %lld < 0", (long long)n);
+    if (n == 0) return CAPVNDF_OK;
+    const void* req[] = {wix, wiy, wiz, hx, hy, hz, ax, ay, u1, u2};
+    const char* names[] = {"wix", "wiy", "wiz", "hx", "hy", "hz", "ax", "ay", "u1", "u2"};
+    bool vec = true;
+    for (int i = 0; i < 10; ++i) {
+        if (int32_t rc = check_array(req[i], names[i])) return rc;
+        if (!aligned_to(req[i], 16)) vec = false;
+    }
+    const hipStream_t st = as_stream(stream);
+    if (vec)
+        hipLaunchKernelGGL(k_inverse_v4, dim3(tiles_for(n)), dim3(kBlock), 0, st, n, wix, wiy, wiz,
+                           hx, hy, hz, ax, ay, u1, u2);
+    else
+        hipLaunchKernelGGL(k_inverse_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix, wiy,
+                           wiz, hx, hy, hz, ax, ay, u1, u2);
+    return check_launch("vndf_inverse launch");
 }
 
 extern "C" int32_t capvndf_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, uint64_t k0,

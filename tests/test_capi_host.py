@@ -72,6 +72,8 @@ def test_sample_argument_errors(lib):
     # n == 0 enqueues nothing and succeeds even with NULL arrays
     assert lib.vndf_sample(0, None, None, None, None, None, None, None, 0, 0, 0, None, None, None,
                            None, None) == 0
+    assert lib.vndf_inverse(-5, *[None] * 10, None) == -2
+    assert lib.vndf_inverse(3, *[fake] * 9, None, None) == -1
     assert lib.vndf_pdf(-5, *[None] * 9, None) == -2
     assert lib.vndf_pdf(0, *[None] * 9, None) == 0
 

@@ -223,3 +223,57 @@ def test_streaming_full_size_sampled(method):
                                       u1=u1, u2=u2, method=method)
     fh, fp = _compare(sub, hx[it], hy[it], hz[it], pdf[it], h_ref, p_ref, "full size", method)
     print(f"full size method {method}: fraction > 2e-6: h {fh:.2e}, pdf {fp:.2e}")
+
+
+def _circ(a, b):
+    d = np.abs(a - b)
+    return np.minimum(d, 1.0 - d)
+
+
+@pytest.mark.parametrize("n", [65536 + 3, 4096])
+def test_inverse_map(n):
+    """vndf_inverse on the GPU's own FP32 normals vs the oracle's inverse of the
+    same FP32 values (Sec. 3.2 reflection law).  Arithmetic bound with identical
+    inputs: |du2| <= 32 eps; |du1| <= 32 eps / |c_xy| (c the cap point), tested
+    where |c_xy| > 1e-3 (u1 is undefined at the apex)."""
+    d = workloads.tuples_streaming(n, seed=31)
+    t = to_dev(d)
+    u1, u2 = cv.capvndf_uniforms(9, 2, 0, 0, n)
+    hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], u1=u1, u2=u2)
+    g1, g2 = cv.vndf_inverse(t["wx"], t["wy"], t["wz"], hx, hy, hz, t["ax"], t["ay"])
+    H = [host(x).astype(np.float64) for x in (hx, hy, hz)]
+    r1, r2 = oracle.vndf_inverse((d["wx"], d["wy"], d["wz"]), H, d["ax"], d["ay"])
+    eps = 2.0 ** -24
+    assert np.all(np.abs(host(g2) - r2) <= 32 * eps)
+    ax, ay = d["ax"].astype(np.float64), d["ay"].astype(np.float64)
+    ws = np.stack([d["wx"] * ax, d["wy"] * ay, d["wz"].astype(np.float64)], 1)
+    zs = ws[:, 2] / np.linalg.norm(ws, axis=1)
+    cz = 1.0 - r2 * (1.0 + zs)
+    cxy = np.sqrt(np.maximum(0.0, 1.0 - cz * cz))
+    ok = cxy > 1e-3
+    assert np.all(_circ(host(g1)[ok], r1[ok]) <= 32 * eps / cxy[ok])
+    assert np.all((host(g1) >= 0) & (host(g1) < 1) & (host(g2) >= 0) & (host(g2) < 1))
+    # round trip through FP32 normals: error follows the conditioning of the
+    # map u -> h; the bulk is at rounding level
+    e2 = np.abs(host(g2) - host(u2))
+    print(f"round trip |du2|: median {np.median(e2):.2e}, 99th pct {np.percentile(e2, 99):.2e}")
+    assert np.median(e2) < 1e-6
+
+
+def test_inverse_edges_and_scalar_path():
+    wz = torch.tensor([1.0, -1.0, 1.0, 1.0, 1.0], device="cuda")
+    z = torch.zeros(5, device="cuda")
+    ax = torch.tensor([0.5, 0.5, 0.0, 0.5, 0.5], device="cuda")
+    hz = torch.tensor([1.0, 1.0, 1.0, -1.0, 1.0], device="cuda")
+    hx = torch.tensor([0.0, 0.0, 0.0, 0.0, 0.0], device="cuda")
+    g1, g2 = cv.vndf_inverse(z, z, wz, hx, z, hz, ax, ax.clone())
+    G1, G2 = host(g1), host(g2)
+    assert G2[0] == 0.0 and np.all(G1[1:4] == -1) and np.all(G2[1:4] == -1) and G2[4] == 0.0
+    d = workloads.tuples_streaming(1001, seed=2)
+    t = to_dev(d)
+    hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=3)
+    a = cv.vndf_inverse(t["wx"][:1000], t["wy"][:1000], t["wz"][:1000], hx[:1000], hy[:1000],
+                        hz[:1000], t["ax"][:1000], t["ay"][:1000])
+    b = cv.vndf_inverse(t["wx"][1:], t["wy"][1:], t["wz"][1:], hx[1:], hy[1:], hz[1:],
+                        t["ax"][1:], t["ay"][1:])
+    assert torch.equal(a[0][1:], b[0][:-1]) and torch.equal(a[1][1:], b[1][:-1])

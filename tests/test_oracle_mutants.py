@@ -53,6 +53,10 @@ MUTANTS = [
     ("disk warp weight", "T s = (T(1.0) + wi.z) / 2.0;", "T s = (T(1.0) - wi.z) / 2.0;"),
     ("disk basis", "w1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};", "w1 = Vec3<T>{wi.y * inv, wi.x * inv, T(0.0)};"),
     ("lobe exponent", "l += p[4] * std::exp(p[3] * (c - 1.0));", "l += p[4] * std::exp(p[3] * (1.0 - c));"),
+    ("inverse azimuth swapped", "double t = std::atan2(c.y, c.x) / (2.0 * kPi);",
+     "double t = std::atan2(c.x, c.y) / (2.0 * kPi);"),
+    ("inverse height", "u2[i] = 1.0 - (c.z + wi_std.z) / (1.0 + wi_std.z);",
+     "u2[i] = 1.0 - (c.z - wi_std.z) / (1.0 + wi_std.z);"),
     ("radiance at the view", "return radiance(normalize(wb), params, nlobes) * fr * wb.z / pdf;",
      "return radiance(wa, params, nlobes) * fr * wb.z / pdf;"),
 ]

@@ -204,3 +204,26 @@ def test_domain_and_stream_offset(orc):
     hB, pB = orc.vndf_sample(tuple(c[100:] for c in wi), d["ax"][100:], d["ay"][100:],
                              seed=4, index_base=100)
     assert np.array_equal(hA[100:], hB) and np.array_equal(pA[100:], pB)
+
+
+def test_oracle_inverse_map_round_trip(orc):
+    """The oracle's inverse (reflection law of Sec. 3.2) undoes its cap sampler,
+    and marks inputs outside the domain with -1."""
+    d = workloads.tuples_streaming(20000, seed=14)
+    wi = tuple(d[k].astype(np.float64) for k in ("wx", "wy", "wz"))
+    u1, u2 = orc.uniforms(7, orc.TAG_SAMPLE, 0, 0, 20000)
+    h, _ = orc.vndf_sample(wi, d["ax"], d["ay"], u1=u1, u2=u2, method=0)
+    r1, r2 = orc.vndf_inverse(wi, tuple(h.T), d["ax"], d["ay"])
+    assert np.max(np.abs(r2 - u2)) < 1e-9
+    du1 = np.abs(r1 - u1)
+    du1 = np.minimum(du1, 1.0 - du1)
+    # the azimuth is undefined at the apex of the cap (u2 = 0) and ill-posed near it
+    ok = u2 > 1e-6
+    assert np.max(du1[ok]) < 1e-7
+    assert np.all((r1 >= 0) & (r1 < 1) & (r2 >= -1e-12) & (r2 < 1 + 1e-12))
+    n = 4
+    bad1, bad2 = orc.vndf_inverse((np.zeros(n), np.zeros(n), np.array([-1.0, 1.0, 1.0, 1.0])),
+                                  (np.zeros(n), np.array([0.0, 0.0, 1.0, 0.0]),
+                                   np.array([1.0, -0.5, 0.0, 1.0])),
+                                  np.array([0.5, 0.5, 0.5, 0.0]), np.full(n, 0.5))
+    assert np.all(bad1 == -1.0) and np.all(bad2 == -1.0)
