@@ -28,7 +28,7 @@ METRIC = ("Gsamples/s VNDF (cap vs 2018 disk) + albedo-LUT fwd+bwd time at "
 N_STREAM = 1 << 26
 BYTES_PER_SAMPLE = 36  # 5 FP32 inputs read + 4 FP32 outputs written
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("stream", "disk", "probe", "micro", "lut", "grad", "batch", "radiance")
+SECTIONS = ("stream", "disk", "probe", "inverse", "micro", "lut", "grad", "batch", "radiance")
 
 
 def log(msg):
@@ -177,6 +177,19 @@ def main():
         ms_p, _ = timed(lambda: cv.capvndf_stream_probe(ins, outs), args.steps, args.warmup)
         out["stream_probe"] = {"ms_per_launch": round(ms_p, 5),
                                "gbytes_per_s": round(BYTES_PER_SAMPLE * N_STREAM / ms_p / 1e6, 1)}
+    if "inverse" in only:
+        log("timing the inverse map h -> (u1, u2)")
+        run(0)()
+        u1b = torch.empty_like(t["wx"])
+        u2b = torch.empty_like(t["wx"])
+        ms_i, _ = timed(lambda: cv.vndf_inverse(t["wx"], t["wy"], t["wz"], outs[0], outs[1],
+                                                outs[2], t["ax"], t["ay"], out=(u1b, u2b)),
+                        args.steps, args.warmup)
+        out["inverse_map"] = {"ms_per_launch": round(ms_i, 5),
+                              "gsamples_per_s": round(N_STREAM / ms_i / 1e6, 3),
+                              "gbytes_per_s": round(40 * N_STREAM / ms_i / 1e6, 1),
+                              "bytes_per_sample": 40}
+        del u1b, u2b
     if "micro" in only:
         log("timing the register-resident microbenchmark")
         lanes = 256 * 2048 * 4

@@ -188,15 +188,18 @@ def vndf_pdf(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
     return pdf
 
 
-def vndf_inverse(wix, wiy, wiz, hx, hy, hz, ax, ay, stream=None):
+def vndf_inverse(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
     """Uniforms (u1, u2) that the cap sampler maps to the given normals."""
     lib = load_library()
     n = wix.numel()
     for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, hx=hx, hy=hy, hz=hz, ax=ax, ay=ay).items():
         _dev(t, k)
     _same_len(n, wiy=wiy, wiz=wiz, hx=hx, hy=hy, hz=hz, ax=ax, ay=ay)
-    u1 = torch.empty_like(wix)
-    u2 = torch.empty_like(wix)
+    if out is None:
+        u1, u2 = torch.empty_like(wix), torch.empty_like(wix)
+    else:
+        u1, u2 = (_dev(x, "out") for x in out)
+        _same_len(n, u1=u1, u2=u2)
     rc = lib.vndf_inverse(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(hx), _ptr(hy), _ptr(hz),
                           _ptr(ax), _ptr(ay), _ptr(u1), _ptr(u2), _stream(stream))
     _check("vndf_inverse", rc)
