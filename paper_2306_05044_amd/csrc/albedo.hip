@@ -24,6 +24,16 @@ constexpr int kLutBlock = 256;
 constexpr int kLutPairsPerThread = 32;
 constexpr uint64_t kLutChunkPairs = (uint64_t)kLutBlock * kLutPairsPerThread;
 constexpr int kGroup = 8;  // pairs summed plainly before each TwoSum fold
+// Unroll depth of the adjoint's pair loop and the waves per SIMD the
+// adjoint kernels are compiled for (build-time tuning constants).  Seven
+// resident waves beat the compiler's default register budget (five waves) by
+// about 8 % on gfx950, even though a few loop-invariant values then spill.
+#ifndef CAPVNDF_ADJ_UNROLL
+#define CAPVNDF_ADJ_UNROLL 1
+#endif
+#ifndef CAPVNDF_ADJ_WAVES
+#define CAPVNDF_ADJ_WAVES 7
+#endif
 constexpr int kFinishBlock = 256;
 
 // ---------------------------------------------------------------------------
@@ -104,7 +114,7 @@ __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t
     for (int a = 0; a < 7; ++a) acc[a] = Comp{0.0f, 0.0f};
     for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)BLOCK * kGroup) {
         float part[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
+#pragma unroll CAPVNDF_ADJ_UNROLL
         for (int j = 0; j < kGroup; ++j) {
             const uint64_t p = p0 + (uint64_t)j * BLOCK;
             if (p < pend) {
@@ -167,8 +177,9 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
 
 // Adjoint of A(F0); WITH_VALUE also reduces the value itself (4 sums: A,
 // dA/d alpha_x, dA/d alpha_y, dA/d theta_o), otherwise the 3 gradient sums.
+#define CAPVNDF_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(CAPVNDF_ADJ_WAVES)))
 template <bool WITH_VALUE>
-__global__ __launch_bounds__(kLutBlock) void k_albedo_adj(
+__global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
     uint64_t nsamples, int32_t cpc, uint32_t unit_base, uint32_t k0, uint32_t k1,
@@ -233,7 +244,7 @@ __global__ __launch_bounds__(kLutBlock) void k_radiance(
 // [block_chunks[b], block_chunks[b+1]); each chunk is (job, pair range).
 // ---------------------------------------------------------------------------
 template <int BLOCK, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void k_batch(
+__global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
     const int64_t* __restrict__ nsamp, const int32_t* __restrict__ chunk_job,

@@ -70,11 +70,13 @@ __device__ __forceinline__ FwdTerm albedo_fwd(const CellConst& c, float u1, floa
     const float wlz = __builtin_fmaf(x2, n.hz, -c.oz);
     const float plx = c.ax * wlx, ply = c.ay * wly;
     const float m = fsqrt(__builtin_fmaf(plx, plx, __builtin_fmaf(ply, ply, wlz * wlz)));
-    const float g = 2.0f * wlz * rcp(__builtin_fmaf(c.go, m, c.tgo * wlz));
+    // wl_z clamped at 0: g is exactly 0 below the horizon, with a positive
+    // denominator (Go m > 0)
+    const float wz0 = fmaxf(wlz, 0.0f);
+    FwdTerm r;
+    r.g = 2.0f * wz0 * rcp(__builtin_fmaf(c.go, m, c.tgo * wz0));
     const float mx = 1.0f - x;
     const float mm = mx * mx;
-    FwdTerm r;
-    r.g = wlz > 0.0f ? g : 0.0f;
     r.m5 = mm * mm * mx;
     return r;
 }
@@ -130,12 +132,12 @@ __device__ __forceinline__ float radiance_term(const CellConst& c, float f0, con
     const float wlz = __builtin_fmaf(x2, n.hz, -c.oz);
     const float plx = c.ax * wlx, ply = c.ay * wly;
     const float m = fsqrt(__builtin_fmaf(plx, plx, __builtin_fmaf(ply, ply, wlz * wlz)));
-    const float g = 2.0f * wlz * rcp(__builtin_fmaf(c.go, m, c.tgo * wlz));
+    const float wz0 = fmaxf(wlz, 0.0f);
+    const float g = 2.0f * wz0 * rcp(__builtin_fmaf(c.go, m, c.tgo * wz0));
     const float mx = 1.0f - x;
     const float mm = mx * mx;
     const float F = __builtin_fmaf(1.0f - f0, mm * mm * mx, f0);
-    const float L = lobe_radiance(lobes, wlx, wly, wlz);
-    return wlz > 0.0f ? F * g * L : 0.0f;
+    return F * g * lobe_radiance(lobes, wlx, wly, wlz);
 }
 
 // Adjoint term for A = mean of w = F g: the weight w and its derivatives at
@@ -154,7 +156,11 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     const float a = 1.0f - u2;
     const float hsz = a * s.opz;
     const float s2 = u2 * s.opz * (hsz + s.omz);
-    const float st = fsqrt(s2);
+    // sin(theta_c) = s2 / sqrt(s2), keeping 1 / sin(theta_c) for the reverse
+    // sweep; s2 == 0 only at the apex (u2 == 0), where both are taken as 0
+    const bool apex = !(s2 > 0.0f);
+    const float ist = rsq(s2);
+    const float st = apex ? 0.0f : s2 * ist;
     float sp, cp;
     sincos_turns(u1, &sp, &cp);
     const float hsx = __builtin_fmaf(st, cp, s.wsx);
@@ -172,8 +178,12 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     const float m2 = __builtin_fmaf(wlz, wlz, pp);
     const float im = rsq(m2);
     const float ml = m2 * im;  // |M^-1 wl|
-    const float iD = rcp(__builtin_fmaf(c.go, ml, c.tgo * wlz));
-    const float g = 2.0f * wlz * iD;
+    // wl_z clamped at 0 (see albedo_fwd): below the horizon g and all its
+    // derivatives vanish except the direct one in wl_z, which is masked
+    const bool live = wlz > 0.0f;
+    const float wz0 = fmaxf(wlz, 0.0f);
+    const float iD = rcp(__builtin_fmaf(c.go, ml, c.tgo * wz0));
+    const float g = 2.0f * wz0 * iD;
     const float mx = 1.0f - x;
     const float mm = mx * mx;
     const float m4 = mm * mm;
@@ -184,12 +194,12 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     // dg/dwl_z = 2 Go m / D^2, dg/dm = -2 Go wl_z / D^2, dg/dGo = -2 wl_z (m - wl_z) / D^2,
     // and m = |(plx, ply, wl_z)|.
     float dx = -5.0f * f1 * m4 * g;              // through F(x)
-    const float t2 = 2.0f * iD * iD;
-    const float e = F * t2 * c.go * im;          // F dg/dm / m, up to the sign
-    const float dwlz = e * pp;                   // F (dg/dwl_z + dg/dm wl_z / m)
-    const float ew = -e * wlz;
+    const float ft2 = F * 2.0f * iD * iD;
+    const float e = ft2 * c.go * im;             // F dg/dm / m, up to the sign
+    const float dwlz = live ? e * pp : 0.0f;     // F (dg/dwl_z + dg/dm wl_z / m)
+    const float ew = -e * wz0;
     const float dplx = ew * plx, dply = ew * ply;
-    const float dgo = -F * t2 * wlz * (ml - wlz);
+    const float dgo = -ft2 * wz0 * (ml - wz0);
     float dax = dplx * wlx;
     float day = dply * wly;
     const float dwlx = dplx * c.ax, dwly = dply * c.ay;
@@ -215,22 +225,21 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     // hs = (st cos phi + wsx, st sin phi + wsy, (1 - u2)(1 + zs)),
     // st^2 = u2 (1 + zs) ((1 - u2)(1 + zs) + 1 - zs)
     const float dst = __builtin_fmaf(dhsx, cp, dhsy * sp);
-    const float ds2u = st > 0.0f ? 0.5f * dst * rcp(st) * u2 : 0.0f;
+    const float ds2u = apex ? 0.0f : 0.5f * dst * ist * u2;
     const float dopz = __builtin_fmaf(dvz, a, ds2u * (2.0f * hsz + s.omz));
     const float domz = ds2u * s.opz;
     const float iopz = rcp(s.opz);
     // Go = 2 zs / (1 + zs), 1 + zs, 1 - zs
     const float dzs = __builtin_fmaf(dgo * 2.0f * iopz, iopz, dopz - domz);
 
-    const bool live = wlz > 0.0f;
     AdjTerm r;
-    r.w = live ? F * g : 0.0f;
-    r.dax = live ? dax : 0.0f;
-    r.day = live ? day : 0.0f;
-    r.dth = live ? __builtin_fmaf(c.tx, dox, __builtin_fmaf(c.ty, doy, c.tz * doz)) : 0.0f;
-    r.dwsx = live ? dhsx : 0.0f;
-    r.dwsy = live ? dhsy : 0.0f;
-    r.dzs = live ? dzs : 0.0f;
+    r.w = F * g;
+    r.dax = dax;
+    r.day = day;
+    r.dth = __builtin_fmaf(c.tx, dox, __builtin_fmaf(c.ty, doy, c.tz * doz));
+    r.dwsx = dhsx;
+    r.dwsy = dhsy;
+    r.dzs = dzs;
     return r;
 }
 
