@@ -134,7 +134,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by "
-              "tuple/cell/job ranges with no exchange but a final reduction, which this build "
+              "tuple/cell/job ranges with no exchange but a final reduction, which this library "
               "does not run across GPUs.", file=sys.stderr)
         sys.exit(2)
     only = set(args.only) if args.only else set(SECTIONS)

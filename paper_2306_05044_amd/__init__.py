@@ -96,7 +96,7 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(
             f"libcapvndf.so not found at {path}: build it first "
-            "(python -c 'import __graft_entry__ as g; g.build()')")
+            "(python paper_2306_05044_amd/build.py)")
     lib = ctypes.CDLL(path)
     for name, (args, res) in _SIGNATURES.items():
         fn = getattr(lib, name)

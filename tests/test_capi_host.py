@@ -24,7 +24,7 @@ def _declared_functions():
 def lib():
     import paper_2306_05044_amd as cv
     if not os.path.exists(cv.LIB_PATH):
-        pytest.fail("libcapvndf.so is not built (run __graft_entry__.build())")
+        pytest.fail("libcapvndf.so is not built (run python paper_2306_05044_amd/build.py)")
     return cv.load_library()
 
 

@@ -277,3 +277,52 @@ def test_inverse_edges_and_scalar_path():
     b = cv.vndf_inverse(t["wx"][1:], t["wy"][1:], t["wz"][1:], hx[1:], hy[1:], hz[1:],
                         t["ax"][1:], t["ay"][1:])
     assert torch.equal(a[0][1:], b[0][:-1]) and torch.equal(a[1][1:], b[1][:-1])
+
+
+def test_degenerate_cases():
+    """Apex (u2 = 0) and rim (u2 = 1 - 2^-24) of the cap, azimuth on quadrant
+    boundaries, normal incidence, near-grazing views, isotropic alpha = 1 and
+    extreme roughness, each against the oracle with the conditioning rule."""
+    u2s = [0.0, 2.0 ** -24, 0.5, 1.0 - 2.0 ** -24]
+    u1s = [0.0, 0.25, 0.5, 0.75, 1.0 - 2.0 ** -24]
+    views = [(0.0, 0.0, 1.0), (np.sqrt(1 - 1e-6), 0.0, 1e-3), (0.6, 0.0, 0.8),
+             (0.0, -np.sqrt(1 - 1e-8), 1e-4)]
+    alphas = [(1.0, 1.0), (1e-3, 1e-3), (1e-5, 0.5), (0.5, 1e-5), (1.0, 1e-3)]
+    rows = [(v, a, p, q) for v in views for a in alphas for p in u1s for q in u2s]
+    d = {"wx": np.array([r[0][0] for r in rows], np.float32),
+         "wy": np.array([r[0][1] for r in rows], np.float32),
+         "wz": np.array([r[0][2] for r in rows], np.float32),
+         "ax": np.array([r[1][0] for r in rows], np.float32),
+         "ay": np.array([r[1][1] for r in rows], np.float32)}
+    u1 = np.array([r[2] for r in rows], np.float32)
+    u2 = np.array([r[3] for r in rows], np.float32)
+    t = to_dev(d)
+    for method in (0, 1):
+        hx, hy, hz, pdf = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                                         u1=torch.from_numpy(u1).cuda(),
+                                         u2=torch.from_numpy(u2).cuda(), method=method)
+        H = np.stack([host(hx), host(hy), host(hz)], 1)
+        P = host(pdf)
+        assert np.all(np.isfinite(H)) and np.all(np.isfinite(P))
+        assert np.allclose(np.linalg.norm(H, axis=1), 1.0, atol=2e-6)
+        # the cap's pdf L^3 / (pi ax ay (1 + zs) |hs|^2) is positive for u2 < 1;
+        # the disk's pdf is proportional to its height above the disk, which
+        # rounds to 0 at the rim in FP32
+        assert np.all(P > 0) if method == 0 else np.all(P >= 0), (method, P.min())
+        h_ref, p_ref = oracle.vndf_sample((d["wx"], d["wy"], d["wz"]), d["ax"], d["ay"],
+                                          u1=u1.astype(np.float64), u2=u2.astype(np.float64),
+                                          method=method)
+        if method == 0:
+            _compare(d, hx, hy, hz, pdf, h_ref, p_ref, "degenerate cap", 0)
+
+
+def test_stream_index_crossing_high_counter_word():
+    """Sample indices around 2^33 (the counter's high word changes there)."""
+    n = 4096
+    d = workloads.tuples_streaming(n, seed=41)
+    t = to_dev(d)
+    base = (1 << 33) - 2048
+    got = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=77, index_base=base)
+    h_ref, p_ref = oracle.vndf_sample((d["wx"], d["wy"], d["wz"]), d["ax"], d["ay"], seed=77,
+                                      index_base=base)
+    _compare(d, *got, h_ref, p_ref, "index 2^33", 0)
