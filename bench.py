@@ -286,7 +286,7 @@ def main():
         tune_s = time.perf_counter() - t0
         steps = max(3, args.steps // 10)
         plan0 = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
-                             with_grad=True, tiling=(256, 32, 8))
+                             with_grad=True, tiling=(256, 32, 8, 0))
         ms_default, _ = timed(plan0.run, steps, 2)
         plan0.close()
         plan = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,

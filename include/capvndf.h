@@ -237,14 +237,17 @@ int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy, co
  * captured once into a HIP graph and replayed by albedo_batch_run.  Job j uses
  * unit j of tag 3, so its values equal albedo_estimate/backward on that job.
  *
- * Tiling: block size, pairs of samples per thread per chunk (multiple of 8)
- * and resident blocks per compute unit.
+ * Tiling: block size, pairs of samples per thread per chunk (multiple of 8),
+ * resident blocks per compute unit, and who owns a chunk: the whole block
+ * (per_wave = 0; block-wide reduction through LDS) or a single wavefront
+ * (per_wave = 1; smaller chunks, wave-only reduction, so short jobs occupy 64
+ * lanes instead of a block).
  */
 typedef struct capvndf_tiling {
-    int32_t block;          /* 256 or 512 threads                            */
-    int32_t pairs_per_thread; /* chunk = block * pairs_per_thread * 2 samples */
-    int32_t blocks_per_cu;  /* persistent grid = CUs * blocks_per_cu          */
-    int32_t reserved;
+    int32_t block;            /* 256 or 512 threads                          */
+    int32_t pairs_per_thread; /* chunk = owner lanes * pairs_per_thread pairs */
+    int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu        */
+    int32_t per_wave;         /* 0: a block owns a chunk; 1: a wavefront does */
 } capvndf_tiling;
 
 typedef struct capvndf_batch_plan capvndf_batch_plan;
@@ -260,7 +263,8 @@ typedef struct capvndf_batch_plan capvndf_batch_plan;
  *   albedo       [njobs]  device out: A_j(F0_j)
  *   grad_ax, grad_ay, grad_theta_o [njobs] device out (ignored if !with_grad)
  *   tiling                NULL: the tuned tiling cached for this problem
- *                         signature (CAPVNDF_TUNE_CACHE file) or a default
+ *                         signature (CAPVNDF_TUNE_CACHE file) or the default
+ *                         {256, 32, 8, 0}
  *   stream                stream used for the capture
  *   out                   receives the plan
  * The plan keeps the pointers: they must stay valid while the plan is used,

@@ -77,15 +77,15 @@ __device__ __forceinline__ void block_reduce_store(Comp (&acc)[NACC], float* __r
 // ---------------------------------------------------------------------------
 // Per-thread sample loops over pairs [pbeg, pend) with stride BLOCK.
 // ---------------------------------------------------------------------------
-template <int BLOCK>
+template <int STRIDE>
 __device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uint64_t pend,
                                           uint64_t nsamples, uint32_t unit, uint32_t k0,
-                                          uint32_t k1, Comp (&acc)[2]) {
-    for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)BLOCK * kGroup) {
+                                          uint32_t k1, Comp (&acc)[2], uint32_t lane = threadIdx.x) {
+    for (uint64_t p0 = pbeg + lane; p0 < pend; p0 += (uint64_t)STRIDE * kGroup) {
         float sg = 0.0f, sgm = 0.0f;
 #pragma unroll 2
         for (int j = 0; j < kGroup; ++j) {
-            const uint64_t p = p0 + (uint64_t)j * BLOCK;
+            const uint64_t p = p0 + (uint64_t)j * STRIDE;
             if (p < pend) {
                 const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
                 const FwdTerm t0 = albedo_fwd(c, unit24(w.w0), unit24(w.w1));
@@ -105,18 +105,19 @@ __device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uin
 
 // Adjoint loop: accumulates w, the direct derivatives and the adjoint of ws,
 // then chains ws into (alpha_x, alpha_y, theta_o).  out = {w, gax, gay, gth}.
-template <int BLOCK>
+template <int STRIDE>
 __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t pbeg,
                                           uint64_t pend, uint64_t nsamples, uint32_t unit,
-                                          uint32_t k0, uint32_t k1, Comp (&out)[4]) {
+                                          uint32_t k0, uint32_t k1, Comp (&out)[4],
+                                          uint32_t lane = threadIdx.x) {
     Comp acc[7];
 #pragma unroll
     for (int a = 0; a < 7; ++a) acc[a] = Comp{0.0f, 0.0f};
-    for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)BLOCK * kGroup) {
+    for (uint64_t p0 = pbeg + lane; p0 < pend; p0 += (uint64_t)STRIDE * kGroup) {
         float part[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll CAPVNDF_ADJ_UNROLL
         for (int j = 0; j < kGroup; ++j) {
-            const uint64_t p = p0 + (uint64_t)j * BLOCK;
+            const uint64_t p = p0 + (uint64_t)j * STRIDE;
             if (p < pend) {
                 const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
                 const AdjTerm t0 = albedo_adj(c, f0, unit24(w.w0), unit24(w.w1));
@@ -271,6 +272,54 @@ __global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch(
             const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
             Comp w[1] = {Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f}};
             block_reduce_store<1, BLOCK>(w, partial + (int64_t)ch * 2);
+        }
+    }
+}
+
+// Per-wave variant: every wavefront owns its static range of (smaller)
+// chunks [wave_chunks[w], wave_chunks[w+1]) and reduces each one with its own
+// butterfly, with no LDS and no barrier -- small jobs then occupy 64 lanes
+// instead of a whole block.
+template <int BLOCK, bool GRAD>
+__global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch_wave(
+    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
+    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
+    const int64_t* __restrict__ nsamp, const int32_t* __restrict__ chunk_job,
+    const int64_t* __restrict__ chunk_pbeg, const int64_t* __restrict__ chunk_pend,
+    const int32_t* __restrict__ wave_chunks, uint32_t k0, uint32_t k1,
+    float* __restrict__ partial) {
+    const uint32_t lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
+    const int32_t cb = wave_chunks[wave];
+    const int32_t ce = wave_chunks[wave + 1];
+    for (int32_t ch = cb; ch < ce; ++ch) {
+        const int32_t j = chunk_job[ch];
+        const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
+        const float f0 = f0p ? f0p[j] : 1.0f;
+        const uint64_t n = (uint64_t)nsamp[j];
+        const uint64_t pbeg = (uint64_t)chunk_pbeg[ch];
+        const uint64_t pend = (uint64_t)chunk_pend[ch];
+        if (GRAD) {
+            Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+            if (c.ok) pairs_adj<64>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out, lane);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) out[a] = wave_reduce(out[a]);
+            if (lane == 0) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    partial[(int64_t)ch * 8 + 2 * a] = out[a].s;
+                    partial[(int64_t)ch * 8 + 2 * a + 1] = out[a].c;
+                }
+            }
+        } else {
+            Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+            if (c.ok) pairs_fwd<64>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc, lane);
+            const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
+            Comp w = wave_reduce(Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f});
+            if (lane == 0) {
+                partial[(int64_t)ch * 2] = w.s;
+                partial[(int64_t)ch * 2 + 1] = w.c;
+            }
         }
     }
 }
@@ -538,7 +587,7 @@ namespace {
 bool valid_tiling(const capvndf_tiling& t) {
     return (t.block == 256 || t.block == 512) && t.pairs_per_thread >= kGroup &&
            t.pairs_per_thread <= 4096 && t.pairs_per_thread % kGroup == 0 &&
-           t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32;
+           t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && (t.per_wave == 0 || t.per_wave == 1);
 }
 
 capvndf_tiling default_tiling() { return capvndf_tiling{256, 32, 8, 0}; }
@@ -559,18 +608,19 @@ std::string problem_signature(int device, int64_t njobs, int64_t total, int with
     return buf;
 }
 
-// Tuning cache: text lines "<signature> <block> <pairs_per_thread> <blocks_per_cu> <ms>".
+// Tuning cache: text lines
+// "<signature> <block> <pairs_per_thread> <blocks_per_cu> <per_wave> <ms>".
 bool cache_lookup(const std::string& sig, capvndf_tiling* out) {
     const char* path = getenv("CAPVNDF_TUNE_CACHE");
     if (!path || !*path) return false;
     FILE* f = fopen(path, "r");
     if (!f) return false;
     char key[256];
-    int b, p, c;
+    int b, p, c, w;
     float ms;
     bool found = false;
-    while (fscanf(f, "%255s %d %d %d %f", key, &b, &p, &c, &ms) == 5) {
-        capvndf_tiling t{b, p, c, 0};
+    while (fscanf(f, "%255s %d %d %d %d %f", key, &b, &p, &c, &w, &ms) == 6) {
+        capvndf_tiling t{b, p, c, w};
         if (sig == key && valid_tiling(t)) {
             *out = t;  // last matching line wins
             found = true;
@@ -585,7 +635,8 @@ void cache_store(const std::string& sig, const capvndf_tiling& t, float ms) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %.6f\n", sig.c_str(), t.block, t.pairs_per_thread, t.blocks_per_cu, ms);
+    fprintf(f, "%s %d %d %d %d %.6f\n", sig.c_str(), t.block, t.pairs_per_thread, t.blocks_per_cu,
+            t.per_wave, ms);
     fclose(f);
 }
 
@@ -595,14 +646,22 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
     const int g = p->with_grad;
     const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
     const dim3 grid((unsigned)p->grid), block((unsigned)p->tiling.block);
-#define CAPVNDF_LAUNCH_BATCH(B, G)                                                                  \
-    hipLaunchKernelGGL((k_batch<B, G>), grid, block, 0, st, p->wox, p->woy, p->woz, p->ax, p->ay, \
+#define CAPVNDF_LAUNCH_BATCH(K, B, G)                                                               \
+    hipLaunchKernelGGL((K<B, G>), grid, block, 0, st, p->wox, p->woy, p->woz, p->ax, p->ay,       \
                        p->f0, p->d_nsamp, p->d_chunk_job, p->d_chunk_pbeg, p->d_chunk_pend,        \
                        p->d_block_chunks, k0, k1, p->d_partial)
-    if (p->tiling.block == 256) {
-        if (g) CAPVNDF_LAUNCH_BATCH(256, true); else CAPVNDF_LAUNCH_BATCH(256, false);
+    if (p->tiling.per_wave) {
+        if (p->tiling.block == 256) {
+            if (g) CAPVNDF_LAUNCH_BATCH(k_batch_wave, 256, true);
+            else CAPVNDF_LAUNCH_BATCH(k_batch_wave, 256, false);
+        } else {
+            if (g) CAPVNDF_LAUNCH_BATCH(k_batch_wave, 512, true);
+            else CAPVNDF_LAUNCH_BATCH(k_batch_wave, 512, false);
+        }
+    } else if (p->tiling.block == 256) {
+        if (g) CAPVNDF_LAUNCH_BATCH(k_batch, 256, true); else CAPVNDF_LAUNCH_BATCH(k_batch, 256, false);
     } else {
-        if (g) CAPVNDF_LAUNCH_BATCH(512, true); else CAPVNDF_LAUNCH_BATCH(512, false);
+        if (g) CAPVNDF_LAUNCH_BATCH(k_batch, 512, true); else CAPVNDF_LAUNCH_BATCH(k_batch, 512, false);
     }
 #undef CAPVNDF_LAUNCH_BATCH
     if (int32_t rc = check_launch("batch kernel launch")) return rc;
@@ -664,7 +723,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
         if (!valid_tiling(*tiling))
             return fail(CAPVNDF_ERR_BAD_ARG,
                         "albedo_batch_plan_create: invalid tiling (block 256|512, pairs_per_thread "
-                        "a multiple of 8 in [8, 4096], blocks_per_cu in [1, 32])");
+                        "a multiple of 8 in [8, 4096], blocks_per_cu in [1, 32], per_wave 0|1)");
         t = *tiling;
     } else {
         (void)cache_lookup(problem_signature(device, njobs, total, with_grad), &t);
@@ -674,8 +733,9 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
                                "hipDeviceGetAttribute"))
         return rc;
 
-    // Chunk table: job-major, pair ranges of chunk_pairs.
-    const int64_t chunk_pairs = (int64_t)t.block * t.pairs_per_thread;
+    // Chunk table: job-major, pair ranges of chunk_pairs (one block's or, per
+    // wave, one wavefront's lanes times pairs_per_thread).
+    const int64_t chunk_pairs = (int64_t)(t.per_wave ? 64 : t.block) * t.pairs_per_thread;
     std::vector<int32_t> chunk_job;
     std::vector<int64_t> pbeg, pend;
     std::vector<int32_t> job_chunks((size_t)njobs + 1, 0);
@@ -693,24 +753,27 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     job_chunks[njobs] = (int32_t)chunk_job.size();
     const int64_t nchunks = (int64_t)chunk_job.size();
 
-    // Static partition of the chunks over a persistent grid, balanced by pairs.
+    // Static partition of the chunks over the persistent grid's owners (its
+    // blocks, or its wavefronts per wave), balanced by pairs.
+    const int64_t waves_per_block = t.per_wave ? t.block / 64 : 1;
     int64_t grid = std::max<int64_t>(1, (int64_t)cus * t.blocks_per_cu);
-    if (nchunks > 0) grid = std::min<int64_t>(grid, nchunks);
-    std::vector<int32_t> block_chunks((size_t)grid + 1, 0);
+    if (nchunks > 0) grid = std::min<int64_t>(grid, (nchunks + waves_per_block - 1) / waves_per_block);
+    const int64_t owners = grid * waves_per_block;
+    std::vector<int32_t> block_chunks((size_t)owners + 1, 0);
     {
         double sum = 0.0;
         for (int64_t c = 0; c < nchunks; ++c) sum += (double)(pend[c] - pbeg[c]);
         double acc = 0.0;
         int64_t c = 0;
-        for (int64_t b = 0; b < grid; ++b) {
+        for (int64_t b = 0; b < owners; ++b) {
             block_chunks[b] = (int32_t)c;
-            const double target = sum * (double)(b + 1) / (double)grid;
-            while (c < nchunks && (acc + 0.5 * (double)(pend[c] - pbeg[c]) <= target || b == grid - 1)) {
+            const double target = sum * (double)(b + 1) / (double)owners;
+            while (c < nchunks && (acc + 0.5 * (double)(pend[c] - pbeg[c]) <= target || b == owners - 1)) {
                 acc += (double)(pend[c] - pbeg[c]);
                 ++c;
             }
         }
-        block_chunks[grid] = (int32_t)nchunks;
+        block_chunks[owners] = (int32_t)nchunks;
     }
 
     // Device memory: tables, partials, per-request scratch.
@@ -725,7 +788,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     const size_t o_cj = carve(sizeof(int32_t) * std::max<int64_t>(nchunks, 1));
     const size_t o_pb = carve(sizeof(int64_t) * std::max<int64_t>(nchunks, 1));
     const size_t o_pe = carve(sizeof(int64_t) * std::max<int64_t>(nchunks, 1));
-    const size_t o_bc = carve(sizeof(int32_t) * (size_t)(grid + 1));
+    const size_t o_bc = carve(sizeof(int32_t) * (size_t)(owners + 1));
     const size_t o_jc = carve(sizeof(int32_t) * (size_t)(njobs + 1));
     const size_t o_ns = carve(sizeof(int64_t) * (size_t)njobs);
     const size_t o_pa = carve(sizeof(float) * 2 * nacc * (size_t)std::max<int64_t>(nchunks, 1));
@@ -751,7 +814,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
         if (!rc) rc = check_hip(hipMemcpy(p->d_chunk_pbeg, pbeg.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice), "hipMemcpy");
         if (!rc) rc = check_hip(hipMemcpy(p->d_chunk_pend, pend.data(), sizeof(int64_t) * nchunks, hipMemcpyHostToDevice), "hipMemcpy");
     }
-    if (!rc) rc = check_hip(hipMemcpy(p->d_block_chunks, block_chunks.data(), sizeof(int32_t) * (grid + 1), hipMemcpyHostToDevice), "hipMemcpy");
+    if (!rc) rc = check_hip(hipMemcpy(p->d_block_chunks, block_chunks.data(), sizeof(int32_t) * (owners + 1), hipMemcpyHostToDevice), "hipMemcpy");
     if (!rc) rc = check_hip(hipMemcpy(p->d_job_chunks, job_chunks.data(), sizeof(int32_t) * (njobs + 1), hipMemcpyHostToDevice), "hipMemcpy");
     if (!rc) rc = check_hip(hipMemcpy(p->d_nsamp, nsamples_host, sizeof(int64_t) * njobs, hipMemcpyHostToDevice), "hipMemcpy");
     if (rc) {
@@ -861,8 +924,9 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
     if (best == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_autotune: best is NULL");
     const hipStream_t st = as_stream(stream);
     const int blocks[] = {256, 512};
-    const int ppts[] = {8, 16, 32, 64};
+    const int ppts[] = {8, 16, 32, 64, 128};
     const int bpcs[] = {2, 4, 8, 16};
+    const int modes[] = {0, 1};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int32_t rc = check_hip(hipEventCreate(&e0), "hipEventCreate");
     if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
@@ -870,12 +934,14 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
     capvndf_tiling best_tiling = default_tiling();
     int64_t total = 0;
     for (int64_t j = 0; j < njobs && nsamples_host; ++j) total += nsamples_host[j];
+    for (int mode : modes) {
     for (int b : blocks) {
         for (int ppt : ppts) {
             for (int bpc : bpcs) {
                 if (rc) break;
                 if (b == 512 && bpc > 8) continue;
-                capvndf_tiling t{b, ppt, bpc, 0};
+                if (mode == 0 && ppt > 64) continue;
+                capvndf_tiling t{b, ppt, bpc, mode};
                 capvndf_batch_plan* p = nullptr;
                 rc = create_plan(njobs, wox, woy, woz, ax, ay, f0, nsamples_host, seed, with_grad,
                                  albedo, grad_ax, grad_ay, grad_theta_o, &t, &p);
@@ -896,6 +962,7 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
                 }
             }
         }
+    }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

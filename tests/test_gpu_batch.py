@@ -40,7 +40,8 @@ def _check(plan, j, f0, with_grad):
             assert np.all(d <= 1e-4 + 1e-3 * np.abs(ref)), np.max(d / (1e-4 + 1e-3 * np.abs(ref)))
 
 
-@pytest.mark.parametrize("tiling", [None, (256, 8, 2), (512, 16, 4), (256, 64, 16)])
+@pytest.mark.parametrize("tiling", [None, (256, 8, 2), (512, 16, 4), (256, 64, 16),
+                                    (256, 8, 4, 1), (512, 128, 8, 1), (256, 32, 16, 1)])
 def test_batch_matches_oracle(tiling):
     j = _jobs(97, seed=5)
     t = to_dev({k: v for k, v in j.items() if k != "n"})
@@ -55,10 +56,12 @@ def test_batch_matches_oracle(tiling):
     plan.close()
 
 
-def test_batch_forward_only():
+@pytest.mark.parametrize("tiling", [None, (256, 16, 4, 1)])
+def test_batch_forward_only(tiling):
     j = _jobs(50, seed=6)
     t = to_dev({k: v for k, v in j.items() if k != "n"})
-    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=False)
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=False,
+                        tiling=tiling)
     plan.run()
     torch.cuda.synchronize()
     _check(plan, j, 1.0, False)
@@ -113,9 +116,9 @@ def test_autotune_small(tmp_path, monkeypatch):
     j = _jobs(32, seed=8, lo=8, hi=14)
     t = to_dev({k: v for k, v in j.items() if k != "n"})
     best, ms = cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
-    assert best[0] in (256, 512) and best[1] % 8 == 0 and ms > 0
+    assert best[0] in (256, 512) and best[1] % 8 == 0 and best[3] in (0, 1) and ms > 0
     text = (tmp_path / "tune.txt").read_text().split()
-    assert [int(x) for x in text[1:4]] == list(best)
+    assert [int(x) for x in text[1:5]] == list(best)
     plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
     assert plan.info()["tiling"] == best   # picked up from the cache
     plan.run()
