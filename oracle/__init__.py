@@ -33,6 +33,7 @@ _THREADS = int(os.environ.get("CAPVNDF_ORACLE_THREADS", "0"))
 
 TAG_SAMPLE = 2
 TAG_ALBEDO = 3
+TAG_DIELECTRIC = 5
 CAP = 0
 DISK2018 = 1
 
@@ -54,6 +55,7 @@ _lib = None
 _d = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.POINTER(ctypes.c_int64)
 _u32 = ctypes.POINTER(ctypes.c_uint32)
+_i32 = ctypes.POINTER(ctypes.c_int32)
 
 
 def _load():
@@ -109,6 +111,18 @@ def _load():
     lib.orc_vndf_inverse.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d,
                                      ctypes.c_int32]
     lib.orc_vndf_inverse.restype = ctypes.c_int32
+    lib.orc_dielectric_sample.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, ctypes.c_double,
+                                          _d, _d, _d, ctypes.c_uint64, ctypes.c_uint64,
+                                          _d, _d, _d, _d, _d, _i32, _d, _d, _d, ctypes.c_int32]
+    lib.orc_dielectric_sample.restype = ctypes.c_int32
+    lib.orc_dielectric_eval.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _d, _d, _d,
+                                        ctypes.c_double, _d, _d, ctypes.c_int32]
+    lib.orc_dielectric_eval.restype = ctypes.c_int32
+    lib.orc_fresnel_dielectric.argtypes = [ctypes.c_int64, _d, ctypes.c_double, _d]
+    lib.orc_fresnel_dielectric.restype = None
+    lib.orc_dielectric_uniforms.argtypes = [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+                                            _d, _d, _d]
+    lib.orc_dielectric_uniforms.restype = None
     lib.orc_hardware_threads.argtypes = []
     lib.orc_hardware_threads.restype = ctypes.c_int32
     _lib = lib
@@ -342,3 +356,61 @@ def vndf_inverse(wi, h, ax, ay, nthreads=0):
     if rc != 0:
         raise ValueError("orc_vndf_inverse failed")
     return u1, u2
+
+
+def dielectric_sample(wi, ax, ay, eta, u=None, seed=0, index_base=0, nthreads=0):
+    """Rough-dielectric sampler: a cap-sampled visible normal h (Sec. 3.3), the
+    lobe from u3 against the Fresnel reflectance, then reflection or Snell
+    refraction about h (Walter et al. 2007).  ``u`` is None (dielectric Philox
+    stream) or (u1, u2, u3).  Returns a dict with wo[n,3], pdf, weight
+    (= f |wo.n| / pdf), lobe (0 reflect, 1 transmit, -1 outside the domain)
+    and h[n,3]."""
+    wi = [_f64(c) for c in wi]
+    n = wi[0].shape[0]
+    ax = _f64(ax, n)
+    ay = _f64(ay, n)
+    us = [None, None, None] if u is None else [_f64(c, n) for c in u]
+    wo = [np.zeros(n) for _ in range(3)]
+    h = [np.zeros(n) for _ in range(3)]
+    pdf = np.zeros(n)
+    weight = np.zeros(n)
+    lobe = np.zeros(n, dtype=np.int32)
+    rc = _load().orc_dielectric_sample(
+        n, *[_p(c) for c in wi], _p(ax), _p(ay), float(eta), *[_p(c) for c in us], seed,
+        index_base, *[_p(c) for c in wo], _p(pdf), _p(weight),
+        lobe.ctypes.data_as(_i32), *[_p(c) for c in h], _nt(nthreads))
+    if rc != 0:
+        raise ValueError("orc_dielectric_sample failed (eta must be > 0 and != 1)")
+    return {"wo": np.stack(wo, axis=-1), "pdf": pdf, "weight": weight, "lobe": lobe,
+            "h": np.stack(h, axis=-1)}
+
+
+def dielectric_eval(wi, wo, ax, ay, eta, nthreads=0):
+    """(pdf, bsdf) of the rough dielectric at caller-given directions
+    (Walter et al. 2007, BSDF and half-vector Jacobians)."""
+    wi = [_f64(c) for c in wi]
+    n = wi[0].shape[0]
+    wo = [_f64(c) for c in wo]
+    pdf = np.zeros(n)
+    bsdf = np.zeros(n)
+    rc = _load().orc_dielectric_eval(n, *[_p(c) for c in wi], *[_p(c) for c in wo],
+                                     _p(_f64(ax, n)), _p(_f64(ay, n)), float(eta), _p(pdf),
+                                     _p(bsdf), _nt(nthreads))
+    if rc != 0:
+        raise ValueError("orc_dielectric_eval failed (eta must be > 0 and != 1)")
+    return pdf, bsdf
+
+
+def fresnel_dielectric(cos_i, eta):
+    """Unpolarised Fresnel reflectance of a smooth dielectric interface."""
+    c = _f64(cos_i).ravel()
+    out = np.zeros(c.shape[0])
+    _load().orc_fresnel_dielectric(c.shape[0], _p(c), float(eta), _p(out))
+    return out
+
+
+def dielectric_uniforms(n, seed, index_base=0):
+    """(u1, u2, u3) of the dielectric stream for tuples index_base .. + n - 1."""
+    u = [np.zeros(n) for _ in range(3)]
+    _load().orc_dielectric_uniforms(n, seed, index_base, *[_p(c) for c in u])
+    return tuple(u)

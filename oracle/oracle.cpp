@@ -24,7 +24,10 @@
 //   * its gradient by forward-mode dual numbers (exact derivative of this
 //     same program) and by central finite differences;
 //   * the same estimator with a non-constant incident radiance (a sum of
-//     spherical-Gaussian lobes), i.e. the direct-illumination integral.
+//     spherical-Gaussian lobes), i.e. the direct-illumination integral;
+//   * a rough dielectric (reflection and transmission) sampled with the same
+//     VNDF, after Walter et al. 2007, whom the paper cites for it: Fresnel
+//     equations, Snell's law, generalised half vector and its Jacobian.
 //
 // Readings where the paper is silent (each also listed in the design doc):
 //   * u1 drives the azimuth and u2 the height, exactly as the cap listing.
@@ -38,6 +41,10 @@
 //     still count in N.
 //   * Inputs outside the domain (w_z <= 0, alpha <= 0) give h = (0,0,1)
 //     and pdf = 0; albedo cells with wo_z <= 0 give 0 and zero gradient.
+//   * Dielectric: eta = n_lower / n_upper with wi above; lobe chosen by a third
+//     uniform u3 < F (reflect); uniforms from one Philox block per sample
+//     (counter (lo32(k), unit, 5, hi32(k)), words 0..2); the transmission G2
+//     is the same height-correlated combination as for reflection.
 //   * grad_theta_o is the derivative along the meridian of wo at fixed
 //     azimuth: dwo/dtheta = (cos t cos p, cos t sin p, -sin t); at the pole
 //     the azimuth is taken as 0.
@@ -420,6 +427,163 @@ double radiance_term(const Vec3<double>& wa, double ax, double ay, double u1, do
     return radiance(normalize(wb), params, nlobes) * fr * wb.z / pdf;
 }
 
+
+// ---------------------------------------------------------------------------
+// Rough dielectric interface (reflection and transmission) sampled with the
+// same VNDF.  The paper applies its sampler to rough dielectrics but states
+// the transmission model only by reference to Walter, Marschner, Li and
+// Torrance, "Microfacet models for refraction through rough surfaces"
+// (EGSR 2007); the routines below follow that paper's definitions, in its
+// notation, with wi on the upper side (index of refraction 1) and eta the
+// relative index n_lower / n_upper.
+// ---------------------------------------------------------------------------
+
+const uint32_t kTagDielectric = 5;  // dielectric_sample tuples, unit 0, k = tuple index
+
+// The three uniforms of sample k of the dielectric stream: one Philox block
+// per sample, counter (lo32(k), unit, tag, hi32(k)), words 0, 1, 2.
+void dielectric_uniforms(uint64_t seed, uint32_t unit, uint64_t k, double* u1, double* u2,
+                         double* u3) {
+    uint32_t ctr[4] = {(uint32_t)k, unit, kTagDielectric, (uint32_t)(k >> 32)};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    philox4x32_10(ctr, key, w);
+    *u1 = word_to_unit(w[0]);
+    *u2 = word_to_unit(w[1]);
+    *u3 = word_to_unit(w[2]);
+}
+
+// Unpolarised Fresnel reflectance of a smooth dielectric interface (the
+// Fresnel equations): light arrives at cosine cos_i > 0 from the side of
+// index n_i and refracts into index n_t, eta = n_t / n_i.  The s- and
+// p-polarised amplitude ratios are
+//   r_s = (n_i cos_i - n_t cos_t) / (n_i cos_i + n_t cos_t),
+//   r_p = (n_t cos_i - n_i cos_t) / (n_t cos_i + n_i cos_t),
+// with Snell's law n_i sin_i = n_t sin_t; R = (r_s^2 + r_p^2) / 2, and R = 1
+// under total internal reflection.
+double fresnel_dielectric(double cos_i, double eta) {
+    double sin_i2 = std::max(0.0, 1.0 - cos_i * cos_i);
+    double sin_t2 = sin_i2 / (eta * eta);
+    if (sin_t2 >= 1.0) return 1.0;
+    double cos_t = std::sqrt(1.0 - sin_t2);
+    double rs = (cos_i - eta * cos_t) / (cos_i + eta * cos_t);
+    double rp = (eta * cos_i - cos_t) / (eta * cos_i + cos_t);
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+// Smith G1 for a direction on either side of the surface (Walter et al.,
+// Eq. (23) for GGX): chi+((v . m) / (v . n)) times the monostatic term of the
+// unsigned direction, written here in the paper's hemisphere form
+// z_std / sigma_std of the flipped-up direction.
+double smith_g1_two_sided(const Vec3<double>& wm, const Vec3<double>& v, double ax, double ay) {
+    if (v.z == 0.0) return 0.0;
+    if (!(dot(v, wm) / v.z > 0.0)) return 0.0;
+    Vec3<double> up = v.z > 0.0 ? v : Vec3<double>{-v.x, -v.y, -v.z};
+    Vec3<double> up_std = normalize(Vec3<double>{up.x * ax, up.y * ay, up.z});
+    return up_std.z / sigma_std(up_std);
+}
+
+// Height-correlated G2 built from the two one-sided terms, as in the
+// paper's Appendix A (the same combination for both lobes).
+double smith_g2_two_sided(const Vec3<double>& wm, const Vec3<double>& wi, const Vec3<double>& wo,
+                          double ax, double ay) {
+    double gi = smith_g1_two_sided(wm, wi, ax, ay);
+    double go = smith_g1_two_sided(wm, wo, ax, ay);
+    double den = gi + go - gi * go;
+    if (!(den > 0.0)) return 0.0;
+    return gi * go / den;
+}
+
+// Half vector of a pair (wi, wo): h_r = wi + wo for reflection (wo above the
+// surface), the generalised h_t = -(wi + eta wo) for transmission (Walter et
+// al., Eqs. (13) and (16)); normalised and turned to the upper side.
+Vec3<double> dielectric_half(const Vec3<double>& wi, const Vec3<double>& wo, double eta) {
+    Vec3<double> h = wo.z > 0.0 ? Vec3<double>{wi.x + wo.x, wi.y + wo.y, wi.z + wo.z}
+                                : Vec3<double>{-(wi.x + eta * wo.x), -(wi.y + eta * wo.y),
+                                               -(wi.z + eta * wo.z)};
+    h = normalize(h);
+    if (h.z < 0.0) h = Vec3<double>{-h.x, -h.y, -h.z};
+    return h;
+}
+
+// BSDF of the rough dielectric (Walter et al., Eqs. (20) and (21)), radiance
+// scaling by eta^2 included in the transmission term as printed there:
+//   f_r = F G2 D / (4 |wi.n| |wo.n|),
+//   f_t = |wi.h| |wo.h| / (|wi.n| |wo.n|) * eta^2 (1 - F) G2 D / (wi.h + eta wo.h)^2.
+double dielectric_bsdf(const Vec3<double>& wi, const Vec3<double>& wo, double ax, double ay,
+                       double eta) {
+    if (!(wi.z > 0.0) || wo.z == 0.0) return 0.0;
+    Vec3<double> h = dielectric_half(wi, wo, eta);
+    double ci = dot(wi, h), co = dot(wo, h);
+    if (!(ci > 0.0)) return 0.0;
+    double f = fresnel_dielectric(ci, eta);
+    double g2 = smith_g2_two_sided(h, wi, wo, ax, ay);
+    double d = ggx_ndf(h, ax, ay);
+    if (wo.z > 0.0) return f * g2 * d / (4.0 * wi.z * wo.z);
+    if (!(co < 0.0)) return 0.0;
+    double den = ci + eta * co;
+    return std::fabs(ci) * std::fabs(co) / (wi.z * std::fabs(wo.z)) * eta * eta * (1.0 - f) *
+           g2 * d / (den * den);
+}
+
+// Density of the dielectric sampler at wo (solid angle): the lobe's selection
+// probability (F or 1 - F) times the VNDF of Eq. (1) at the half vector times
+// the Jacobian |dh/dwo| of Walter et al., Eqs. (14) and (17):
+//   reflection 1 / (4 |wo.h|),  transmission eta^2 |wo.h| / (wi.h + eta wo.h)^2.
+double dielectric_pdf(const Vec3<double>& wi, const Vec3<double>& wo, double ax, double ay,
+                      double eta) {
+    if (!(wi.z > 0.0) || !(ax > 0.0) || !(ay > 0.0) || wo.z == 0.0) return 0.0;
+    Vec3<double> h = dielectric_half(wi, wo, eta);
+    double ci = dot(wi, h), co = dot(wo, h);
+    if (!(ci > 0.0)) return 0.0;
+    double f = fresnel_dielectric(ci, eta);
+    double dv = vndf_pdf(h, wi, ax, ay);
+    if (wo.z > 0.0) return f * dv / (4.0 * std::fabs(co));
+    if (!(co < 0.0)) return 0.0;
+    double den = ci + eta * co;
+    return (1.0 - f) * dv * eta * eta * std::fabs(co) / (den * den);
+}
+
+struct DielectricSample {
+    Vec3<double> h, wo;
+    double pdf, weight;
+    int lobe;  // 0 reflection, 1 transmission
+};
+
+// The sampler: a visible normal h from the spherical-cap VNDF sampler, the
+// lobe from u3 against the Fresnel reflectance at wi . h (reflect if u3 < F),
+// then the mirror direction 2 (wi.h) h - wi or the refracted direction of
+// Snell's law in vector form (Walter et al., Eq. (40)),
+//   wo = (c / eta - sqrt(1 - (1 - c^2) / eta^2)) h - wi / eta,  c = wi . h.
+// A direction on the wrong side of the surface for its lobe is no sample
+// (pdf 0, weight 0).  weight = f |wo.n| / pdf.
+DielectricSample dielectric_sample(double u1, double u2, double u3, const Vec3<double>& wi,
+                                   double ax, double ay, double eta) {
+    DielectricSample s;
+    s.h = sample_vndf(u1, u2, wi, ax, ay, 0);
+    double c = dot(wi, s.h);
+    double f = fresnel_dielectric(c, eta);
+    bool valid;
+    if (u3 < f) {
+        s.lobe = 0;
+        s.wo = Vec3<double>{2.0 * c * s.h.x - wi.x, 2.0 * c * s.h.y - wi.y, 2.0 * c * s.h.z - wi.z};
+        valid = s.wo.z > 0.0;
+    } else {
+        s.lobe = 1;
+        double k = std::sqrt(1.0 - (1.0 - c * c) / (eta * eta));
+        double a = c / eta - k;
+        s.wo = Vec3<double>{a * s.h.x - wi.x / eta, a * s.h.y - wi.y / eta, a * s.h.z - wi.z / eta};
+        valid = s.wo.z < 0.0;
+    }
+    s.pdf = 0.0;
+    s.weight = 0.0;
+    if (valid) {
+        s.pdf = dielectric_pdf(wi, s.wo, ax, ay, eta);
+        if (s.pdf > 0.0) s.weight = dielectric_bsdf(wi, s.wo, ax, ay, eta) * std::fabs(s.wo.z) / s.pdf;
+    }
+    return s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -663,6 +827,70 @@ int32_t orc_vndf_inverse(int64_t n, const double* wix, const double* wiy, const 
         u1[i] = t < 0.0 ? t + 1.0 : t;
     });
     return 0;
+}
+
+// Rough-dielectric sampler over tuples (wi, alpha) with one relative index
+// eta: outputs wo, the pdf at wo, the weight f |wo.n| / pdf, the lobe (0
+// reflection, 1 transmission) and the visible normal h.  Uniforms are given
+// (u1, u2, u3 all non-NULL) or drawn from the dielectric stream.  Inputs
+// outside the domain (wi_z <= 0, alpha <= 0) give wo = (0, 0, 1), h = (0, 0, 1),
+// pdf = weight = 0, lobe = -1.
+int32_t orc_dielectric_sample(int64_t n, const double* wix, const double* wiy, const double* wiz,
+                              const double* ax, const double* ay, double eta, const double* u1,
+                              const double* u2, const double* u3, uint64_t seed,
+                              uint64_t index_base, double* wox, double* woy, double* woz,
+                              double* pdf, double* weight, int32_t* lobe, double* hx, double* hy,
+                              double* hz, int32_t nthreads) {
+    if (n < 0 || !(eta > 0.0) || eta == 1.0) return -1;
+    if ((u1 == nullptr) != (u2 == nullptr) || (u1 == nullptr) != (u3 == nullptr)) return -1;
+    parallel_for(n, nthreads, [&](int64_t i) {
+        Vec3<double> wi{wix[i], wiy[i], wiz[i]};
+        double a = ax[i], b = ay[i];
+        double r1, r2, r3;
+        if (u1 != nullptr) {
+            r1 = u1[i]; r2 = u2[i]; r3 = u3[i];
+        } else {
+            dielectric_uniforms(seed, 0u, index_base + (uint64_t)i, &r1, &r2, &r3);
+        }
+        if (!(wi.z > 0.0) || !(a > 0.0) || !(b > 0.0)) {
+            wox[i] = 0.0; woy[i] = 0.0; woz[i] = 1.0;
+            pdf[i] = 0.0; weight[i] = 0.0; lobe[i] = -1;
+            if (hx) { hx[i] = 0.0; hy[i] = 0.0; hz[i] = 1.0; }
+            return;
+        }
+        DielectricSample s = dielectric_sample(r1, r2, r3, wi, a, b, eta);
+        wox[i] = s.wo.x; woy[i] = s.wo.y; woz[i] = s.wo.z;
+        pdf[i] = s.pdf; weight[i] = s.weight; lobe[i] = s.lobe;
+        if (hx) { hx[i] = s.h.x; hy[i] = s.h.y; hz[i] = s.h.z; }
+    });
+    return 0;
+}
+
+// Dielectric pdf and BSDF at caller-given (wi, wo, alpha), one eta; either
+// output may be NULL.
+int32_t orc_dielectric_eval(int64_t n, const double* wix, const double* wiy, const double* wiz,
+                            const double* wox, const double* woy, const double* woz,
+                            const double* ax, const double* ay, double eta, double* pdf,
+                            double* bsdf, int32_t nthreads) {
+    if (n < 0 || !(eta > 0.0) || eta == 1.0) return -1;
+    parallel_for(n, nthreads, [&](int64_t i) {
+        Vec3<double> wi{wix[i], wiy[i], wiz[i]}, wo{wox[i], woy[i], woz[i]};
+        if (pdf) pdf[i] = dielectric_pdf(wi, wo, ax[i], ay[i], eta);
+        if (bsdf) bsdf[i] = (ax[i] > 0.0 && ay[i] > 0.0) ? dielectric_bsdf(wi, wo, ax[i], ay[i], eta) : 0.0;
+    });
+    return 0;
+}
+
+// Unpolarised Fresnel reflectance, element-wise.
+void orc_fresnel_dielectric(int64_t n, const double* cos_i, double eta, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = fresnel_dielectric(cos_i[i], eta);
+}
+
+// Raw uniforms of the dielectric stream (tuple indices index_base + i).
+void orc_dielectric_uniforms(int64_t n, uint64_t seed, uint64_t index_base, double* u1,
+                             double* u2, double* u3) {
+    for (int64_t i = 0; i < n; ++i)
+        dielectric_uniforms(seed, 0u, index_base + (uint64_t)i, u1 + i, u2 + i, u3 + i);
 }
 
 int32_t orc_hardware_threads(void) {

@@ -17,7 +17,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_sampler.py", "tests/test_oracle_pdf.py",
-        "tests/test_oracle_albedo.py", "tests/test_oracle_radiance.py"]
+        "tests/test_oracle_albedo.py", "tests/test_oracle_radiance.py",
+        "tests/test_oracle_dielectric.py"]
 
 # (name, text in oracle.cpp, replacement)
 MUTANTS = [
@@ -39,7 +40,8 @@ MUTANTS = [
     ("cross-section area", "T sigma_std(const Vec3<T>& wi) { return (T(1.0) + wi.z) / 2.0; }",
      "T sigma_std(const Vec3<T>& wi) { return (T(1.0) + wi.z); }"),
     ("NDF determinant", "T det = T(1.0) / (ax * ay);\n    T len2", "T det = ax * ay;\n    T len2"),
-    ("G2 uncorrelated", "return gi * go / den;", "return gi * go;"),
+    ("G2 uncorrelated", "if (!(value(den) > 0.0)) return T(0.0);\n    return gi * go / den;",
+     "if (!(value(den) > 0.0)) return T(0.0);\n    return gi * go;"),
     ("Fresnel power", "return f0 + (1.0 - f0) * (m2 * m2 * m);", "return f0 + (1.0 - f0) * (m2 * m2);"),
     ("reflection sign", "Vec3<T> wb{2.0 * c * wm.x - wa.x, 2.0 * c * wm.y - wa.y, 2.0 * c * wm.z - wa.z};",
      "Vec3<T> wb{2.0 * c * wm.x + wa.x, 2.0 * c * wm.y + wa.y, 2.0 * c * wm.z - wa.z};"),
@@ -59,6 +61,25 @@ MUTANTS = [
      "u2[i] = 1.0 - (c.z - wi_std.z) / (1.0 + wi_std.z);"),
     ("radiance at the view", "return radiance(normalize(wb), params, nlobes) * fr * wb.z / pdf;",
      "return radiance(wa, params, nlobes) * fr * wb.z / pdf;"),
+    # rough dielectric
+    ("Fresnel p-amplitude", "double rp = (eta * cos_i - cos_t) / (eta * cos_i + cos_t);",
+     "double rp = (cos_i - eta * cos_t) / (cos_i + eta * cos_t);"),
+    ("Fresnel Snell ratio", "double sin_t2 = sin_i2 / (eta * eta);", "double sin_t2 = sin_i2 / eta;"),
+    ("refraction index inverted", "double a = c / eta - k;", "double a = c * eta - k;"),
+    ("lobe choice inverted", "if (u3 < f) {", "if (u3 > f) {"),
+    ("transmission Jacobian eta^2", "return (1.0 - f) * dv * eta * eta * std::fabs(co) / (den * den);",
+     "return (1.0 - f) * dv * std::fabs(co) / (den * den);"),
+    ("reflection Jacobian", "if (wo.z > 0.0) return f * dv / (4.0 * std::fabs(co));",
+     "if (wo.z > 0.0) return f * dv / (2.0 * std::fabs(co));"),
+    ("BTDF eta^2", "(wi.z * std::fabs(wo.z)) * eta * eta * (1.0 - f) *",
+     "(wi.z * std::fabs(wo.z)) * (1.0 - f) *"),
+    ("generalised half vector", "-(wi.x + eta * wo.x), -(wi.y + eta * wo.y),",
+     "-(wi.x + wo.x / eta), -(wi.y + wo.y / eta),"),
+    ("two-sided G1 side test", "if (!(dot(v, wm) / v.z > 0.0)) return 0.0;",
+     "if (!(dot(v, wm) > 0.0)) return 0.0;"),
+    ("dielectric G2 uncorrelated", "if (!(den > 0.0)) return 0.0;\n    return gi * go / den;",
+     "if (!(den > 0.0)) return 0.0;\n    return gi * go;"),
+    ("dielectric stream word", "*u3 = word_to_unit(w[2]);", "*u3 = word_to_unit(w[3]);"),
 ]
 
 
