@@ -28,7 +28,8 @@ METRIC = ("Gsamples/s VNDF (cap vs 2018 disk) + albedo-LUT fwd+bwd time at "
 N_STREAM = 1 << 26
 BYTES_PER_SAMPLE = 36  # 5 FP32 inputs read + 4 FP32 outputs written
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("stream", "disk", "probe", "inverse", "micro", "lut", "grad", "batch", "radiance")
+SECTIONS = ("stream", "disk", "probe", "inverse", "dielectric", "micro", "lut", "grad", "batch",
+            "radiance")
 
 
 def log(msg):
@@ -193,6 +194,26 @@ def main():
                               "gbytes_per_s": round(40 * N_STREAM / ms_i / 1e6, 1),
                               "bytes_per_sample": 40}
         del u1b, u2b
+    if "dielectric" in only:
+        log("timing the rough-dielectric sampler and its pdf (eta = 1.5)")
+        douts = (outs[0], outs[1], outs[2], outs[3], torch.empty_like(t["wx"]))
+        ms_ds, _ = timed(lambda: cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                                                      1.5, seed=1, out=douts),
+                         args.steps, args.warmup)
+        ms_dp, _ = timed(lambda: cv.dielectric_pdf(t["wx"], t["wy"], t["wz"], douts[0], douts[1],
+                                                   douts[2], t["ax"], t["ay"], 1.5, out=douts[4]),
+                         args.steps, args.warmup)
+        out["dielectric"] = {
+            "eta": 1.5,
+            "sample": {"ms_per_launch": round(ms_ds, 5),
+                       "gsamples_per_s": round(N_STREAM / ms_ds / 1e6, 3),
+                       "gbytes_per_s": round(40 * N_STREAM / ms_ds / 1e6, 1),
+                       "bytes_per_sample": 40},
+            "pdf": {"ms_per_launch": round(ms_dp, 5),
+                    "gsamples_per_s": round(N_STREAM / ms_dp / 1e6, 3),
+                    "gbytes_per_s": round(36 * N_STREAM / ms_dp / 1e6, 1),
+                    "bytes_per_sample": 36}}
+        del douts
     if "micro" in only:
         log("timing the register-resident microbenchmark")
         lanes = 256 * 2048 * 4

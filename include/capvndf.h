@@ -122,6 +122,56 @@ int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float*
                      const float* ay, float* u1, float* u2, void* stream);
 
 /*
+ * dielectric_sample -- sampling of a rough dielectric interface (reflection
+ * and transmission) with the same spherical-cap VNDF sampler.  The paper
+ * benchmarks its sampler on rough dielectrics and takes their model from
+ * Walter et al. 2007: a visible normal h is drawn from the VNDF seen from wi
+ * (Sec. 3.3), the lobe is reflection with probability F (unpolarised Fresnel
+ * reflectance at wi . h, 1 under total internal reflection), and wi is then
+ * reflected (wo = 2 (wi.h) h - wi) or refracted by Snell's law about h.
+ *
+ *   n            number of tuples (>= 0)
+ *   wix,wiy,wiz  unit incident directions on the upper side, w_z > 0      [n]
+ *   ax, ay       roughness                                               [n]
+ *   eta          relative index of refraction n_lower / n_upper: finite,
+ *                > 0 and != 1 (1.5 for glass seen from air, 1/1.5 for air
+ *                seen from inside glass with the frame flipped)
+ *   seed, index_base  Philox key and stream offset: tuple i uses the block
+ *                with counter (lo32(k), 0, 5, hi32(k)), k = index_base + i,
+ *                u1, u2, u3 from its words 0, 1, 2 (u3 chooses the lobe)
+ *   wox,woy,woz  out: unit outgoing directions                           [n]
+ *   pdf          out: density of wo per unit solid angle, the lobe
+ *                probability times the VNDF times |dh/dwo|               [n]
+ *   weight       out: f |wo_z| / pdf = G2(wi, wo) / G1(wi), with the BTDF of
+ *                Walter et al. (its eta^2 factor included, i.e. no
+ *                radiance rescaling by 1/eta^2)                          [n]
+ * A reflected direction below the surface or a transmitted one above it is
+ * no sample: its pdf and weight are 0 (wo is still written).  Inputs outside
+ * the domain (w_z <= 0, alpha <= 0) give wo = (0, 0, 1), pdf = weight = 0.
+ * Errors: NULL_PTR, BAD_SIZE (n < 0), MISALIGNED, BAD_ARG (eta), HIP.
+ */
+int32_t dielectric_sample(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                          const float* ax, const float* ay, float eta, uint64_t seed,
+                          uint64_t index_base, float* wox, float* woy, float* woz, float* pdf,
+                          float* weight, void* stream);
+
+/*
+ * dielectric_pdf -- the density of dielectric_sample at caller-given unit
+ * pairs (wi, wo), for multiple importance sampling: with the half vector
+ * h = wi + wo (wo above) or h = -(wi + eta wo) (wo below, Walter et al.'s
+ * generalised half vector), normalised to the upper side,
+ *   pdf = F(wi.h) VNDF(h) / (4 |wo.h|)                         (reflection),
+ *   pdf = (1 - F(wi.h)) VNDF(h) eta^2 |wo.h| / (wi.h + eta wo.h)^2 (transmission).
+ * 0 when wi.h <= 0, when a transmitted wo lies on the front side of h
+ * (wo.h >= 0), for wo_z = 0 and outside the domain.
+ *   n; wix,wiy,wiz [n]; wox,woy,woz [n]; ax, ay [n]; eta as above; pdf out [n].
+ * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, BAD_ARG (eta), HIP.
+ */
+int32_t dielectric_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz,
+                       const float* wox, const float* woy, const float* woz, const float* ax,
+                       const float* ay, float eta, float* pdf, void* stream);
+
+/*
  * albedo_workspace_size -- bytes of device workspace needed for ncells cells
  * of nsamples samples each by albedo_estimate (mode 0),
  * albedo_estimate_backward (mode 1) or albedo_value_and_grad (mode 2; enough

@@ -61,6 +61,9 @@ _SIGNATURES = {
     "vndf_sample": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _U64, _I32, _P, _P, _P, _P, _P], _I32),
     "vndf_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "vndf_inverse": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "dielectric_sample": ([_I64, _P, _P, _P, _P, _P, ctypes.c_float, _U64, _U64, _P, _P, _P, _P,
+                           _P, _P], _I32),
+    "dielectric_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _P, _P], _I32),
     "albedo_workspace_size": ([_I64, _I64, _I32], ctypes.c_size_t),
     "albedo_estimate": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, ctypes.c_size_t, _P],
                         _I32),
@@ -204,6 +207,42 @@ def vndf_inverse(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
                           _ptr(ax), _ptr(ay), _ptr(u1), _ptr(u2), _stream(stream))
     _check("vndf_inverse", rc)
     return u1, u2
+
+
+def dielectric_sample(wix, wiy, wiz, ax, ay, eta, seed=0, index_base=0, out=None, stream=None):
+    """Rough-dielectric sampling with the cap VNDF: (wox, woy, woz, pdf, weight)."""
+    lib = load_library()
+    n = wix.numel()
+    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, ax=ax, ay=ay).items():
+        _dev(t, k)
+    _same_len(n, wiy=wiy, wiz=wiz, ax=ax, ay=ay)
+    if out is None:
+        outs = tuple(torch.empty_like(wix) for _ in range(5))
+    else:
+        outs = tuple(_dev(x, "out") for x in out)
+        if len(outs) != 5:
+            raise ValueError("out must hold (wox, woy, woz, pdf, weight)")
+        _same_len(n, **{f"out{i}": x for i, x in enumerate(outs)})
+    rc = lib.dielectric_sample(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(ax), _ptr(ay), float(eta),
+                               int(seed), int(index_base), *[_ptr(x) for x in outs],
+                               _stream(stream))
+    _check("dielectric_sample", rc)
+    return outs
+
+
+def dielectric_pdf(wix, wiy, wiz, wox, woy, woz, ax, ay, eta, out=None, stream=None):
+    """Density of dielectric_sample at given unit pairs (wi, wo)."""
+    lib = load_library()
+    n = wix.numel()
+    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, wox=wox, woy=woy, woz=woz, ax=ax, ay=ay).items():
+        _dev(t, k)
+    _same_len(n, wiy=wiy, wiz=wiz, wox=wox, woy=woy, woz=woz, ax=ax, ay=ay)
+    pdf = torch.empty_like(wix) if out is None else _dev(out, "out")
+    _same_len(n, pdf=pdf)
+    rc = lib.dielectric_pdf(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(wox), _ptr(woy), _ptr(woz),
+                            _ptr(ax), _ptr(ay), float(eta), _ptr(pdf), _stream(stream))
+    _check("dielectric_pdf", rc)
+    return pdf
 
 
 def albedo_workspace_size(ncells: int, nsamples: int, mode: int) -> int:

@@ -7,38 +7,10 @@
 // reused), and each group of four tuples takes exactly two Philox blocks.
 #include "common.hpp"
 #include "device_math.hpp"
+#include "stream_io.hpp"
 
 namespace capvndf {
 namespace {
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-// Launch shape of the streaming kernels (build-time constants): threads per
-// block, vec4 groups per lane, and whether loads (bit 0) and stores (bit 1)
-// are non-temporal.
-#ifndef CAPVNDF_STREAM_BLOCK
-#define CAPVNDF_STREAM_BLOCK 256
-#endif
-#ifndef CAPVNDF_STREAM_GROUPS
-#define CAPVNDF_STREAM_GROUPS 4
-#endif
-#ifndef CAPVNDF_STREAM_NT
-#define CAPVNDF_STREAM_NT 3
-#endif
-constexpr int kBlock = CAPVNDF_STREAM_BLOCK;
-constexpr int kGroups = CAPVNDF_STREAM_GROUPS;
-constexpr int64_t kTile = (int64_t)kBlock * 4 * kGroups;
-
-__device__ __forceinline__ f4 load4(const float* p) {
-    if (CAPVNDF_STREAM_NT & 1) return __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
-    return *reinterpret_cast<const f4*>(p);
-}
-__device__ __forceinline__ void store4(float* p, f4 v) {
-    if (CAPVNDF_STREAM_NT & 2)
-        __builtin_nontemporal_store(v, reinterpret_cast<f4*>(p));
-    else
-        *reinterpret_cast<f4*>(p) = v;
-}
 
 // One tuple: general sampler with the chosen hemisphere routine.  Inputs
 // outside the domain are replaced by harmless ones and the outputs selected
@@ -403,8 +375,6 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(
     }
 }
 
-inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
-inline unsigned tiles_for(int64_t n) { return (unsigned)((n + kTile - 1) / kTile); }
 
 template <int METHOD, bool EU, bool WP>
 void launch_sample(bool vec, int64_t n, const float* wix, const float* wiy, const float* wiz,

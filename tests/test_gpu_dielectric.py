@@ -1,0 +1,250 @@
+"""GPU parity of the rough-dielectric sampler and its pdf (C ABI through the
+Python binding) against the FP64 oracle.
+
+Tolerance.  The GPU builds the same visible normal h as the VNDF sampler, so
+h carries that path's FP32 error, O(2^-24 kappa) with kappa = 1 / |M^-T hs|
+(see _gpu.py).  Reflecting or refracting wi about h multiplies it by the
+derivative of wo with respect to h:
+  reflection    wo = 2 c h - wi,               |dwo| <= 4 |dh|,
+  transmission  wo = ((c - g) h - wi) / eta,   |dwo| <= (1 + c / g + |c - g|) |dh| / eta,
+with c = wi . h and g = sqrt(eta^2 - 1 + c^2) (g -> 0 at the critical angle,
+where refraction is ill-conditioned).  The pdf F p_h / (4c) or
+(1 - F) p_h eta g / (c - g)^2 adds the relative sensitivities of c, F and g:
+K_pdf = kappa (2 + 1 / c + |F'| / F)  or  kappa (2 + |F'| / (1 - F) + c / g^2
++ 2 (1 + c / g) / |c - g|).  The weight |wo_z| (1 + z_i) / (z_i l_o + |wo_z|)
+moves by at most (1 + 1 / z_i) |dwo|.  Rule: err <= max(4e-6, C 2^-24 K) per
+sample with C = 64 (wo), 128 (pdf), 64 (weight), and err <= 4e-6 on every
+sample with K <= 5.  Samples whose lobe decision u3 < F lies within the FP32
+error of F, or whose wo_z lies within the wo tolerance of the horizon, may
+legitimately take the other branch; they are checked for validity only and
+must be rare.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from _gpu import EPS32, host, kappa, to_dev
+
+pytestmark = pytest.mark.gpu
+
+cv = pytest.importorskip("paper_2306_05044_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cv.load_library()
+
+
+def _fresnel_slope(c, eta):
+    h = 1e-6
+    lo = np.clip(c - h, 0.0, 1.0)
+    hi = np.clip(c + h, 0.0, 1.0)
+    return (oracle.fresnel_dielectric(hi, eta) - oracle.fresnel_dielectric(lo, eta)) / (hi - lo)
+
+
+def _conditioning(d, ref, eta, u3):
+    W = np.stack([d[k].astype(np.float64) for k in ("wx", "wy", "wz")], 1)
+    h = ref["h"]
+    kap = kappa(h, d["wx"], d["wy"], d["wz"], d["ax"], d["ay"])
+    c = np.einsum("ij,ij->i", W, h)
+    g = np.sqrt(np.maximum(eta * eta - 1.0 + c * c, 0.0))
+    f = oracle.fresnel_dielectric(c, eta)
+    fp = np.abs(_fresnel_slope(c, eta))
+    refl = ref["lobe"] == 0
+    gs = np.maximum(g, 1e-30)
+    a_wo = np.where(refl, 4.0, (1.0 + c / gs + np.abs(c - g)) / eta)
+    k_wo = kap * a_wo
+    k_pdf = np.where(refl, kap * (2.0 + 1.0 / c + fp / np.maximum(f, 1e-30)),
+                     kap * (2.0 + fp / np.maximum(1.0 - f, 1e-30) + c / (gs * gs)
+                            + 2.0 * (1.0 + c / gs) / np.maximum(np.abs(c - g), 1e-30)))
+    ax = d["ax"].astype(np.float64)
+    ay = d["ay"].astype(np.float64)
+    zi = W[:, 2] / np.sqrt((ax * W[:, 0]) ** 2 + (ay * W[:, 1]) ** 2 + W[:, 2] ** 2)
+    k_w = k_wo * (1.0 + 1.0 / zi)
+    # lobe decision within reach of FP32 error in F
+    near_lobe = np.abs(u3 - f) <= 64 * EPS32 * (1.0 + fp * kap)
+    near_horizon = np.abs(ref["wo"][:, 2]) <= np.maximum(4e-6, 64 * EPS32 * k_wo)
+    return k_wo, k_pdf, k_w, near_lobe | near_horizon
+
+
+def _check(err, k, c, name, mask):
+    lim = np.maximum(4e-6, c * EPS32 * k)
+    bad = (err > lim) & mask
+    assert not bad.any(), f"{name}: {bad.sum()} over the limit, worst {err[bad].max():.3e} " \
+        f"(K {k[bad][np.argmax(err[bad])]:.3e})"
+    well = mask & (k <= 5.0)
+    if well.any():
+        assert np.all(err[well] <= 4e-6), f"{name}: well-conditioned max {err[well].max():.3e}"
+    r = err[mask] / (EPS32 * k[mask])
+    print(f"{name}: max err {err[mask].max():.3e}, max err/(eps K) {r.max():.2f}, "
+          f"fraction > 4e-6 {(err[mask] > 4e-6).mean():.2e}")
+
+
+def _stream_u(seed, index_base, n=None, indices=None):
+    """The oracle's uniforms at contiguous positions, or at given ones."""
+    if indices is None:
+        return oracle.dielectric_uniforms(n, seed, index_base)
+    cols = [oracle.dielectric_uniforms(1, seed, index_base + int(k)) for k in indices]
+    return tuple(np.concatenate([c[j] for c in cols]) for j in range(3))
+
+
+def _compare(d, outs, eta, u, name):
+    """outs: GPU (wox, woy, woz, pdf, weight) as tensors or arrays; u: the
+    stream's uniforms at the same tuples."""
+    wi = (d["wx"], d["wy"], d["wz"])
+    ref = oracle.dielectric_sample(wi, d["ax"], d["ay"], eta, u=u)
+    outs = [host(x) if torch.is_tensor(x) else x for x in outs]
+    wo = np.stack([x.astype(np.float64) for x in outs[:3]], 1)
+    pdf = outs[3].astype(np.float64)
+    wt = outs[4].astype(np.float64)
+    k_wo, k_pdf, k_w, ambiguous = _conditioning(d, ref, eta, u[2])
+    assert ambiguous.sum() <= max(2, 1e-3 * len(ambiguous)), ambiguous.sum()
+    ok = ~ambiguous
+    both = ok & (ref["pdf"] > 0)
+    assert np.array_equal(pdf[ok] > 0, ref["pdf"][ok] > 0), f"{name}: validity differs"
+    _check(np.linalg.norm(wo - ref["wo"], axis=1), k_wo, 64, name + " wo", ok)
+    rel = np.abs(pdf[both] / ref["pdf"][both] - 1.0)
+    full = np.zeros_like(pdf)
+    full[both] = rel
+    _check(full, k_pdf, 128, name + " pdf", both)
+    _check(np.abs(wt - ref["weight"]), k_w, 64, name + " weight", ok)
+    # every GPU sample, ambiguous ones included, is a valid sample or no sample
+    assert np.all(np.isfinite(wo)) and np.all(pdf >= 0) and np.all((wt >= 0) & (wt <= 1 + 1e-6))
+    gv = pdf > 0
+    assert np.all(np.abs(np.linalg.norm(wo[gv], axis=1) - 1.0) < 1e-4)
+    return ref
+
+
+@pytest.mark.parametrize("eta", [1.5, 1.0 / 1.5, 1.33, 2.4])
+def test_small_config_parity(eta):
+    """65,536 isotropic tuples (roughness log-uniform in [0.01, 1]), all compared."""
+    d = workloads.tuples_small(65536, seed=0)
+    t = to_dev(d)
+    outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], eta, seed=7)
+    _compare(d, outs, eta, _stream_u(7, 0, 65536), f"eta {eta:.4f}")
+
+
+@pytest.mark.parametrize("eta", [1.5, 1.0 / 1.33])
+def test_anisotropic_parity(eta):
+    """Streaming-workload tuples: grazing views and roughness down to 1e-3."""
+    d = workloads.tuples_streaming(1 << 16, seed=12)
+    t = to_dev(d)
+    outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], eta, seed=3,
+                                index_base=1 << 33)
+    _compare(d, outs, eta, _stream_u(3, 1 << 33, 1 << 16), f"aniso eta {eta:.4f}")
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 63, 65, 1023, 4097])
+def test_ragged_sizes_and_scalar_path(n):
+    d = workloads.tuples_streaming(n + 1, seed=21)
+    t = to_dev(d)
+    a = cv.dielectric_sample(t["wx"][:n], t["wy"][:n], t["wz"][:n], t["ax"][:n], t["ay"][:n],
+                             1.5, seed=9, index_base=5)
+    _compare({k: v[:n] for k, v in d.items()}, a, 1.5, _stream_u(9, 5, n), f"n={n}")
+    # misaligned copies of the same values take the scalar path: same bits
+    buf = {k: torch.zeros(n + 1, device="cuda") for k in t}
+    for k in t:
+        buf[k][1:].copy_(t[k][:n])
+    b = cv.dielectric_sample(buf["wx"][1:], buf["wy"][1:], buf["wz"][1:], buf["ax"][1:],
+                             buf["ay"][1:], 1.5, seed=9, index_base=5)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    # a split call continues the stream: the second half at index_base + m
+    m = n // 2
+    if m > 0:
+        c2 = cv.dielectric_sample(t["wx"][m:n], t["wy"][m:n], t["wz"][m:n], t["ax"][m:n],
+                                  t["ay"][m:n], 1.5, seed=9, index_base=5 + m)
+        for x, y in zip(a, c2):
+            assert torch.equal(x[m:n], y)
+
+
+def test_domain_edges_and_total_reflection():
+    wz = torch.tensor([1.0, 0.0, -0.5, 1.0, 1.0, 0.2, 0.05, 1.0], device="cuda")
+    wx = torch.sqrt(torch.clamp(1 - wz * wz, min=0.0))
+    wy = torch.zeros_like(wz)
+    ax = torch.tensor([0.5, 0.5, 0.5, 0.0, 0.5, 1e-3, 1e-3, 1.0], device="cuda")
+    ay = torch.tensor([0.5, 0.5, 0.5, 0.5, -1.0, 1e-3, 1e-3, 1.0], device="cuda")
+    wox, woy, woz, pdf, w = cv.dielectric_sample(wx, wy, wz, ax, ay, 1.0 / 1.5, seed=1)
+    O = np.stack([host(wox), host(woy), host(woz)], 1)
+    for i in (1, 2, 3, 4):
+        assert tuple(O[i]) == (0.0, 0.0, 1.0) and host(pdf)[i] == 0 and host(w)[i] == 0
+    # from the dense side at 78 and 87 degrees, past the critical angle of
+    # 41.8 degrees, a nearly smooth surface reflects everything
+    for i in (5, 6):
+        assert O[i, 2] > 0 and host(pdf)[i] > 0
+    assert np.all(np.isfinite(O)) and np.all(np.isfinite(host(pdf)))
+
+
+def test_pdf_entry_point():
+    """dielectric_pdf at FP32 directions vs the oracle at the same values.
+    Conditioning: the half vector t = wi + wo or -(wi + eta wo) loses
+    2^-24 / |t| relatively, and wi.h, which sets F, cancels near grazing."""
+    n = 65536 + 3
+    d = workloads.tuples_streaming(n, seed=8)
+    t = to_dev(d)
+    for eta in (1.5, 1.0 / 1.5):
+        wox, woy, woz, _, _ = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"],
+                                                       t["ay"], eta, seed=2)
+        p = cv.dielectric_pdf(t["wx"], t["wy"], t["wz"], wox, woy, woz, t["ax"], t["ay"], eta)
+        O = [host(x).astype(np.float64) for x in (wox, woy, woz)]
+        W = [d[k].astype(np.float64) for k in ("wx", "wy", "wz")]
+        ref, _ = oracle.dielectric_eval(W, O, d["ax"], d["ay"], eta)
+        got = host(p).astype(np.float64)
+        Wm, Om = np.stack(W, 1), np.stack(O, 1)
+        refl = Om[:, 2] > 0
+        tv = np.where(refl[:, None], Wm + Om, -(Wm + eta * Om))
+        tn = np.linalg.norm(tv, axis=1)
+        hh = tv * (np.sign(tv[:, 2]) / tn)[:, None]
+        ci = np.einsum("ij,ij->i", Wm, hh)
+        co = np.abs(np.einsum("ij,ij->i", Om, hh))
+        g = np.sqrt(np.maximum(eta * eta - 1 + ci * ci, 0.0))
+        fp = np.abs(_fresnel_slope(np.clip(ci, 0, 1), eta))
+        f = oracle.fresnel_dielectric(np.clip(ci, 0, 1), eta)
+        sel = np.where(refl, f, 1 - f)
+        K = (4.0 / tn + 2.0 / np.maximum(ci, 1e-30) + 2.0 / np.maximum(co, 1e-30)
+             + fp / np.maximum(sel, 1e-30) / np.maximum(ci, 1e-30)
+             + np.where(refl, 0.0, ci / np.maximum(g * g, 1e-30)))
+        both = (ref > 0) & (got > 0)
+        # a zero on exactly one side only where the validity tests are within rounding
+        one = (ref > 0) != (got > 0)
+        assert np.all(K[one] > 1e4) or not one.any(), one.sum()
+        rel = np.zeros(n)
+        rel[both] = np.abs(got[both] / ref[both] - 1)
+        _check(rel, K, 128, f"pdf entry eta {eta:.4f}", both)
+
+
+def test_determinism():
+    d = workloads.tuples_streaming(1 << 16, seed=1)
+    t = to_dev(d)
+    a = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, seed=1)
+    b = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, seed=1)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_streaming_full_size_sampled():
+    """2^26 anisotropic tuples in the benchmark's launch configuration
+    (eta = 1.5); 2^16 sampled outputs against the oracle, invariants on all."""
+    n = 1 << 26
+    d = workloads.tuples_streaming(n, seed=1)
+    t = to_dev(d)
+    outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, seed=1)
+    torch.cuda.synchronize()
+    wox, woy, woz, pdf, w = outs
+    assert torch.all(torch.isfinite(pdf)) and torch.all(pdf >= 0)
+    assert torch.all((w >= 0) & (w <= 1.000001))
+    valid = pdf > 0
+    norm = torch.sqrt(wox.double() ** 2 + woy.double() ** 2 + woz.double() ** 2)
+    assert torch.max(torch.abs(norm[valid] - 1.0)).item() < 1e-3
+    assert valid.double().mean().item() > 0.97
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(n, 1 << 13, replace=False))
+    ti = torch.from_numpy(idx).cuda()
+    got = [x[ti] for x in outs]
+    sub = {k: v[idx] for k, v in d.items()}
+    _compare(sub, got, 1.5, _stream_u(1, 0, indices=idx), "2^26 sampled")
