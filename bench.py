@@ -67,7 +67,7 @@ def timed(fn, steps, warmup):
 
 def source_digest():
     h = hashlib.sha256()
-    for f in ("sample.hip", "device_math.hpp"):
+    for f in ("sample.hip", "device_math.hpp", "stream_io.hpp"):
         with open(os.path.join(ROOT, "paper_2306_05044_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
