@@ -329,6 +329,26 @@ def main():
                           "gsamples_per_s_fwd_adj": round(info["total_samples"] / ms_b / 1e6, 2),
                           "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}")}
         plan.close()
+        # a mix of short jobs (2^10 .. 2^14 samples), where wavefront-owned
+        # chunks can beat block-owned ones: the autotuner decides
+        log("batched estimator: 4096 short jobs (2^10 .. 2^14 samples), autotuned")
+        js = workloads.batch_jobs(4096, seed=6, log2_min=10, log2_max=14)
+        cs = {k: torch.from_numpy(v).to(dev) for k, v in js.items() if k != "n"}
+        best_s, _ = cv.albedo_batch_autotune(cs["wx"], cs["wy"], cs["wz"], cs["ax"], cs["ay"],
+                                             js["n"], 4, with_grad=True)
+        res_s = {}
+        for name, til in (("autotuned", best_s), ("block_owned_default", (256, 32, 8, 0)),
+                          ("wave_owned", (256, 16, 8, 1))):
+            p2 = cv.BatchPlan(cs["wx"], cs["wy"], cs["wz"], cs["ax"], cs["ay"], js["n"], 4,
+                              with_grad=True, tiling=til)
+            res_s[name + "_ms"] = round(timed(p2.run, max(5, args.steps // 5), 2)[0], 4)
+            if name == "autotuned":
+                res_s["per_request_ms"] = round(timed(p2.run_per_request, 2, 1)[0], 4)
+                res_s["total_samples"] = p2.info()["total_samples"]
+            p2.close()
+        res_s["tiling"] = list(best_s)
+        res_s["speedup_vs_per_request"] = round(res_s["per_request_ms"] / res_s["autotuned_ms"], 2)
+        out["batched"]["short_jobs"] = res_s
 
     if "radiance" in only:
         import oracle
