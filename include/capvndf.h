@@ -315,7 +315,8 @@ typedef struct capvndf_batch_plan capvndf_batch_plan;
  *   tiling                NULL: the tuned tiling cached for this problem
  *                         signature (CAPVNDF_TUNE_CACHE file) or the default
  *                         {256, 32, 8, 0}
- *   stream                stream used for the capture
+ *   stream                unused: the graph is captured on a private stream
+ *                         of the current device, which the plan belongs to
  *   out                   receives the plan
  * The plan keeps the pointers: they must stay valid while the plan is used,
  * and new buffers need a new plan.  Errors: NULL_PTR, BAD_SIZE, BAD_ARG, HIP.
@@ -327,12 +328,14 @@ int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, const float* w
                                  float* grad_theta_o, const capvndf_tiling* tiling, void* stream,
                                  capvndf_batch_plan** out);
 
-/* Replay the plan's graph on `stream` (one hipGraphLaunch). */
+/* Replay the plan's graph on `stream` (one hipGraphLaunch).  The current
+ * device must be the plan's.  Errors: NULL_PTR, BAD_ARG (other device), HIP. */
 int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream);
 
 /* Same jobs and outputs as albedo_batch_run, launched the per-request way:
  * per job one albedo_value_and_grad-style estimate kernel plus its finishing
- * kernel, no graph.  The baseline the batch is measured against. */
+ * kernel, no graph.  The baseline the batch is measured against.  Errors as
+ * albedo_batch_run. */
 int32_t albedo_batch_run_per_request(capvndf_batch_plan* plan, void* stream);
 
 /* Tiling and chunk statistics of a plan. */

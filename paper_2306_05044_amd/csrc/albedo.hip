@@ -872,13 +872,27 @@ extern "C" int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, con
                        grad_ax, grad_ay, grad_theta_o, tiling, out);
 }
 
+namespace {
+// A plan's pointers and graph belong to the device it was created on.
+int32_t check_plan_device(const capvndf_batch_plan* p, const char* who) {
+    int dev = 0;
+    if (int32_t rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
+    if (dev != p->device)
+        return fail(CAPVNDF_ERR_BAD_ARG, "%s: the plan belongs to device %d, current device is %d",
+                    who, p->device, dev);
+    return CAPVNDF_OK;
+}
+}  // namespace
+
 extern "C" int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream) {
     if (plan == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_run: plan is NULL");
+    if (int32_t rc = check_plan_device(plan, "albedo_batch_run")) return rc;
     return check_hip(hipGraphLaunch(plan->exec, as_stream(stream)), "hipGraphLaunch");
 }
 
 extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* stream) {
     if (p == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_run_per_request: plan is NULL");
+    if (int32_t rc = check_plan_device(p, "albedo_batch_run_per_request")) return rc;
     const hipStream_t st = as_stream(stream);
     const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
     for (int64_t j = 0; j < p->njobs; ++j) {
