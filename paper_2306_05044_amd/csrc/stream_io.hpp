@@ -41,8 +41,12 @@ __device__ __forceinline__ void store4(float* p, f4 v) {
         *reinterpret_cast<f4*>(p) = v;
 }
 
-// Blocks for one element per lane, and for whole tiles.
+// Blocks for one element per lane, and for whole tiles (of G groups per lane).
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
-inline unsigned tiles_for(int64_t n) { return (unsigned)((n + kTile - 1) / kTile); }
+template <int G = kGroups>
+inline unsigned tiles_for(int64_t n) {
+    constexpr int64_t tile = (int64_t)kBlock * 4 * G;
+    return (unsigned)((n + tile - 1) / tile);
+}
 
 }  // namespace capvndf
