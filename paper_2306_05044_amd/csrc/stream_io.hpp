@@ -41,6 +41,10 @@ __device__ __forceinline__ void store4(float* p, f4 v) {
         *reinterpret_cast<f4*>(p) = v;
 }
 
+// Plain (cached) 16-byte store, for a kernel whose output is small next to its
+// non-temporal input stream (measured faster there than a non-temporal one).
+__device__ __forceinline__ void store4_cached(float* p, f4 v) { *reinterpret_cast<f4*>(p) = v; }
+
 // Blocks for one element per lane, and for whole tiles (of G groups per lane).
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 template <int G = kGroups>

@@ -11,8 +11,9 @@ with c = wi . h and g = sqrt(eta^2 - 1 + c^2) (g -> 0 at the critical angle,
 where refraction is ill-conditioned).  The pdf F p_h / (4c) or
 (1 - F) p_h eta g / (c - g)^2 adds the relative sensitivities of c, F and g:
 K_pdf = kappa (2 + 1 / c + |F'| / F)  or  kappa (2 + |F'| / (1 - F) + c / g^2
-+ 2 (1 + c / g) / |c - g|).  The weight |wo_z| (1 + z_i) / (z_i l_o + |wo_z|)
-moves by at most (1 + 1 / z_i) |dwo|.  Rule: err <= max(4e-6, C 2^-24 K) per
++ 2 (1 + c / g) / |c - g|).  The weight w = a (1 + z_i) / (z_i l_o + a), with
+a = |wo_z| and l_o = |M^-1 wo|, moves by (1 + z_i) z_i (l_o + a) / (z_i l_o + a)^2
+times |dwo|, plus its own rounding (K + 8).  Rule: err <= max(4e-6, C 2^-24 K) per
 sample with C = 64 (wo), 128 (pdf), 64 (weight), and err <= 4e-6 on every
 sample with K <= 5.  Samples whose lobe decision u3 < F lies within the FP32
 error of F, or whose wo_z lies within the wo tolerance of the horizon, may
@@ -65,7 +66,12 @@ def _conditioning(d, ref, eta, u3):
     ax = d["ax"].astype(np.float64)
     ay = d["ay"].astype(np.float64)
     zi = W[:, 2] / np.sqrt((ax * W[:, 0]) ** 2 + (ay * W[:, 1]) ** 2 + W[:, 2] ** 2)
-    k_w = k_wo * (1.0 + 1.0 / zi)
+    wo = ref["wo"]
+    a = np.abs(wo[:, 2])
+    lo = np.sqrt((ax * wo[:, 0]) ** 2 + (ay * wo[:, 1]) ** 2 + wo[:, 2] ** 2)
+    # |dw/dwo| for w = a (1 + z_i) / (z_i l_o + a), a = |wo_z| (|dl_o| <= |dwo|),
+    # plus the weight's own rounding (w <= 1)
+    k_w = k_wo * (1.0 + zi) * zi * (lo + a) / (zi * lo + a) ** 2 + 8.0
     # lobe decision within reach of FP32 error in F
     near_lobe = np.abs(u3 - f) <= 64 * EPS32 * (1.0 + fp * kap)
     near_horizon = np.abs(ref["wo"][:, 2]) <= np.maximum(4e-6, 64 * EPS32 * k_wo)
@@ -137,6 +143,17 @@ def test_anisotropic_parity(eta):
     outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], eta, seed=3,
                                 index_base=1 << 33)
     _compare(d, outs, eta, _stream_u(3, 1 << 33, 1 << 16), f"aniso eta {eta:.4f}")
+
+
+@pytest.mark.parametrize("eta", [1.0005, 1.0 / 1.0005, 4.0])
+def test_extreme_indices(eta):
+    """Nearly index-matched media (the refracted ray barely bends and the
+    transmission pdf is sharply peaked) and a very dense one."""
+    d = workloads.tuples_small(1 << 14, seed=4)
+    t = to_dev(d)
+    outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], eta, seed=5)
+    assert all(torch.all(torch.isfinite(o)).item() for o in outs)
+    _compare(d, outs, eta, _stream_u(5, 0, 1 << 14), f"eta {eta:.5f}")
 
 
 @pytest.mark.parametrize("n", [1, 3, 4, 5, 63, 65, 1023, 4097])
