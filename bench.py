@@ -193,6 +193,13 @@ def main():
                               "gsamples_per_s": round(N_STREAM / ms_i / 1e6, 3),
                               "gbytes_per_s": round(40 * N_STREAM / ms_i / 1e6, 1),
                               "bytes_per_sample": 40}
+        log("timing the VNDF pdf at the sampled normals")
+        ms_p, _ = timed(lambda: cv.vndf_pdf(t["wx"], t["wy"], t["wz"], outs[0], outs[1], outs[2],
+                                            t["ax"], t["ay"], out=u1b), args.steps, args.warmup)
+        out["vndf_pdf"] = {"ms_per_launch": round(ms_p, 5),
+                           "gsamples_per_s": round(N_STREAM / ms_p / 1e6, 3),
+                           "gbytes_per_s": round(36 * N_STREAM / ms_p / 1e6, 1),
+                           "bytes_per_sample": 36}
         del u1b, u2b
     if "dielectric" in only:
         log("timing the rough-dielectric sampler and its pdf (eta = 1.5)")
