@@ -112,7 +112,8 @@ int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz
  * sample space (e.g. to reuse or mutate paths).
  *
  *   n; wix,wiy,wiz [n]; hx,hy,hz unit visible normals [n]; ax, ay [n];
- *   u1, u2 [n] out: in [0, 1); both -1 outside the domain (w_z <= 0,
+ *   u1, u2 [n] out: in [0, 1) (u2 clamped there, since rounding can
+ *   carry a normal at the rim of the cap past 1); both -1 outside the domain (w_z <= 0,
  *   alpha <= 0, h_z <= 0 or wi.h <= 0).  u1 is undefined at the apex of the
  *   cap (u2 = 0) and returned as atan2 gives it there.
  * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, HIP.

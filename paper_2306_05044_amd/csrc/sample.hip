@@ -250,7 +250,8 @@ __device__ __forceinline__ void inverse_one(float wx, float wy, float wz, float 
     t = t < 0.0f ? t + 1.0f : t;
     t = t >= 1.0f ? 0.0f : t;
     u1 = ok ? t : -1.0f;
-    u2 = ok ? fmaxf(v2, 0.0f) : -1.0f;
+    // rounding can carry a normal at the rim of the cap to u2 >= 1: clamp into [0, 1)
+    u2 = ok ? fminf(fmaxf(v2, 0.0f), 0x1.fffffep-1f) : -1.0f;
 }
 
 template <int G, bool CACHED_OUT>

@@ -260,6 +260,49 @@ def test_inverse_map(n):
     assert np.median(e2) < 1e-6
 
 
+def test_inverse_and_pdf_full_size_sampled():
+    """2^26 streaming tuples in the benchmark's launch configuration: the
+    inverse map and vndf_pdf over all the GPU's normals, 2^16 sampled outputs
+    against the oracle at the same FP32 normals (rules as above), range and
+    round-trip properties on all of them."""
+    n = 1 << 26
+    d = workloads.tuples_streaming(n, seed=1)
+    t = to_dev(d)
+    del d
+    hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=1)
+    g1, g2 = cv.vndf_inverse(t["wx"], t["wy"], t["wz"], hx, hy, hz, t["ax"], t["ay"])
+    pdf = cv.vndf_pdf(t["wx"], t["wy"], t["wz"], hx, hy, hz, t["ax"], t["ay"])
+    torch.cuda.synchronize()
+    assert torch.all((g1 >= 0) & (g1 < 1) & (g2 >= 0) & (g2 < 1))
+    assert torch.all(torch.isfinite(pdf)) and torch.all(pdf >= 0)
+    # round trip against the stream's own u2 on every tuple: rounding-level bulk
+    u1s, u2s = cv.capvndf_uniforms(1, 2, 0, 0, n)
+    e2 = (g2 - u2s).abs()
+    assert torch.median(e2).item() < 1e-6
+    del u1s, u2s, e2
+    rng = np.random.default_rng(2)
+    idx = np.sort(rng.choice(n, size=1 << 16, replace=False))
+    it = torch.from_numpy(idx).cuda()
+    sub = {k: host(v[it]).astype(np.float64) for k, v in t.items()}
+    H = [host(x[it]).astype(np.float64) for x in (hx, hy, hz)]
+    r1, r2 = oracle.vndf_inverse((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
+    eps = 2.0 ** -24
+    G1, G2 = host(g1[it]), host(g2[it])
+    assert np.all(np.abs(G2 - r2) <= 32 * eps)
+    ws = np.stack([sub["wx"] * sub["ax"], sub["wy"] * sub["ay"], sub["wz"]], 1)
+    zs = ws[:, 2] / np.linalg.norm(ws, axis=1)
+    cz = 1.0 - r2 * (1.0 + zs)
+    cxy = np.sqrt(np.maximum(0.0, 1.0 - cz * cz))
+    ok = cxy > 1e-3
+    assert np.all(_circ(G1[ok], r1[ok]) <= 32 * eps / cxy[ok])
+    ref = oracle.vndf_pdf((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
+    w = np.stack([sub["wx"], sub["wy"], sub["wz"]], 1)
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
+    rel = np.abs(host(pdf[it]) / ref - 1.0)
+    assert np.all(rel <= np.maximum(2e-6, 8 * eps / dot)), rel.max()
+
+
 def test_inverse_edges_and_scalar_path():
     wz = torch.tensor([1.0, -1.0, 1.0, 1.0, 1.0], device="cuda")
     z = torch.zeros(5, device="cuda")
