@@ -10,8 +10,9 @@
  *  - Arrays are caller-owned DEVICE pointers (for example a torch tensor's
  *    data_ptr()), FP32 unless stated, contiguous, at least 4-byte aligned.
  *    Structure-of-arrays layout: one array per vector component.
- *    16-byte alignment of every array (and an even index_base) selects the
- *    vectorised path; otherwise a scalar path gives identical results.
+ *    16-byte alignment of every array (and, for vndf_sample, an even
+ *    index_base) selects the vectorised path; otherwise a scalar path gives
+ *    identical results.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Calls only enqueue work: they return before the GPU has finished and
  *    never synchronise.  Enqueued work reads inputs and writes outputs
@@ -28,6 +29,8 @@
  *    sample k takes words (w0, w1) when k is even and (w2, w3) when odd, and
  *    u = (w >> 8) * 2^-24.  Tags: 2 = vndf_sample (unit 0, k = index_base + i),
  *    3 = albedo estimators (unit = cell or job index, k = sample index).
+ *    dielectric_sample needs three uniforms per tuple and takes a whole block
+ *    per tuple instead: counter (lo32(k), 0, 5, hi32(k)), words 0, 1, 2.
  *  - Domain: directions need w_z > 0 and roughness alpha > 0.  Elements
  *    outside it give h = (0, 0, 1) and pdf = 0; albedo cells or jobs outside
  *    it give 0 values and 0 gradients.  Inputs in the documented ranges never
@@ -351,7 +354,9 @@ void albedo_batch_plan_destroy(capvndf_batch_plan* plan);
  * albedo_batch_autotune -- time candidate tilings on the given jobs (replays
  * on `stream`, synchronising it) and return the fastest in *best and its mean
  * time per run in *best_ms.  When CAPVNDF_TUNE_CACHE names a file, the result
- * is stored there under the problem signature for later plans.
+ * is stored there under the problem signature for later plans.  Candidates:
+ * block 256 or 512 threads x pairs_per_thread 8..64 (block-owned chunks) or
+ * 8..128 (wavefront-owned chunks) x blocks_per_cu 2..16 (2..8 for 512).
  * Arguments as albedo_batch_plan_create; outputs are overwritten.
  */
 int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const float* woy,

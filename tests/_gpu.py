@@ -6,8 +6,9 @@ FP32 inputs and the same uniforms).  The half vector hs = c + ws of the cap
 construction is the sum of two unit vectors, so its components carry absolute
 rounding errors of O(2^-24) however small hs is.  The normal is
 h = M^-T hs / L with L = |M^-T hs| (M^-T = diag(ax, ay, 1)), so those errors
-reach h as O(2^-24 / L) and reach the pdf (which goes as L^3 / |hs|^2) as a
-relative O(2^-24 / L).  The condition number kappa = 1 / L is computed from the
+reach h as O(2^-24 max(1, ax, ay) / L) and reach the pdf (which goes as
+L^3 / |hs|^2) as a relative error of the same order.  The condition number
+kappa = max(1, ax, ay) / L (= 1 / L for roughness up to 1) is computed from the
 oracle's normal: with h_std = M^T h / |M^T h|, |hs| = 2 ws . h_std and
 L = |hs| / |M^T h|.  Rule: every sample has err <= max(2e-6, C 2^-24 kappa),
 and every sample with kappa <= 5 has err <= 2e-6 (C = 64 for h, 128 for the
@@ -46,7 +47,9 @@ def kappa(h_ref, wx, wy, wz, ax, ay):
                    np.asarray(wz, np.float64)], axis=1)
     ws /= np.linalg.norm(ws, axis=1, keepdims=True)
     hs_norm = 2.0 * np.einsum("ij,ij->i", hstd, ws)
-    return mtn / hs_norm
+    # the unstretch M^-T = diag(ax, ay, 1) scales hs's absolute error by up to
+    # max(ax, ay, 1) before the division by L (1 inside the workloads' range)
+    return np.maximum(1.0, np.maximum(ax, ay)) * mtn / hs_norm
 
 
 def kappa_disk_pdf(h_ref, wx, wy, wz, ax, ay):

@@ -369,3 +369,39 @@ def test_stream_index_crossing_high_counter_word():
     h_ref, p_ref = oracle.vndf_sample((d["wx"], d["wy"], d["wz"]), d["ax"], d["ay"], seed=77,
                                       index_base=base)
     _compare(d, *got, h_ref, p_ref, "index 2^33", 0)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_roughness_far_outside_the_workloads(method):
+    """Roughness from 1e-6 (nearly specular) to 100 (beyond physical GGX use):
+    finite, unit normals above the surface, positive pdfs, and parity with the
+    oracle under the conditioning rule for the cap on every sample.  The flat
+    2e-6 clause for well-conditioned samples is the target for the workloads'
+    roughness range [1e-3, 1]; out here the pdf's few extra roundings on large
+    magnitudes reach about 2.2e-6, so only the per-sample rule is applied."""
+    rng = np.random.default_rng(17)
+    n = 1 << 14
+    alphas = np.array([1e-6, 1e-4, 0.03, 3.0, 30.0, 100.0])
+    ax = alphas[rng.integers(0, len(alphas), n)].astype(np.float32)
+    ay = alphas[rng.integers(0, len(alphas), n)].astype(np.float32)
+    mu = (1e-3 + (1 - 1e-3) * rng.random(n))
+    phi = 2 * np.pi * rng.random(n)
+    s_ = np.sqrt(1 - mu * mu)
+    d = {"wx": (s_ * np.cos(phi)).astype(np.float32), "wy": (s_ * np.sin(phi)).astype(np.float32),
+         "wz": mu.astype(np.float32), "ax": ax, "ay": ay}
+    t = to_dev(d)
+    hx, hy, hz, pdf = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=8,
+                                     method=method)
+    H = np.stack([host(hx), host(hy), host(hz)], 1).astype(np.float64)
+    P = host(pdf)
+    assert np.all(np.isfinite(H)) and np.all(np.isfinite(P)) and np.all(P >= 0)
+    assert np.allclose(np.linalg.norm(H, axis=1), 1.0, atol=2e-6) and np.all(H[:, 2] >= 0)
+    h_ref, p_ref = oracle.vndf_sample((d["wx"], d["wy"], d["wz"]), d["ax"], d["ay"], seed=8,
+                                      method=method)
+    if method == 0:
+        assert np.all(P > 0)
+        kap = kappa(h_ref, d["wx"], d["wy"], d["wz"], d["ax"], d["ay"])
+        check_conditioned(np.linalg.norm(H - h_ref, axis=1), kap, 64, "extreme roughness h",
+                          strict_well=False)
+        check_conditioned(np.abs(P / p_ref - 1.0), kap, 128, "extreme roughness pdf",
+                          strict_well=False)
