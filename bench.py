@@ -179,8 +179,14 @@ def main():
         log("timing the streaming probe")
         ins = [t[k] for k in ("wx", "wy", "wz", "ax", "ay")]
         ms_p, _ = timed(lambda: cv.capvndf_stream_probe(ins, outs), args.steps, args.warmup)
+        ms_r, _ = timed(lambda: cv.capvndf_stream_probe(ins, outs, mode=1), args.steps,
+                        args.warmup)
+        ms_w, _ = timed(lambda: cv.capvndf_stream_probe(ins, outs, mode=2), args.steps,
+                        args.warmup)
         out["stream_probe"] = {"ms_per_launch": round(ms_p, 5),
-                               "gbytes_per_s": round(BYTES_PER_SAMPLE * N_STREAM / ms_p / 1e6, 1)}
+                               "gbytes_per_s": round(BYTES_PER_SAMPLE * N_STREAM / ms_p / 1e6, 1),
+                               "read_only_gbytes_per_s": round(20 * N_STREAM / ms_r / 1e6, 1),
+                               "write_only_gbytes_per_s": round(16 * N_STREAM / ms_w / 1e6, 1)}
     if "inverse" in only:
         log("timing the inverse map h -> (u1, u2)")
         run(0)()

@@ -392,14 +392,18 @@ int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters, uint64_t s
                         uint32_t* out, void* stream);
 
 /*
- * capvndf_stream_probe -- plain streaming kernel with the sampler's memory
- * traffic (5 FP32 arrays read, 4 written, same vector width and launch
- * shape): out0 = in0 + in4, out1 = in1, out2 = in2, out3 = in3.  Measures
- * the achievable HBM bandwidth and calibrates hardware byte counters.
+ * capvndf_stream_probe -- plain streaming kernels with the sampler's arrays,
+ * vector width and launch shape, to measure the achievable HBM bandwidth and
+ * calibrate hardware byte counters.  mode 0: the sampler's traffic (5 FP32
+ * arrays read, 4 written: out0 = in0 + in4, out1..3 = in1..3); mode 1: the
+ * five reads only (outputs untouched for finite inputs); mode 2: the four
+ * writes only (index-derived values; inputs unread).  All nine arrays must be
+ * valid and 16-byte aligned.  Errors: NULL_PTR, BAD_SIZE, MISALIGNED,
+ * BAD_ARG (mode), HIP.
  */
-int32_t capvndf_stream_probe(int64_t n, const float* in0, const float* in1, const float* in2,
-                             const float* in3, const float* in4, float* out0, float* out1,
-                             float* out2, float* out3, void* stream);
+int32_t capvndf_stream_probe(int32_t mode, int64_t n, const float* in0, const float* in1,
+                             const float* in2, const float* in3, const float* in4, float* out0,
+                             float* out1, float* out2, float* out3, void* stream);
 
 #ifdef __cplusplus
 }

@@ -85,7 +85,7 @@ _SIGNATURES = {
     "capvndf_uniforms": ([_U64, _U32, _U32, _U64, _I64, _P, _P, _P], _I32),
     "capvndf_philox_blocks": ([_I64, _P, _U32, _U32, _P, _P], _I32),
     "vndf_microbench": ([_I32, _I64, _I32, _U64, _P, _P], _I32),
-    "capvndf_stream_probe": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "capvndf_stream_probe": ([_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
 }
 
 _lib = None
@@ -438,11 +438,15 @@ def vndf_microbench(method, lanes, iters, seed=1, out=None, stream=None):
     return o
 
 
-def capvndf_stream_probe(ins, outs, stream=None):
-    """Streaming probe over 5 input and 4 output float32 GPU tensors."""
+def capvndf_stream_probe(ins, outs, mode=0, stream=None):
+    """Streaming probe over 5 input and 4 output float32 GPU tensors: mode 0
+    the sampler's traffic, 1 the reads only, 2 the writes only."""
     n = ins[0].numel()
+    for k, t in enumerate(list(ins) + list(outs)):
+        _dev(t, f"probe array {k}")
+    _same_len(n, **{f"a{k}": t for k, t in enumerate(list(ins) + list(outs))})
     _check("capvndf_stream_probe", load_library().capvndf_stream_probe(
-        n, *[_ptr(t) for t in ins], *[_ptr(t) for t in outs], _stream(stream)))
+        int(mode), n, *[_ptr(t) for t in ins], *[_ptr(t) for t in outs], _stream(stream)))
 
 
 from .autograd import AlbedoFunction, albedo  # noqa: E402,F401

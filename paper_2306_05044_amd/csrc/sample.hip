@@ -365,6 +365,12 @@ __global__ __launch_bounds__(kBlock) void k_microbench(int64_t lanes, int32_t it
     out[t] = __float_as_uint(acc);
 }
 
+// Bandwidth probe with the sampler's arrays and launch shape.  MODE 0: the
+// sampler's traffic (out0 = in0 + in4, out1..3 = in1..3: 20 B read and 16 B
+// written per element); MODE 1: the five reads only (a data-dependent store
+// that never fires for finite inputs keeps the loads); MODE 2: the four
+// writes only (values from the index).
+template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_stream_probe(
     int64_t n, const float* __restrict__ in0, const float* __restrict__ in1,
     const float* __restrict__ in2, const float* __restrict__ in3,
@@ -372,28 +378,49 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(
     float* __restrict__ out2, float* __restrict__ out3) {
     const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
     f4 a[kGroups], b[kGroups], c[kGroups], d[kGroups], e[kGroups];
+    if (MODE != 2) {
 #pragma unroll
-    for (int g = 0; g < kGroups; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
-        if (i0 + 4 <= n) {
-            a[g] = load4(in0 + i0); b[g] = load4(in1 + i0); c[g] = load4(in2 + i0);
-            d[g] = load4(in3 + i0); e[g] = load4(in4 + i0);
+        for (int g = 0; g < kGroups; ++g) {
+            const int64_t i0 = base + (int64_t)g * kBlock * 4;
+            if (i0 + 4 <= n) {
+                a[g] = load4(in0 + i0); b[g] = load4(in1 + i0); c[g] = load4(in2 + i0);
+                d[g] = load4(in3 + i0); e[g] = load4(in4 + i0);
+            }
         }
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
         const int64_t i0 = base + (int64_t)g * kBlock * 4;
         if (i0 + 4 <= n) {
-            store4(out0 + i0, a[g] + e[g]);
-            store4(out1 + i0, b[g]);
-            store4(out2 + i0, c[g]);
-            store4(out3 + i0, d[g]);
+            if (MODE == 0) {
+                store4(out0 + i0, a[g] + e[g]);
+                store4(out1 + i0, b[g]);
+                store4(out2 + i0, c[g]);
+                store4(out3 + i0, d[g]);
+            } else if (MODE == 1) {
+                const f4 t = a[g] + b[g] + c[g] + d[g] + e[g];
+                const float s4 = t[0] + t[1] + t[2] + t[3];
+                if (!(s4 == s4) || s4 == INFINITY) out0[i0] = s4;
+            } else {
+                const float v = (float)i0;
+                store4(out0 + i0, f4{v, v + 1.0f, v + 2.0f, v + 3.0f});
+                store4(out1 + i0, f4{v, v, v, v});
+                store4(out2 + i0, f4{1.0f, 1.0f, 1.0f, 1.0f});
+                store4(out3 + i0, f4{0.0f, 0.0f, 0.0f, 0.0f});
+            }
         } else {
             for (int64_t i = i0; i < n && i < i0 + 4; ++i) {
-                out0[i] = in0[i] + in4[i];
-                out1[i] = in1[i];
-                out2[i] = in2[i];
-                out3[i] = in3[i];
+                if (MODE == 0) {
+                    out0[i] = in0[i] + in4[i];
+                    out1[i] = in1[i];
+                    out2[i] = in2[i];
+                    out3[i] = in3[i];
+                } else if (MODE == 1) {
+                    const float s1 = in0[i] + in1[i] + in2[i] + in3[i] + in4[i];
+                    if (!(s1 == s1) || s1 == INFINITY) out0[i] = s1;
+                } else {
+                    out0[i] = (float)i; out1[i] = (float)i; out2[i] = 1.0f; out3[i] = 0.0f;
+                }
             }
         }
     }
@@ -557,10 +584,12 @@ extern "C" int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters,
     return check_launch("vndf_microbench launch");
 }
 
-extern "C" int32_t capvndf_stream_probe(int64_t n, const float* in0, const float* in1,
-                                        const float* in2, const float* in3, const float* in4,
-                                        float* out0, float* out1, float* out2, float* out3,
-                                        void* stream) {
+extern "C" int32_t capvndf_stream_probe(int32_t mode, int64_t n, const float* in0,
+                                        const float* in1, const float* in2, const float* in3,
+                                        const float* in4, float* out0, float* out1, float* out2,
+                                        float* out3, void* stream) {
+    if (mode < 0 || mode > 2)
+        return fail(CAPVNDF_ERR_BAD_ARG, "capvndf_stream_probe: mode must be 0, 1 or 2");
     if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "capvndf_stream_probe: n < 0");
     if (n == 0) return CAPVNDF_OK;
     const void* req[] = {in0, in1, in2, in3, in4, out0, out1, out2, out3};
@@ -569,7 +598,16 @@ extern "C" int32_t capvndf_stream_probe(int64_t n, const float* in0, const float
         if (!aligned_to(p, 16))
             return fail(CAPVNDF_ERR_MISALIGNED, "capvndf_stream_probe: arrays must be 16-byte aligned");
     }
-    hipLaunchKernelGGL(k_stream_probe, dim3(tiles_for(n)), dim3(kBlock), 0,
-                       as_stream(stream), n, in0, in1, in2, in3, in4, out0, out1, out2, out3);
+    const dim3 grid(tiles_for(n)), block(kBlock);
+    const hipStream_t st = as_stream(stream);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_stream_probe<0>, grid, block, 0, st, n, in0, in1, in2, in3, in4, out0,
+                           out1, out2, out3);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_stream_probe<1>, grid, block, 0, st, n, in0, in1, in2, in3, in4, out0,
+                           out1, out2, out3);
+    else
+        hipLaunchKernelGGL(k_stream_probe<2>, grid, block, 0, st, n, in0, in1, in2, in3, in4, out0,
+                           out1, out2, out3);
     return check_launch("capvndf_stream_probe launch");
 }
