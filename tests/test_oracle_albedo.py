@@ -9,6 +9,9 @@
   dwl (the integral the estimator targets, Appendix A) vs Monte Carlo.
 * alpha -> 0 gives A -> F(mu); 0 <= A <= 1; a zero-weight (below-horizon)
   sample still counts in N.
+* Symmetries of the microsurface, in expectation: an isotropic surface gives
+  the same albedo at every view azimuth, and mirroring x and y swaps the
+  roughness axes, A(ax, ay, theta, phi) = A(ay, ax, theta, pi/2 - phi).
 * Dual-number gradient vs central differences of the same program (common
   random numbers) at steps where truncation and rounding are both negligible,
   and vs the derivative of the 1-D normal-incidence integral.
@@ -161,3 +164,31 @@ def test_gradient_at_normal_incidence(orc):
         G.append(a[0] + b[0])
     sig = np.std(G) * np.sqrt(4096)
     assert abs(gx[0] + gy[0] - ref) <= 5.0 * sig / np.sqrt(N), (gx + gy, ref, sig)
+
+
+def _mc_mean_sd(orc, ax, ay, mu, phi, n, seed):
+    s = np.sqrt(1 - mu * mu)
+    wo = (np.full(n, s * np.cos(phi)), np.full(n, s * np.sin(phi)), np.full(n, mu))
+    u1, u2 = orc.uniforms(seed, orc.TAG_ALBEDO, 0, 0, n)
+    w = orc.albedo_terms(wo, ax, ay, u1, u2, f0=1.0)
+    return w.mean(), w.std() / np.sqrt(n)
+
+
+@pytest.mark.parametrize("alpha,mu", [(0.3, 0.4), (0.8, 0.15)])
+def test_isotropic_azimuth_invariance(orc, alpha, mu):
+    n = 1 << 18
+    ref, sd = _mc_mean_sd(orc, alpha, alpha, mu, 0.0, n, seed=21)
+    for k, phi in enumerate((1.1, 2.7, 4.9)):
+        a, sd2 = _mc_mean_sd(orc, alpha, alpha, mu, phi, n, seed=22 + k)
+        assert abs(a - ref) <= 5 * np.hypot(sd, sd2), (phi, a, ref)
+
+
+@pytest.mark.parametrize("ax,ay,mu,phi", [(0.1, 0.7, 0.3, 0.4), (0.9, 0.05, 0.6, 1.2)])
+def test_axis_swap_symmetry(orc, ax, ay, mu, phi):
+    n = 1 << 18
+    a, sd = _mc_mean_sd(orc, ax, ay, mu, phi, n, seed=31)
+    b, sd2 = _mc_mean_sd(orc, ay, ax, mu, np.pi / 2 - phi, n, seed=32)
+    assert abs(a - b) <= 5 * np.hypot(sd, sd2), (a, b)
+    # and the asymmetry is real: without the azimuth mirror the values differ
+    c, sd3 = _mc_mean_sd(orc, ay, ax, mu, phi, n, seed=33)
+    assert abs(a - c) > 5 * np.hypot(sd, sd3), (a, c)
