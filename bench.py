@@ -46,6 +46,13 @@ def parse():
     return ap.parse_args()
 
 
+def _bandwidth(bytes_per_element, ms):
+    """GB/s of a streaming launch over the 2^26-element workload, and its
+    fraction of the 8 TB/s HBM peak."""
+    gbs = bytes_per_element * N_STREAM / ms / 1e6
+    return {"gbytes_per_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def timed(fn, steps, warmup):
     """Mean ms per call of fn over `steps` calls on the current stream, with
     events recorded on that stream and device synchronisation around."""
@@ -172,7 +179,8 @@ def main():
         log("timing the disk-2018 sampler")
         ms_disk, _ = timed(run(1), args.steps, args.warmup)
         out["disk2018"] = {"ms_per_launch": round(ms_disk, 5),
-                           "gsamples_per_s": round(N_STREAM / ms_disk / 1e6, 3)}
+                           "gsamples_per_s": round(N_STREAM / ms_disk / 1e6, 3),
+                           **_bandwidth(BYTES_PER_SAMPLE, ms_disk)}
         if ms_cap:
             out["disk2018"]["t_disk_over_t_cap"] = round(ms_disk / ms_cap, 4)
     if "probe" in only:
@@ -184,7 +192,7 @@ def main():
         ms_w, _ = timed(lambda: cv.capvndf_stream_probe(ins, outs, mode=2), args.steps,
                         args.warmup)
         out["stream_probe"] = {"ms_per_launch": round(ms_p, 5),
-                               "gbytes_per_s": round(BYTES_PER_SAMPLE * N_STREAM / ms_p / 1e6, 1),
+                               **_bandwidth(BYTES_PER_SAMPLE, ms_p),
                                "read_only_gbytes_per_s": round(20 * N_STREAM / ms_r / 1e6, 1),
                                "write_only_gbytes_per_s": round(16 * N_STREAM / ms_w / 1e6, 1)}
     if "inverse" in only:
@@ -197,14 +205,14 @@ def main():
                         args.steps, args.warmup)
         out["inverse_map"] = {"ms_per_launch": round(ms_i, 5),
                               "gsamples_per_s": round(N_STREAM / ms_i / 1e6, 3),
-                              "gbytes_per_s": round(40 * N_STREAM / ms_i / 1e6, 1),
+                              **_bandwidth(40, ms_i),
                               "bytes_per_sample": 40}
         log("timing the VNDF pdf at the sampled normals")
         ms_p, _ = timed(lambda: cv.vndf_pdf(t["wx"], t["wy"], t["wz"], outs[0], outs[1], outs[2],
                                             t["ax"], t["ay"], out=u1b), args.steps, args.warmup)
         out["vndf_pdf"] = {"ms_per_launch": round(ms_p, 5),
                            "gsamples_per_s": round(N_STREAM / ms_p / 1e6, 3),
-                           "gbytes_per_s": round(36 * N_STREAM / ms_p / 1e6, 1),
+                           **_bandwidth(36, ms_p),
                            "bytes_per_sample": 36}
         del u1b, u2b
     if "dielectric" in only:
@@ -220,11 +228,11 @@ def main():
             "eta": 1.5,
             "sample": {"ms_per_launch": round(ms_ds, 5),
                        "gsamples_per_s": round(N_STREAM / ms_ds / 1e6, 3),
-                       "gbytes_per_s": round(40 * N_STREAM / ms_ds / 1e6, 1),
+                       **_bandwidth(40, ms_ds),
                        "bytes_per_sample": 40},
             "pdf": {"ms_per_launch": round(ms_dp, 5),
                     "gsamples_per_s": round(N_STREAM / ms_dp / 1e6, 3),
-                    "gbytes_per_s": round(36 * N_STREAM / ms_dp / 1e6, 1),
+                    **_bandwidth(36, ms_dp),
                     "bytes_per_sample": 36}}
         del douts
     if "micro" in only:
