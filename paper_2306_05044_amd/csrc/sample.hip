@@ -73,11 +73,10 @@ __device__ __forceinline__ void stream_u(uint64_t k, uint32_t key0, uint32_t key
 }
 
 // Vector path (index_base even, arrays 16-byte aligned).  A block owns a tile
-// of kBlock * 4 * kGroups consecutive tuples; lane l handles kGroups groups of
-// four, group g starting at tile + (g * kBlock + l) * 4, so every wavefront
-// access is a contiguous 1 KiB per array.  All loads of a lane are issued
-// before any arithmetic to keep enough bytes in flight.  Groups that straddle
-// n finish their tuples one by one.
+// of kBlock * 4 * kGroups consecutive tuples and each lane kGroups groups of
+// four (see group_start: every wavefront reads a contiguous run per array).
+// All loads of a lane are issued before any arithmetic to keep enough bytes
+// in flight.  Groups that straddle n finish their tuples one by one.
 template <int METHOD, bool EXPLICIT_U, bool WITH_PDF>
 __global__ __launch_bounds__(kBlock) void k_sample_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
@@ -85,23 +84,20 @@ __global__ __launch_bounds__(kBlock) void k_sample_v4(
     const float* __restrict__ u1p, const float* __restrict__ u2p, uint64_t index_base,
     uint32_t key0, uint32_t key1, float* __restrict__ hx, float* __restrict__ hy,
     float* __restrict__ hz, float* __restrict__ pdf) {
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
+    const int64_t tile = (int64_t)blockIdx.x * kTile;
     f4 x[kGroups], y[kGroups], z[kGroups], a[kGroups], b[kGroups], r1[kGroups], r2[kGroups];
-#pragma unroll
-    for (int g = 0; g < kGroups; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
-        if (i0 + 4 <= n) {
-            x[g] = load4(wix + i0); y[g] = load4(wiy + i0); z[g] = load4(wiz + i0);
-            a[g] = load4(ax + i0); b[g] = load4(ay + i0);
-            if (EXPLICIT_U) {
-                r1[g] = load4(u1p + i0);
-                r2[g] = load4(u2p + i0);
-            }
-        }
+    load_groups(x, wix, tile, n);
+    load_groups(y, wiy, tile, n);
+    load_groups(z, wiz, tile, n);
+    load_groups(a, ax, tile, n);
+    load_groups(b, ay, tile, n);
+    if (EXPLICIT_U) {
+        load_groups(r1, u1p, tile, n);
+        load_groups(r2, u2p, tile, n);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        const int64_t i0 = group_start<kGroups>(tile, g);
         if (i0 + 4 <= n) {
             if (!EXPLICIT_U) {
                 const uint64_t pair = (index_base >> 1) + (uint64_t)(i0 >> 1);
@@ -188,20 +184,19 @@ __global__ __launch_bounds__(kBlock) void k_pdf_v4(
     const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
     const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
     float* __restrict__ pdf) {
-    const int64_t base = (int64_t)blockIdx.x * kBlock * 4 * G + (int64_t)threadIdx.x * 4;
+    const int64_t tile = (int64_t)blockIdx.x * kBlock * 4 * G;
     f4 x[G], y[G], z[G], hx[G], hy[G], hz[G], a[G], b[G];
+    load_groups(x, wix, tile, n);
+    load_groups(y, wiy, tile, n);
+    load_groups(z, wiz, tile, n);
+    load_groups(hx, hxp, tile, n);
+    load_groups(hy, hyp, tile, n);
+    load_groups(hz, hzp, tile, n);
+    load_groups(a, ax, tile, n);
+    load_groups(b, ay, tile, n);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
-        if (i0 + 4 <= n) {
-            x[g] = load4(wix + i0); y[g] = load4(wiy + i0); z[g] = load4(wiz + i0);
-            hx[g] = load4(hxp + i0); hy[g] = load4(hyp + i0); hz[g] = load4(hzp + i0);
-            a[g] = load4(ax + i0); b[g] = load4(ay + i0);
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        const int64_t i0 = group_start<G>(tile, g);
         if (i0 + 4 <= n) {
             f4 o;
 #pragma unroll
@@ -260,20 +255,19 @@ __global__ __launch_bounds__(kBlock) void k_inverse_v4(
     const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
     const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
     float* __restrict__ u1p, float* __restrict__ u2p) {
-    const int64_t base = (int64_t)blockIdx.x * kBlock * 4 * G + (int64_t)threadIdx.x * 4;
+    const int64_t tile = (int64_t)blockIdx.x * kBlock * 4 * G;
     f4 x[G], y[G], z[G], hx[G], hy[G], hz[G], a[G], b[G];
+    load_groups(x, wix, tile, n);
+    load_groups(y, wiy, tile, n);
+    load_groups(z, wiz, tile, n);
+    load_groups(hx, hxp, tile, n);
+    load_groups(hy, hyp, tile, n);
+    load_groups(hz, hzp, tile, n);
+    load_groups(a, ax, tile, n);
+    load_groups(b, ay, tile, n);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
-        if (i0 + 4 <= n) {
-            x[g] = load4(wix + i0); y[g] = load4(wiy + i0); z[g] = load4(wiz + i0);
-            hx[g] = load4(hxp + i0); hy[g] = load4(hyp + i0); hz[g] = load4(hzp + i0);
-            a[g] = load4(ax + i0); b[g] = load4(ay + i0);
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        const int64_t i0 = group_start<G>(tile, g);
         if (i0 + 4 <= n) {
             f4 o1, o2;
 #pragma unroll
@@ -376,21 +370,18 @@ __global__ __launch_bounds__(kBlock) void k_stream_probe(
     const float* __restrict__ in2, const float* __restrict__ in3,
     const float* __restrict__ in4, float* __restrict__ out0, float* __restrict__ out1,
     float* __restrict__ out2, float* __restrict__ out3) {
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * 4;
+    const int64_t tile = (int64_t)blockIdx.x * kTile;
     f4 a[kGroups], b[kGroups], c[kGroups], d[kGroups], e[kGroups];
     if (MODE != 2) {
-#pragma unroll
-        for (int g = 0; g < kGroups; ++g) {
-            const int64_t i0 = base + (int64_t)g * kBlock * 4;
-            if (i0 + 4 <= n) {
-                a[g] = load4(in0 + i0); b[g] = load4(in1 + i0); c[g] = load4(in2 + i0);
-                d[g] = load4(in3 + i0); e[g] = load4(in4 + i0);
-            }
-        }
+        load_groups(a, in0, tile, n);
+        load_groups(b, in1, tile, n);
+        load_groups(c, in2, tile, n);
+        load_groups(d, in3, tile, n);
+        load_groups(e, in4, tile, n);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
-        const int64_t i0 = base + (int64_t)g * kBlock * 4;
+        const int64_t i0 = group_start<kGroups>(tile, g);
         if (i0 + 4 <= n) {
             if (MODE == 0) {
                 store4(out0 + i0, a[g] + e[g]);
