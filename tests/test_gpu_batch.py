@@ -124,3 +124,20 @@ def test_autotune_small(tmp_path, monkeypatch):
     plan.run()
     torch.cuda.synchronize()
     _check(plan, j, 1.0, True)
+
+
+@pytest.mark.parametrize("tiling", [None, (256, 8, 4, 1)])
+@pytest.mark.parametrize("n_samples", [1, 2, 1 << 20])
+def test_single_job(n_samples, tiling):
+    """A batch of one job: one sample, one pair, and a job large enough to be
+    split over many chunks and blocks."""
+    j = workloads.batch_jobs(1, seed=9)
+    j["n"][0] = n_samples
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True,
+                        tiling=tiling)
+    plan.run()
+    torch.cuda.synchronize()
+    _check(plan, j, 1.0, True)
+    assert plan.info()["total_samples"] == n_samples
+    plan.close()
