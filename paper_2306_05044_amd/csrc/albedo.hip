@@ -3,10 +3,12 @@
 // fixed-order finishing pass, plus their C entry points.
 //
 // Work decomposition: a cell (or job) of N samples is N/2 Philox pairs, cut
-// into chunks of block * pairs_per_thread pairs.  One block reduces one chunk
-// to a compensated partial (lane TwoSum accumulators -> wavefront butterfly ->
-// LDS across waves); the finishing pass merges a cell's chunk partials in
-// chunk order.  No atomics anywhere, so every result is bitwise reproducible.
+// into chunks of block * pairs_per_thread pairs (or 64 * pairs_per_thread when
+// a batch gives chunks to single wavefronts).  The owner reduces a chunk to a
+// compensated partial (lane TwoSum accumulators -> wavefront DPP/permute
+// butterfly -> LDS across waves); the finishing pass merges a cell's chunk
+// partials in chunk order.  No atomics anywhere, so every result is bitwise
+// reproducible.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
