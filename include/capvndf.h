@@ -137,12 +137,14 @@ int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float*
  *   n            number of tuples (>= 0)
  *   wix,wiy,wiz  unit incident directions on the upper side, w_z > 0      [n]
  *   ax, ay       roughness                                               [n]
+ *   u1, u2, u3   caller-given uniforms in [0, 1) (u1 azimuth, u2 height on
+ *                the cap, u3 the lobe), or all three NULL to draw them from
+ *                the Philox block with counter (lo32(k), 0, 5, hi32(k)),
+ *                k = index_base + i, words 0, 1, 2                       [n]
  *   eta          relative index of refraction n_lower / n_upper: finite,
  *                > 0 and != 1 (1.5 for glass seen from air, 1/1.5 for air
  *                seen from inside glass with the frame flipped)
- *   seed, index_base  Philox key and stream offset: tuple i uses the block
- *                with counter (lo32(k), 0, 5, hi32(k)), k = index_base + i,
- *                u1, u2, u3 from its words 0, 1, 2 (u3 chooses the lobe)
+ *   seed, index_base  Philox key and stream offset (ignored with explicit u)
  *   wox,woy,woz  out: unit outgoing directions                           [n]
  *   pdf          out: density of wo per unit solid angle, the lobe
  *                probability times the VNDF times |dh/dwo|               [n]
@@ -152,12 +154,14 @@ int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float*
  * A reflected direction below the surface or a transmitted one above it is
  * no sample: its pdf and weight are 0 (wo is still written).  Inputs outside
  * the domain (w_z <= 0, alpha <= 0) give wo = (0, 0, 1), pdf = weight = 0.
- * Errors: NULL_PTR, BAD_SIZE (n < 0), MISALIGNED, BAD_ARG (eta), HIP.
+ * Errors: NULL_PTR (a required array is NULL or only some of u1, u2, u3
+ * given), BAD_SIZE (n < 0), MISALIGNED, BAD_ARG (eta), HIP.
  */
 int32_t dielectric_sample(int64_t n, const float* wix, const float* wiy, const float* wiz,
-                          const float* ax, const float* ay, float eta, uint64_t seed,
-                          uint64_t index_base, float* wox, float* woy, float* woz, float* pdf,
-                          float* weight, void* stream);
+                          const float* ax, const float* ay, const float* u1, const float* u2,
+                          const float* u3, float eta, uint64_t seed, uint64_t index_base,
+                          float* wox, float* woy, float* woz, float* pdf, float* weight,
+                          void* stream);
 
 /*
  * dielectric_pdf -- the density of dielectric_sample at caller-given unit

@@ -61,8 +61,8 @@ _SIGNATURES = {
     "vndf_sample": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _U64, _I32, _P, _P, _P, _P, _P], _I32),
     "vndf_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "vndf_inverse": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
-    "dielectric_sample": ([_I64, _P, _P, _P, _P, _P, ctypes.c_float, _U64, _U64, _P, _P, _P, _P,
-                           _P, _P], _I32),
+    "dielectric_sample": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _U64, _U64, _P,
+                           _P, _P, _P, _P, _P], _I32),
     "dielectric_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _P, _P], _I32),
     "albedo_workspace_size": ([_I64, _I64, _I32], ctypes.c_size_t),
     "albedo_estimate": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, ctypes.c_size_t, _P],
@@ -212,13 +212,18 @@ def vndf_inverse(wix, wiy, wiz, hx, hy, hz, ax, ay, out=None, stream=None):
     return u1, u2
 
 
-def dielectric_sample(wix, wiy, wiz, ax, ay, eta, seed=0, index_base=0, out=None, stream=None):
-    """Rough-dielectric sampling with the cap VNDF: (wox, woy, woz, pdf, weight)."""
+def dielectric_sample(wix, wiy, wiz, ax, ay, eta, seed=0, index_base=0, u=None, out=None,
+                      stream=None):
+    """Rough-dielectric sampling with the cap VNDF: (wox, woy, woz, pdf, weight).
+    ``u`` is None (Philox stream) or a tuple (u1, u2, u3) of float32 tensors."""
     lib = load_library()
     n = wix.numel()
-    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, ax=ax, ay=ay).items():
+    us = (None, None, None) if u is None else tuple(u)
+    if len(us) != 3:
+        raise ValueError("u must be None or (u1, u2, u3)")
+    for k, t in dict(wix=wix, wiy=wiy, wiz=wiz, ax=ax, ay=ay, u1=us[0], u2=us[1], u3=us[2]).items():
         _dev(t, k)
-    _same_len(n, wiy=wiy, wiz=wiz, ax=ax, ay=ay)
+    _same_len(n, wiy=wiy, wiz=wiz, ax=ax, ay=ay, u1=us[0], u2=us[1], u3=us[2])
     if out is None:
         outs = tuple(torch.empty_like(wix) for _ in range(5))
     else:
@@ -226,9 +231,9 @@ def dielectric_sample(wix, wiy, wiz, ax, ay, eta, seed=0, index_base=0, out=None
         if len(outs) != 5:
             raise ValueError("out must hold (wox, woy, woz, pdf, weight)")
         _same_len(n, **{f"out{i}": x for i, x in enumerate(outs)})
-    rc = lib.dielectric_sample(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(ax), _ptr(ay), float(eta),
-                               int(seed), int(index_base), *[_ptr(x) for x in outs],
-                               _stream(stream))
+    rc = lib.dielectric_sample(n, _ptr(wix), _ptr(wiy), _ptr(wiz), _ptr(ax), _ptr(ay),
+                               *[_ptr(x) for x in us], float(eta), int(seed), int(index_base),
+                               *[_ptr(x) for x in outs], _stream(stream))
     _check("dielectric_sample", rc)
     return outs
 

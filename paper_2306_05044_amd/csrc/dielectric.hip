@@ -113,20 +113,26 @@ __device__ __forceinline__ void dielectric_u(uint64_t k, uint32_t key0, uint32_t
 
 // Vector path (arrays 16-byte aligned): tiles of BLOCK * 4 * G tuples, all
 // loads of a lane issued before any arithmetic.
-template <int G, int BLOCK>
+template <int G, int BLOCK, bool EXPLICIT_U>
 __global__ __launch_bounds__(BLOCK) void k_dielectric_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
     const float* __restrict__ wiz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ u1p, const float* __restrict__ u2p, const float* __restrict__ u3p,
     Eta e, uint64_t index_base, uint32_t key0, uint32_t key1, float* __restrict__ wox,
     float* __restrict__ woy, float* __restrict__ woz, float* __restrict__ pdf,
     float* __restrict__ weight) {
     const int64_t tile = (int64_t)blockIdx.x * BLOCK * 4 * G;
-    f4 x[G], y[G], z[G], a[G], b[G];
+    f4 x[G], y[G], z[G], a[G], b[G], r1[G], r2[G], r3[G];
     load_groups<G, BLOCK>(x, wix, tile, n);
     load_groups<G, BLOCK>(y, wiy, tile, n);
     load_groups<G, BLOCK>(z, wiz, tile, n);
     load_groups<G, BLOCK>(a, ax, tile, n);
     load_groups<G, BLOCK>(b, ay, tile, n);
+    if (EXPLICIT_U) {
+        load_groups<G, BLOCK>(r1, u1p, tile, n);
+        load_groups<G, BLOCK>(r2, u2p, tile, n);
+        load_groups<G, BLOCK>(r3, u3p, tile, n);
+    }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         const int64_t i0 = group_start<G, BLOCK>(tile, g);
@@ -135,7 +141,11 @@ __global__ __launch_bounds__(BLOCK) void k_dielectric_v4(
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 float u1, u2, u3;
-                dielectric_u(index_base + (uint64_t)(i0 + j), key0, key1, u1, u2, u3);
+                if (EXPLICIT_U) {
+                    u1 = r1[g][j]; u2 = r2[g][j]; u3 = r3[g][j];
+                } else {
+                    dielectric_u(index_base + (uint64_t)(i0 + j), key0, key1, u1, u2, u3);
+                }
                 const DielectricOut o =
                     dielectric_one(x[g][j], y[g][j], z[g][j], a[g][j], b[g][j], u1, u2, u3, e);
                 ox[j] = o.wox; oy[j] = o.woy; oz[j] = o.woz; op[j] = o.pdf; ow[j] = o.weight;
@@ -148,7 +158,11 @@ __global__ __launch_bounds__(BLOCK) void k_dielectric_v4(
         } else {
             for (int64_t i = i0; i < n && i < i0 + 4; ++i) {
                 float u1, u2, u3;
-                dielectric_u(index_base + (uint64_t)i, key0, key1, u1, u2, u3);
+                if (EXPLICIT_U) {
+                    u1 = u1p[i]; u2 = u2p[i]; u3 = u3p[i];
+                } else {
+                    dielectric_u(index_base + (uint64_t)i, key0, key1, u1, u2, u3);
+                }
                 const DielectricOut o = dielectric_one(wix[i], wiy[i], wiz[i], ax[i], ay[i], u1, u2, u3, e);
                 wox[i] = o.wox; woy[i] = o.woy; woz[i] = o.woz; pdf[i] = o.pdf; weight[i] = o.weight;
             }
@@ -157,16 +171,22 @@ __global__ __launch_bounds__(BLOCK) void k_dielectric_v4(
 }
 
 // Scalar path (any 4-byte alignment): one tuple per lane.
+template <bool EXPLICIT_U>
 __global__ __launch_bounds__(kBlock) void k_dielectric_scalar(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
     const float* __restrict__ wiz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ u1p, const float* __restrict__ u2p, const float* __restrict__ u3p,
     Eta e, uint64_t index_base, uint32_t key0, uint32_t key1, float* __restrict__ wox,
     float* __restrict__ woy, float* __restrict__ woz, float* __restrict__ pdf,
     float* __restrict__ weight) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     float u1, u2, u3;
-    dielectric_u(index_base + (uint64_t)i, key0, key1, u1, u2, u3);
+    if (EXPLICIT_U) {
+        u1 = u1p[i]; u2 = u2p[i]; u3 = u3p[i];
+    } else {
+        dielectric_u(index_base + (uint64_t)i, key0, key1, u1, u2, u3);
+    }
     const DielectricOut o = dielectric_one(wix[i], wiy[i], wiz[i], ax[i], ay[i], u1, u2, u3, e);
     wox[i] = o.wox; woy[i] = o.woy; woz[i] = o.woz; pdf[i] = o.pdf; weight[i] = o.weight;
 }
@@ -273,12 +293,16 @@ int32_t make_eta(float eta, const char* who, Eta* out) {
 using namespace capvndf;
 
 extern "C" int32_t dielectric_sample(int64_t n, const float* wix, const float* wiy,
-                                     const float* wiz, const float* ax, const float* ay, float eta,
+                                     const float* wiz, const float* ax, const float* ay,
+                                     const float* u1, const float* u2, const float* u3, float eta,
                                      uint64_t seed, uint64_t index_base, float* wox, float* woy,
                                      float* woz, float* pdf, float* weight, void* stream) {
     if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "dielectric_sample: n = %lld < 0", (long long)n);
     Eta e;
     if (int32_t rc = make_eta(eta, "dielectric_sample", &e)) return rc;
+    const bool eu = u1 != nullptr;
+    if ((u2 != nullptr) != eu || (u3 != nullptr) != eu)
+        return fail(CAPVNDF_ERR_NULL_PTR, "dielectric_sample: give all of u1, u2, u3 or none");
     if (n == 0) return CAPVNDF_OK;
     const void* req[] = {wix, wiy, wiz, ax, ay, wox, woy, woz, pdf, weight};
     const char* names[] = {"wix", "wiy", "wiz", "ax", "ay", "wox", "woy", "woz", "pdf", "weight"};
@@ -287,17 +311,35 @@ extern "C" int32_t dielectric_sample(int64_t n, const float* wix, const float* w
         if (int32_t rc = check_array(req[i], names[i])) return rc;
         if (!aligned_to(req[i], 16)) vec = false;
     }
+    if (eu) {
+        const void* us[] = {u1, u2, u3};
+        const char* un[] = {"u1", "u2", "u3"};
+        for (int i = 0; i < 3; ++i) {
+            if (int32_t rc = check_array(us[i], un[i])) return rc;
+            if (!aligned_to(us[i], 16)) vec = false;
+        }
+    }
     const hipStream_t st = as_stream(stream);
-    if (vec)
-        hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock>),
-                           dim3(tiles_for<kSampleGroups, kSampleBlock>(n)),
-                           dim3(kSampleBlock), 0, st, n, wix, wiy,
-                           wiz, ax, ay, e, index_base, key_lo(seed), key_hi(seed), wox, woy, woz,
-                           pdf, weight);
-    else
-        hipLaunchKernelGGL(k_dielectric_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix,
-                           wiy, wiz, ax, ay, e, index_base, key_lo(seed), key_hi(seed), wox, woy,
-                           woz, pdf, weight);
+    const uint32_t k0 = key_lo(seed), k1 = key_hi(seed);
+    if (vec) {
+        const dim3 grid(tiles_for<kSampleGroups, kSampleBlock>(n)), block(kSampleBlock);
+        if (eu)
+            hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock, true>), grid, block, 0,
+                               st, n, wix, wiy, wiz, ax, ay, u1, u2, u3, e, index_base, k0, k1,
+                               wox, woy, woz, pdf, weight);
+        else
+            hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock, false>), grid, block,
+                               0, st, n, wix, wiy, wiz, ax, ay, u1, u2, u3, e, index_base, k0, k1,
+                               wox, woy, woz, pdf, weight);
+    } else {
+        const dim3 grid(grid_for(n)), block(kBlock);
+        if (eu)
+            hipLaunchKernelGGL(k_dielectric_scalar<true>, grid, block, 0, st, n, wix, wiy, wiz, ax,
+                               ay, u1, u2, u3, e, index_base, k0, k1, wox, woy, woz, pdf, weight);
+        else
+            hipLaunchKernelGGL(k_dielectric_scalar<false>, grid, block, 0, st, n, wix, wiy, wiz, ax,
+                               ay, u1, u2, u3, e, index_base, k0, k1, wox, woy, woz, pdf, weight);
+    }
     return check_launch("dielectric_sample launch");
 }
 

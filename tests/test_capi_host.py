@@ -125,14 +125,19 @@ def test_albedo_argument_errors(lib):
 def test_dielectric_argument_errors(lib):
     P = ctypes.c_void_p
     fake = P(0x1000)  # never dereferenced: validation fails first
-    assert lib.dielectric_sample(-1, *[fake] * 5, 1.5, 0, 0, *[fake] * 5, None) == -2
+    nou = [None] * 3
+    assert lib.dielectric_sample(-1, *[fake] * 5, *nou, 1.5, 0, 0, *[fake] * 5, None) == -2
     for bad in (1.0, 0.0, -1.5, float("inf"), float("nan")):
-        assert lib.dielectric_sample(4, *[fake] * 5, bad, 0, 0, *[fake] * 5, None) == -7
+        assert lib.dielectric_sample(4, *[fake] * 5, *nou, bad, 0, 0, *[fake] * 5, None) == -7
         assert "eta" in _err(lib)
         assert lib.dielectric_pdf(4, *[fake] * 8, bad, fake, None) == -7
-    assert lib.dielectric_sample(4, *[fake] * 5, 1.5, 0, 0, *[fake] * 4, None, None) == -1
+    assert lib.dielectric_sample(4, *[fake] * 5, *nou, 1.5, 0, 0, *[fake] * 4, None, None) == -1
     assert "weight is NULL" in _err(lib)
-    assert lib.dielectric_sample(4, P(0x1002), *[fake] * 4, 1.5, 0, 0, *[fake] * 5, None) == -3
+    assert lib.dielectric_sample(4, *[fake] * 5, fake, None, fake, 1.5, 0, 0, *[fake] * 5,
+                                 None) == -1
+    assert "u1, u2, u3" in _err(lib)
+    assert lib.dielectric_sample(4, P(0x1002), *[fake] * 4, *nou, 1.5, 0, 0, *[fake] * 5,
+                                 None) == -3
     assert lib.dielectric_pdf(-3, *[None] * 8, 1.5, None, None) == -2
     assert lib.dielectric_pdf(0, *[None] * 8, 1.5, None, None) == 0
-    assert lib.dielectric_sample(0, *[None] * 5, 1.5, 0, 0, *[None] * 5, None) == 0
+    assert lib.dielectric_sample(0, *[None] * 5, *nou, 1.5, 0, 0, *[None] * 5, None) == 0

@@ -235,6 +235,28 @@ def test_pdf_entry_point():
         _check(rel, K, 128, f"pdf entry eta {eta:.4f}", both)
 
 
+def test_explicit_uniforms_match_the_stream():
+    """Caller-given (u1, u2, u3) equal to the stream's give the same bits, on
+    the vector path and (through misaligned copies) the scalar path."""
+    n = 4099
+    d = workloads.tuples_small(n, seed=3)
+    t = to_dev(d)
+    a = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, seed=11,
+                             index_base=7)
+    u = [torch.from_numpy(x.astype(np.float32)).cuda() for x in oracle.dielectric_uniforms(n, 11, 7)]
+    b = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, u=u)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    bufs = []
+    for x in u:
+        buf = torch.zeros(n + 1, device="cuda")
+        buf[1:].copy_(x)
+        bufs.append(buf[1:])
+    c = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, u=bufs)
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
+
+
 def test_determinism():
     d = workloads.tuples_streaming(1 << 16, seed=1)
     t = to_dev(d)
