@@ -5,9 +5,11 @@ tuples (FP32 structure of arrays in HBM, Philox uniforms drawn in-kernel,
 outputs h and its pdf).  The JSON line's value is that sampler's throughput in
 Gsamples/s; alongside it the line reports the Heitz-2018 disk sampler on the
 same inputs, the register-resident cap-vs-disk microbenchmark, the
-directional-albedo table forward+backward time and its error against the FP64
-oracle, the batched estimator against per-request launches, the roofline of
-the streaming kernel and the FP64 oracle timed on the host cores.
+directional-albedo table forward+backward time, the batched estimator against
+per-request launches, the roofline of the streaming kernel, and -- in the CPU
+leg, which is the only part that runs the FP64 oracle -- the oracle timed on
+the host cores and its values at a few table cells, against which the
+estimators' errors are reported.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only SECTION ...]
            [--no-cpu-baseline]
@@ -141,6 +143,29 @@ def cpu_baseline(d):
                       f"median of 3 runs ({dt:.2f} s each on {threads} host threads)"}
 
 
+def oracle_checks(checks):
+    """The CPU leg's second part: the FP64 oracle at the cells whose GPU values
+    the estimator sections kept (same Philox streams), max |GPU - oracle|."""
+    import numpy as np
+    import oracle
+    errs = {}
+    if "albedo_lut" in checks:
+        c = checks["albedo_lut"]
+        g = c["grid"]
+        wo = (g["wx"], g["wy"], g["wz"])
+        a1 = oracle.albedo(wo, g["ax"], g["ay"], c["n"], 2, f0=1.0, units=c["cells"])
+        a5 = oracle.albedo(wo, g["ax"], g["ay"], c["n"], 2, f0=0.0, units=c["cells"])
+        errs["albedo_lut"] = max(np.abs(c["s1"] - a1).max(), np.abs(c["s5"] - a5).max(),
+                                 np.abs(c["a004"] - (0.04 * a1 + 0.96 * a5)).max())
+    if "direct_illumination" in checks:
+        c = checks["direct_illumination"]
+        g = c["grid"]
+        ref = oracle.radiance((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], c["n"], 2,
+                              c["lobes"].astype(np.float64), units=c["cells"])
+        errs["direct_illumination"] = np.abs(c["value"] - ref).max()
+    return errs
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -160,6 +185,7 @@ def main():
     torch.cuda.set_device(dev)
     cv.load_library()
     out = {}
+    checks = {}  # GPU values at a few cells, compared with the oracle in the CPU leg
 
     log("generating the 2^26-tuple streaming workload")
     d = workloads.tuples_streaming(N_STREAM, seed=1)
@@ -254,7 +280,6 @@ def main():
     torch.cuda.empty_cache()
 
     if "lut" in only:
-        import oracle
         log("albedo table 64 x 64 x 2^20: forward, backward, one-pass value + gradient")
         g = workloads.lut_grid(64, 64)
         c = {k: torch.from_numpy(v).to(dev) for k, v in g.items()}
@@ -281,13 +306,10 @@ def main():
         a004 = fused()[0]
         torch.cuda.synchronize()
         cells = np.array([0, 1000, 2047, 3333, 4095])
-        sub = {k: v[cells] for k, v in g.items()}
-        wo = (sub["wx"], sub["wy"], sub["wz"])
-        a1 = oracle.albedo(wo, sub["ax"], sub["ay"], n, 2, f0=1.0, units=cells)
-        a5 = oracle.albedo(wo, sub["ax"], sub["ay"], n, 2, f0=0.0, units=cells)
-        err = max(np.abs(s1.cpu().numpy()[cells] - a1).max(),
-                  np.abs(s5.cpu().numpy()[cells] - a5).max(),
-                  np.abs(a004.cpu().numpy()[cells] - (0.04 * a1 + 0.96 * a5)).max())
+        checks["albedo_lut"] = {"grid": {k: v[cells] for k, v in g.items()}, "cells": cells,
+                                "n": n, "s1": s1.cpu().numpy()[cells],
+                                "s5": s5.cpu().numpy()[cells],
+                                "a004": a004.cpu().numpy()[cells]}
         samples = 4096 * n
         out["albedo_lut"] = {
             "cells": 4096, "samples_per_cell": n,
@@ -299,8 +321,6 @@ def main():
             "fwd_gsamples_per_s": round(samples / ms_f / 1e6, 2),
             "bwd_gsamples_per_s": round(samples / ms_b / 1e6, 2),
             "fwd_bwd_gsamples_per_s": round(samples / ms_vg / 1e6, 2),
-            "max_abs_err_vs_oracle": float(f"{err:.3e}"),
-            "err_checked_cells": int(len(cells)),
             "roofline_fwd": alu_roofline("forward_two_sums", samples, ms_f),
             "roofline_fwd_bwd": alu_roofline("value_and_grad", samples, ms_vg)}
         del c, ws
@@ -372,7 +392,6 @@ def main():
         out["batched"]["short_jobs"] = res_s
 
     if "radiance" in only:
-        import oracle
         log("direct illumination 64 x 64 x 2^20 under 4 spherical-Gaussian lobes")
         g = workloads.lut_grid(64, 64)
         c = {k: torch.from_numpy(v).to(dev) for k, v in g.items()}
@@ -390,14 +409,12 @@ def main():
         r = rad()
         torch.cuda.synchronize()
         cells = np.array([5, 2900, 4095])
-        sub = {k: v[cells] for k, v in g.items()}
-        ref = oracle.radiance((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"], n, 2,
-                              lobes_np.astype(np.float64), units=cells)
+        checks["direct_illumination"] = {"grid": {k: v[cells] for k, v in g.items()},
+                                         "cells": cells, "n": n, "lobes": lobes_np,
+                                         "value": r.cpu().numpy()[cells]}
         out["direct_illumination"] = {
             "cells": 4096, "samples_per_cell": n, "lobes": 4, "ms": round(ms_r, 4),
-            "gsamples_per_s": round(4096 * n / ms_r / 1e6, 2),
-            "max_abs_err_vs_oracle": float(f"{np.abs(r.cpu().numpy()[cells] - ref).max():.3e}"),
-            "err_checked_cells": int(len(cells))}
+            "gsamples_per_s": round(4096 * n / ms_r / 1e6, 2)}
 
     result = {"metric": METRIC, "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
@@ -421,9 +438,15 @@ def main():
         "tuples": N_STREAM, "method": "cap", "bytes_per_sample": BYTES_PER_SAMPLE,
         "parallelism": "single GPU"}
     result.update(out)
-    if not args.no_cpu_baseline and ms_cap is not None:
-        log("timing the FP64 oracle on the host cores")
-        result["cpu_baseline"] = cpu_baseline(d)
+    if not args.no_cpu_baseline:
+        if ms_cap is not None:
+            log("timing the FP64 oracle on the host cores")
+            result["cpu_baseline"] = cpu_baseline(d)
+        if checks:
+            log("checking the estimators at sampled cells against the FP64 oracle")
+            for key, err in oracle_checks(checks).items():
+                result[key]["max_abs_err_vs_oracle"] = float(f"{err:.3e}")
+                result[key]["err_checked_cells"] = int(len(checks[key]["cells"]))
     print(json.dumps(result), flush=True)
 
 
