@@ -19,33 +19,42 @@ class AlbedoFunction(torch.autograd.Function):
 
     Inputs: ax, ay, theta_o, phi_o, f0 -- float32 GPU tensors of one shape --
     then nsamples (int) and seed (int).  Gradients flow to ax, ay and theta_o
-    (theta_o is the polar angle of the view direction, phi_o its azimuth).
+    (theta_o is the polar angle of the view direction, phi_o its azimuth) by
+    the pathwise adjoint, and to f0 exactly (A is linear in F0); phi_o gets
+    none.
     """
 
     @staticmethod
     def forward(ctx, ax, ay, theta_o, phi_o, f0, nsamples, seed):
-        from . import albedo_value_and_grad
+        from . import albedo_estimate, albedo_value_and_grad
         # view direction from its spherical angles (argument marshalling)
         st = torch.sin(theta_o)
         wox = (st * torch.cos(phi_o)).contiguous().reshape(-1)
         woy = (st * torch.sin(phi_o)).contiguous().reshape(-1)
         woz = torch.cos(theta_o).contiguous().reshape(-1)
+        axf, ayf = ax.contiguous().reshape(-1), ay.contiguous().reshape(-1)
         need = any(ctx.needs_input_grad[:3])
         a, gx, gy, gt = albedo_value_and_grad(
-            wox, woy, woz, ax.contiguous().reshape(-1), ay.contiguous().reshape(-1),
-            int(nsamples), int(seed), f0=f0.contiguous().reshape(-1), with_grad=need)
+            wox, woy, woz, axf, ayf, int(nsamples), int(seed), f0=f0.contiguous().reshape(-1),
+            with_grad=need)
         shape = ax.shape
-        if need:
-            ctx.save_for_backward(gx.reshape(shape), gy.reshape(shape), gt.reshape(shape))
+        saved = [gx.reshape(shape), gy.reshape(shape), gt.reshape(shape)] if need else [None] * 3
+        if ctx.needs_input_grad[4]:
+            # the estimate is linear in F0: dA/dF0 = S1 - S5 on the same stream
+            s1, s5 = albedo_estimate(wox, woy, woz, axf, ayf, int(nsamples), int(seed))
+            saved.append((s1 - s5).reshape(shape))
+        else:
+            saved.append(None)
+        ctx.save_for_backward(*saved)
         return a.reshape(shape)
 
     @staticmethod
     def backward(ctx, grad_a):
-        jx, jy, jt = ctx.saved_tensors
+        jx, jy, jt, jf = ctx.saved_tensors
         g = grad_a.to(torch.float32)
-        return (g * jx if ctx.needs_input_grad[0] else None,
-                g * jy if ctx.needs_input_grad[1] else None,
-                g * jt if ctx.needs_input_grad[2] else None, None, None, None, None)
+        need = ctx.needs_input_grad
+        return (g * jx if need[0] else None, g * jy if need[1] else None,
+                g * jt if need[2] else None, None, g * jf if need[4] else None, None, None)
 
 
 def albedo(ax, ay, theta_o, phi_o, f0, nsamples, seed):

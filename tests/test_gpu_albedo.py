@@ -195,6 +195,26 @@ def test_autograd_function():
     _check_grad(host(th.grad), W * rt, "autograd theta_o")
 
 
+def test_autograd_f0_gradient():
+    """dA/dF0 = S1 - S5 (the estimate is linear in F0), against the oracle's
+    two sums on the same stream; phi_o gets no gradient."""
+    gg = workloads.grad_grid(5, seed=12)
+    ax = torch.from_numpy(gg["ax"]).cuda()
+    ay = torch.from_numpy(gg["ay"]).cuda()
+    th = torch.from_numpy(gg["theta"]).cuda()
+    ph = torch.from_numpy(gg["phi"]).cuda()
+    f0 = torch.full_like(ph, 0.3).requires_grad_(True)
+    n = 4097
+    a = cv.albedo(ax, ay, th, ph, f0, n, 6)
+    a.sum().backward()
+    wo = [host(x) for x in (torch.sin(th) * torch.cos(ph), torch.sin(th) * torch.sin(ph),
+                            torch.cos(th))]
+    s1 = oracle.albedo(wo, gg["ax"], gg["ay"], n, 6, f0=1.0)
+    s5 = oracle.albedo(wo, gg["ax"], gg["ay"], n, 6, f0=0.0)
+    assert np.abs(host(f0.grad) - (s1 - s5)).max() <= 2e-4
+    assert np.abs(host(a.detach()) - (0.3 * s1 + 0.7 * s5)).max() <= ATOL_A
+
+
 def test_estimator_determinism():
     g = workloads.lut_grid(8, 8)
     t = to_dev(g)
