@@ -351,8 +351,12 @@ def main():
         tune_s = time.perf_counter() - t0
         steps = max(3, args.steps // 10)
         plan0 = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
-                             with_grad=True, tiling=(256, 32, 8, 0))
+                             with_grad=True, tiling=(256, 32, 8, 0, 0))
         ms_default, _ = timed(plan0.run, steps, 2)
+        plan0.close()
+        plan0 = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
+                             with_grad=True, tiling=(256, 32, 8, 0, 1))
+        ms_default_dyn, _ = timed(plan0.run, steps, 2)
         plan0.close()
         plan = cv.BatchPlan(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], j["n"], 4,
                             with_grad=True, tiling=best)
@@ -366,6 +370,7 @@ def main():
                           "graph_ms": round(ms_b, 4), "per_request_ms": round(ms_r, 4),
                           "speedup": round(ms_r / ms_b, 3),
                           "default_tiling_ms": round(ms_default, 4),
+                          "default_tiling_dynamic_ms": round(ms_default_dyn, 4),
                           "autotune_s": round(tune_s, 2),
                           "gsamples_per_s_fwd_adj": round(info["total_samples"] / ms_b / 1e6, 2),
                           "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}")}
@@ -378,8 +383,9 @@ def main():
         best_s, _ = cv.albedo_batch_autotune(cs["wx"], cs["wy"], cs["wz"], cs["ax"], cs["ay"],
                                              js["n"], 4, with_grad=True)
         res_s = {}
-        for name, til in (("autotuned", best_s), ("block_owned_default", (256, 32, 8, 0)),
-                          ("wave_owned", (256, 16, 8, 1))):
+        for name, til in (("autotuned", best_s), ("block_owned_default", (256, 32, 8, 0, 0)),
+                          ("wave_owned", (256, 16, 8, 1, 0)),
+                          ("wave_owned_dynamic", (256, 16, 8, 1, 1))):
             p2 = cv.BatchPlan(cs["wx"], cs["wy"], cs["wz"], cs["ax"], cs["ay"], js["n"], 4,
                               with_grad=True, tiling=til)
             res_s[name + "_ms"] = round(timed(p2.run, max(5, args.steps // 5), 2)[0], 4)

@@ -296,16 +296,20 @@ int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy, co
  * unit j of tag 3, so its values equal albedo_estimate/backward on that job.
  *
  * Tiling: block size, pairs of samples per thread per chunk (multiple of 8),
- * resident blocks per compute unit, and who owns a chunk: the whole block
+ * resident blocks per compute unit, who owns a chunk -- the whole block
  * (per_wave = 0; block-wide reduction through LDS) or a single wavefront
  * (per_wave = 1; smaller chunks, wave-only reduction, so short jobs occupy 64
- * lanes instead of a block).
+ * lanes instead of a block) -- and how chunks reach their owners: a static
+ * partition balanced by sample count (dynamic = 0) or the next index from a
+ * device counter (dynamic = 1; balances run-time differences, still
+ * deterministic since every chunk has its own result slot).
  */
 typedef struct capvndf_tiling {
     int32_t block;            /* 256 or 512 threads                          */
     int32_t pairs_per_thread; /* chunk = owner lanes * pairs_per_thread pairs */
     int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu        */
     int32_t per_wave;         /* 0: a block owns a chunk; 1: a wavefront does */
+    int32_t dynamic;          /* 0: static chunk ranges; 1: chunk counter      */
 } capvndf_tiling;
 
 typedef struct capvndf_batch_plan capvndf_batch_plan;
@@ -322,7 +326,7 @@ typedef struct capvndf_batch_plan capvndf_batch_plan;
  *   grad_ax, grad_ay, grad_theta_o [njobs] device out (ignored if !with_grad)
  *   tiling                NULL: the tuned tiling cached for this problem
  *                         signature (CAPVNDF_TUNE_CACHE file) or the default
- *                         {256, 32, 8, 0}
+ *                         {256, 32, 8, 0, 0}
  *   stream                unused: the graph is captured on a private stream
  *                         of the current device, which the plan belongs to
  *   out                   receives the plan
@@ -337,7 +341,11 @@ int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, const float* w
                                  capvndf_batch_plan** out);
 
 /* Replay the plan's graph on `stream` (one hipGraphLaunch).  The current
- * device must be the plan's.  Errors: NULL_PTR, BAD_ARG (other device), HIP. */
+ * device must be the plan's.  A plan's partials (and, with dynamic = 1, its
+ * chunk counter, which the graph resets with a kernel before each launch)
+ * belong to the plan: replays of one plan must not overlap (issue them on one
+ * stream or order them with events); different plans may run concurrently.
+ * Errors: NULL_PTR, BAD_ARG (other device), HIP. */
 int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream);
 
 /* Same jobs and outputs as albedo_batch_run, launched the per-request way:
@@ -360,7 +368,8 @@ void albedo_batch_plan_destroy(capvndf_batch_plan* plan);
  * time per run in *best_ms.  When CAPVNDF_TUNE_CACHE names a file, the result
  * is stored there under the problem signature for later plans.  Candidates:
  * block 256 or 512 threads x pairs_per_thread 8..64 (block-owned chunks) or
- * 8..128 (wavefront-owned chunks) x blocks_per_cu 2..16 (2..8 for 512).
+ * 8..128 (wavefront-owned chunks) x blocks_per_cu 2..16 (2..8 for 512), each
+ * with static and dynamic chunk assignment.
  * Arguments as albedo_batch_plan_create; outputs are overwritten.
  */
 int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const float* woy,

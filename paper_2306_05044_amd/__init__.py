@@ -43,10 +43,12 @@ class CapvndfError(RuntimeError):
 
 class Tiling(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("pairs_per_thread", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("per_wave", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("per_wave", ctypes.c_int32),
+                ("dynamic", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.block, self.pairs_per_thread, self.blocks_per_cu, self.per_wave)
+        return (self.block, self.pairs_per_thread, self.blocks_per_cu, self.per_wave,
+                self.dynamic)
 
 
 _P = ctypes.c_void_p
@@ -362,7 +364,8 @@ class BatchPlan:
         t = None
         if tiling is not None:
             t = Tiling(int(tiling[0]), int(tiling[1]), int(tiling[2]),
-                       int(tiling[3]) if len(tiling) > 3 else 0)
+                       int(tiling[3]) if len(tiling) > 3 else 0,
+                       int(tiling[4]) if len(tiling) > 4 else 0)
         plan = ctypes.c_void_p()
         rc = lib.albedo_batch_plan_create(
             n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), _ptr(f0),
@@ -402,7 +405,8 @@ class BatchPlan:
 
 def albedo_batch_autotune(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_grad=True,
                           stream=None):
-    """Time candidate tilings on these jobs; returns ((block, ppt, bpc, per_wave), ms)."""
+    """Time candidate tilings on these jobs; returns
+    ((block, ppt, bpc, per_wave, dynamic), ms)."""
     lib = load_library()
     n = wox.numel()
     ns = torch.as_tensor(nsamples, dtype=torch.int64).cpu().contiguous()

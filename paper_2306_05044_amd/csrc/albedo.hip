@@ -262,87 +262,147 @@ __global__ __launch_bounds__(kLutBlock) void k_radiance(
 }
 
 // ---------------------------------------------------------------------------
-// Batched persistent kernel: block b walks its static range of chunks
-// [block_chunks[b], block_chunks[b+1]); each chunk is (job, pair range).
+// Batched persistent kernels.  Each chunk is (job, pair range) and owns one
+// slot of `partial`, so results do not depend on which block or wavefront
+// processes it.  Static scheduling: owner o walks its precomputed range
+// [owner_chunks[o], owner_chunks[o+1]) (balanced by sample count).  Dynamic
+// scheduling: owners take the next chunk index from a device counter (reset
+// to 0 before every launch) until it passes nchunks, so every owner exits.
 // ---------------------------------------------------------------------------
 template <int BLOCK, bool GRAD>
-__global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch(
-    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
-    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
-    const int64_t* __restrict__ nsamp, const int32_t* __restrict__ chunk_job,
-    const int64_t* __restrict__ chunk_pbeg, const int64_t* __restrict__ chunk_pend,
-    const int32_t* __restrict__ block_chunks, uint32_t k0, uint32_t k1,
+__device__ __forceinline__ void batch_chunk_block(
+    int32_t ch, const float* __restrict__ wox, const float* __restrict__ woy,
+    const float* __restrict__ woz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ f0p, const int64_t* __restrict__ nsamp,
+    const int32_t* __restrict__ chunk_job, const int64_t* __restrict__ chunk_pbeg,
+    const int64_t* __restrict__ chunk_pend, uint32_t k0, uint32_t k1,
     float* __restrict__ partial) {
-    const int32_t cb = block_chunks[blockIdx.x];
-    const int32_t ce = block_chunks[blockIdx.x + 1];
-    for (int32_t ch = cb; ch < ce; ++ch) {
-        const int32_t j = chunk_job[ch];
-        const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
-        const float f0 = f0p ? f0p[j] : 1.0f;
-        const uint64_t n = (uint64_t)nsamp[j];
-        const uint64_t pbeg = (uint64_t)chunk_pbeg[ch];
-        const uint64_t pend = (uint64_t)chunk_pend[ch];
-        if (GRAD) {
-            Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-            if (c.ok) pairs_adj<BLOCK>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out);
-            block_reduce_store<4, BLOCK>(out, partial + (int64_t)ch * 8);
-        } else {
-            Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-            if (c.ok) pairs_fwd<BLOCK>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc);
-            // A(F0) = F0 S1 + (1 - F0) S5, folded per chunk
-            const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
-            Comp w[1] = {Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f}};
-            block_reduce_store<1, BLOCK>(w, partial + (int64_t)ch * 2);
+    const int32_t j = chunk_job[ch];
+    const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
+    const float f0 = f0p ? f0p[j] : 1.0f;
+    const uint64_t n = (uint64_t)nsamp[j];
+    const uint64_t pbeg = (uint64_t)chunk_pbeg[ch];
+    const uint64_t pend = (uint64_t)chunk_pend[ch];
+    if (GRAD) {
+        Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+        if (c.ok) pairs_adj<BLOCK>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out);
+        block_reduce_store<4, BLOCK>(out, partial + (int64_t)ch * 8);
+    } else {
+        Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+        if (c.ok) pairs_fwd<BLOCK>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc);
+        // A(F0) = F0 S1 + (1 - F0) S5, folded per chunk
+        const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
+        Comp w[1] = {Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f}};
+        block_reduce_store<1, BLOCK>(w, partial + (int64_t)ch * 2);
+    }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ void batch_chunk_wave(
+    int32_t ch, uint32_t lane, const float* __restrict__ wox, const float* __restrict__ woy,
+    const float* __restrict__ woz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ f0p, const int64_t* __restrict__ nsamp,
+    const int32_t* __restrict__ chunk_job, const int64_t* __restrict__ chunk_pbeg,
+    const int64_t* __restrict__ chunk_pend, uint32_t k0, uint32_t k1,
+    float* __restrict__ partial) {
+    const int32_t j = chunk_job[ch];
+    const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
+    const float f0 = f0p ? f0p[j] : 1.0f;
+    const uint64_t n = (uint64_t)nsamp[j];
+    const uint64_t pbeg = (uint64_t)chunk_pbeg[ch];
+    const uint64_t pend = (uint64_t)chunk_pend[ch];
+    if (GRAD) {
+        Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+        if (c.ok) pairs_adj<64>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out, lane);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) out[a] = wave_reduce(out[a]);
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                partial[(int64_t)ch * 8 + 2 * a] = out[a].s;
+                partial[(int64_t)ch * 8 + 2 * a + 1] = out[a].c;
+            }
+        }
+    } else {
+        Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+        if (c.ok) pairs_fwd<64>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc, lane);
+        const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
+        Comp w = wave_reduce(Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f});
+        if (lane == 0) {
+            partial[(int64_t)ch * 2] = w.s;
+            partial[(int64_t)ch * 2 + 1] = w.c;
         }
     }
 }
 
-// Per-wave variant: every wavefront owns its static range of (smaller)
-// chunks [wave_chunks[w], wave_chunks[w+1]) and reduces each one with its own
-// butterfly, with no LDS and no barrier -- small jobs then occupy 64 lanes
-// instead of a whole block.
-template <int BLOCK, bool GRAD>
-__global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch_wave(
-    const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
-    const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
-    const int64_t* __restrict__ nsamp, const int32_t* __restrict__ chunk_job,
-    const int64_t* __restrict__ chunk_pbeg, const int64_t* __restrict__ chunk_pend,
-    const int32_t* __restrict__ wave_chunks, uint32_t k0, uint32_t k1,
-    float* __restrict__ partial) {
-    const uint32_t lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6);
-    const int32_t cb = wave_chunks[wave];
-    const int32_t ce = wave_chunks[wave + 1];
-    for (int32_t ch = cb; ch < ce; ++ch) {
-        const int32_t j = chunk_job[ch];
-        const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
-        const float f0 = f0p ? f0p[j] : 1.0f;
-        const uint64_t n = (uint64_t)nsamp[j];
-        const uint64_t pbeg = (uint64_t)chunk_pbeg[ch];
-        const uint64_t pend = (uint64_t)chunk_pend[ch];
-        if (GRAD) {
-            Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-            if (c.ok) pairs_adj<64>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out, lane);
-#pragma unroll
-            for (int a = 0; a < 4; ++a) out[a] = wave_reduce(out[a]);
-            if (lane == 0) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    partial[(int64_t)ch * 8 + 2 * a] = out[a].s;
-                    partial[(int64_t)ch * 8 + 2 * a + 1] = out[a].c;
-                }
-            }
-        } else {
-            Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-            if (c.ok) pairs_fwd<64>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc, lane);
-            const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
-            Comp w = wave_reduce(Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f});
-            if (lane == 0) {
-                partial[(int64_t)ch * 2] = w.s;
-                partial[(int64_t)ch * 2 + 1] = w.c;
-            }
+#define CAPVNDF_BATCH_PARAMS                                                                     \
+    const float *__restrict__ wox, const float *__restrict__ woy, const float *__restrict__ woz, \
+        const float *__restrict__ ax, const float *__restrict__ ay,                              \
+        const float *__restrict__ f0p, const int64_t *__restrict__ nsamp,                        \
+        const int32_t *__restrict__ chunk_job, const int64_t *__restrict__ chunk_pbeg,           \
+        const int64_t *__restrict__ chunk_pend, const int32_t *__restrict__ owner_chunks,        \
+        int32_t *__restrict__ counter, int32_t nchunks, uint32_t k0, uint32_t k1,              \
+        float *__restrict__ partial
+#define CAPVNDF_CHUNK_ARGS wox, woy, woz, ax, ay, f0p, nsamp, chunk_job, chunk_pbeg, chunk_pend, \
+                           k0, k1, partial
+
+// A block owns a chunk (block-wide reduction through LDS).
+template <int BLOCK, bool GRAD, bool DYN>
+__global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch(CAPVNDF_BATCH_PARAMS) {
+    // Loop control is made wave-uniform (readfirstlane) so that the compiler
+    // emits scalar loops: the chunk loop contains barriers and cross-lane
+    // reductions, which must not sit in a loop it treats as divergent.
+    if (!DYN) {
+        const int32_t cb = __builtin_amdgcn_readfirstlane(owner_chunks[blockIdx.x]);
+        const int32_t ce = __builtin_amdgcn_readfirstlane(owner_chunks[blockIdx.x + 1]);
+        for (int32_t ch = cb; ch < ce; ++ch) batch_chunk_block<BLOCK, GRAD>(ch, CAPVNDF_CHUNK_ARGS);
+    } else {
+        __shared__ int32_t next;
+        for (;;) {
+            if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+            __syncthreads();
+            const int32_t ch = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();  // all have read `next` before thread 0 takes another
+            if (ch >= nchunks) break;
+            batch_chunk_block<BLOCK, GRAD>(ch, CAPVNDF_CHUNK_ARGS);
         }
     }
+}
+
+// A wavefront owns a chunk (smaller chunks, wave-only reduction, no LDS or
+// barrier), so short jobs occupy 64 lanes instead of a whole block.
+template <int BLOCK, bool GRAD, bool DYN>
+__global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch_wave(CAPVNDF_BATCH_PARAMS) {
+    const uint32_t lane = threadIdx.x & 63;
+    if (!DYN) {
+        const int32_t wave =
+            __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * (BLOCK / 64) + (threadIdx.x >> 6)));
+        const int32_t cb = __builtin_amdgcn_readfirstlane(owner_chunks[wave]);
+        const int32_t ce = __builtin_amdgcn_readfirstlane(owner_chunks[wave + 1]);
+        for (int32_t ch = cb; ch < ce; ++ch) batch_chunk_wave<GRAD>(ch, lane, CAPVNDF_CHUNK_ARGS);
+    } else {
+        // Every lane takes part in the atomic (lane 0 adds 1, the others 0)
+        // and the ticket is read from lane 0 with readfirstlane, so the loop
+        // has no lane-0 branch and its exit is a scalar branch.  With the add
+        // under `if (lane == 0)` the compiler joined it to the lane-0 store
+        // that ends the previous chunk and split the loop in two: lane 0 went
+        // back to take a ticket while lanes 1-63 looped on with a zero ticket
+        // and never left.
+        for (;;) {
+            const int32_t mine = atomicAdd(counter, lane == 0 ? 1 : 0);
+            const int32_t ch = __builtin_amdgcn_readfirstlane(mine);
+            if (ch >= nchunks) break;
+            batch_chunk_wave<GRAD>(ch, lane, CAPVNDF_CHUNK_ARGS);
+        }
+    }
+}
+#undef CAPVNDF_CHUNK_ARGS
+#undef CAPVNDF_BATCH_PARAMS
+
+// Resets the dynamic scheduler's counter (a kernel, so that a captured graph
+// holds no memset node).
+__global__ void k_reset_counter(int32_t* counter) {
+    if (threadIdx.x == 0) counter[0] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -598,6 +658,7 @@ struct capvndf_batch_plan {
     int64_t* d_nsamp = nullptr;
     float* d_partial = nullptr;
     float* d_req_ws = nullptr;  // per-request baseline scratch
+    int32_t* d_counter = nullptr;  // dynamic scheduling
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -608,10 +669,11 @@ namespace {
 bool valid_tiling(const capvndf_tiling& t) {
     return (t.block == 256 || t.block == 512) && t.pairs_per_thread >= kGroup &&
            t.pairs_per_thread <= 4096 && t.pairs_per_thread % kGroup == 0 &&
-           t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && (t.per_wave == 0 || t.per_wave == 1);
+           t.blocks_per_cu >= 1 && t.blocks_per_cu <= 32 && (t.per_wave == 0 || t.per_wave == 1) &&
+           (t.dynamic == 0 || t.dynamic == 1);
 }
 
-capvndf_tiling default_tiling() { return capvndf_tiling{256, 32, 8, 0}; }
+capvndf_tiling default_tiling() { return capvndf_tiling{256, 32, 8, 0, 0}; }
 
 std::string problem_signature(int device, int64_t njobs, int64_t total, int with_grad) {
     hipDeviceProp_t prop;
@@ -630,18 +692,18 @@ std::string problem_signature(int device, int64_t njobs, int64_t total, int with
 }
 
 // Tuning cache: text lines
-// "<signature> <block> <pairs_per_thread> <blocks_per_cu> <per_wave> <ms>".
+// "<signature> <block> <pairs_per_thread> <blocks_per_cu> <per_wave> <dynamic> <ms>".
 bool cache_lookup(const std::string& sig, capvndf_tiling* out) {
     const char* path = getenv("CAPVNDF_TUNE_CACHE");
     if (!path || !*path) return false;
     FILE* f = fopen(path, "r");
     if (!f) return false;
     char key[256];
-    int b, p, c, w;
+    int b, p, c, w, dy;
     float ms;
     bool found = false;
-    while (fscanf(f, "%255s %d %d %d %d %f", key, &b, &p, &c, &w, &ms) == 6) {
-        capvndf_tiling t{b, p, c, w};
+    while (fscanf(f, "%255s %d %d %d %d %d %f", key, &b, &p, &c, &w, &dy, &ms) == 7) {
+        capvndf_tiling t{b, p, c, w, dy};
         if (sig == key && valid_tiling(t)) {
             *out = t;  // last matching line wins
             found = true;
@@ -656,8 +718,8 @@ void cache_store(const std::string& sig, const capvndf_tiling& t, float ms) {
     if (!path || !*path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d %.6f\n", sig.c_str(), t.block, t.pairs_per_thread, t.blocks_per_cu,
-            t.per_wave, ms);
+    fprintf(f, "%s %d %d %d %d %d %.6f\n", sig.c_str(), t.block, t.pairs_per_thread,
+            t.blocks_per_cu, t.per_wave, t.dynamic, ms);
     fclose(f);
 }
 
@@ -667,23 +729,36 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
     const int g = p->with_grad;
     const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
     const dim3 grid((unsigned)p->grid), block((unsigned)p->tiling.block);
-#define CAPVNDF_LAUNCH_BATCH(K, B, G)                                                               \
-    hipLaunchKernelGGL((K<B, G>), grid, block, 0, st, p->wox, p->woy, p->woz, p->ax, p->ay,       \
+    const bool dyn = p->tiling.dynamic != 0;
+    if (dyn) {
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, p->d_counter);
+        if (int32_t rc = check_launch("batch counter reset")) return rc;
+    }
+#define CAPVNDF_LAUNCH_BATCH(K, B, G, D)                                                            \
+    hipLaunchKernelGGL((K<B, G, D>), grid, block, 0, st, p->wox, p->woy, p->woz, p->ax, p->ay,    \
                        p->f0, p->d_nsamp, p->d_chunk_job, p->d_chunk_pbeg, p->d_chunk_pend,        \
-                       p->d_block_chunks, k0, k1, p->d_partial)
+                       p->d_block_chunks, p->d_counter, (int32_t)p->nchunks, k0, k1, p->d_partial)
+#define CAPVNDF_LAUNCH_BATCH_D(K, B, G)                                                             \
+    do {                                                                                            \
+        if (dyn) CAPVNDF_LAUNCH_BATCH(K, B, G, true);                                               \
+        else CAPVNDF_LAUNCH_BATCH(K, B, G, false);                                                  \
+    } while (0)
     if (p->tiling.per_wave) {
         if (p->tiling.block == 256) {
-            if (g) CAPVNDF_LAUNCH_BATCH(k_batch_wave, 256, true);
-            else CAPVNDF_LAUNCH_BATCH(k_batch_wave, 256, false);
+            if (g) CAPVNDF_LAUNCH_BATCH_D(k_batch_wave, 256, true);
+            else CAPVNDF_LAUNCH_BATCH_D(k_batch_wave, 256, false);
         } else {
-            if (g) CAPVNDF_LAUNCH_BATCH(k_batch_wave, 512, true);
-            else CAPVNDF_LAUNCH_BATCH(k_batch_wave, 512, false);
+            if (g) CAPVNDF_LAUNCH_BATCH_D(k_batch_wave, 512, true);
+            else CAPVNDF_LAUNCH_BATCH_D(k_batch_wave, 512, false);
         }
     } else if (p->tiling.block == 256) {
-        if (g) CAPVNDF_LAUNCH_BATCH(k_batch, 256, true); else CAPVNDF_LAUNCH_BATCH(k_batch, 256, false);
+        if (g) CAPVNDF_LAUNCH_BATCH_D(k_batch, 256, true);
+        else CAPVNDF_LAUNCH_BATCH_D(k_batch, 256, false);
     } else {
-        if (g) CAPVNDF_LAUNCH_BATCH(k_batch, 512, true); else CAPVNDF_LAUNCH_BATCH(k_batch, 512, false);
+        if (g) CAPVNDF_LAUNCH_BATCH_D(k_batch, 512, true);
+        else CAPVNDF_LAUNCH_BATCH_D(k_batch, 512, false);
     }
+#undef CAPVNDF_LAUNCH_BATCH_D
 #undef CAPVNDF_LAUNCH_BATCH
     if (int32_t rc = check_launch("batch kernel launch")) return rc;
     if (g)
@@ -744,7 +819,8 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
         if (!valid_tiling(*tiling))
             return fail(CAPVNDF_ERR_BAD_ARG,
                         "albedo_batch_plan_create: invalid tiling (block 256|512, pairs_per_thread "
-                        "a multiple of 8 in [8, 4096], blocks_per_cu in [1, 32], per_wave 0|1)");
+                        "a multiple of 8 in [8, 4096], blocks_per_cu in [1, 32], per_wave 0|1, "
+                        "dynamic 0|1)");
         t = *tiling;
     } else {
         (void)cache_lookup(problem_signature(device, njobs, total, with_grad), &t);
@@ -814,6 +890,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     const size_t o_ns = carve(sizeof(int64_t) * (size_t)njobs);
     const size_t o_pa = carve(sizeof(float) * 2 * nacc * (size_t)std::max<int64_t>(nchunks, 1));
     const size_t o_rw = carve(sizeof(float) * 8 * (size_t)max_cpc);
+    const size_t o_ct = carve(sizeof(int32_t));
     capvndf_batch_plan* p = new capvndf_batch_plan();
     if (int32_t rc = check_hip(hipMalloc(&p->dmem, off), "hipMalloc (batch plan)")) {
         p->dmem = nullptr;
@@ -829,6 +906,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     p->d_nsamp = reinterpret_cast<int64_t*>(base + o_ns);
     p->d_partial = reinterpret_cast<float*>(base + o_pa);
     p->d_req_ws = reinterpret_cast<float*>(base + o_rw);
+    p->d_counter = reinterpret_cast<int32_t*>(base + o_ct);
     int32_t rc = CAPVNDF_OK;
     if (nchunks > 0) {
         if (!rc) rc = check_hip(hipMemcpy(p->d_chunk_job, chunk_job.data(), sizeof(int32_t) * nchunks, hipMemcpyHostToDevice), "hipMemcpy");
@@ -969,35 +1047,33 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
     capvndf_tiling best_tiling = default_tiling();
     int64_t total = 0;
     for (int64_t j = 0; j < njobs && nsamples_host; ++j) total += nsamples_host[j];
-    for (int mode : modes) {
-    for (int b : blocks) {
-        for (int ppt : ppts) {
-            for (int bpc : bpcs) {
-                if (rc) break;
-                if (b == 512 && bpc > 8) continue;
-                if (mode == 0 && ppt > 64) continue;
-                capvndf_tiling t{b, ppt, bpc, mode};
-                capvndf_batch_plan* p = nullptr;
-                rc = create_plan(njobs, wox, woy, woz, ax, ay, f0, nsamples_host, seed, with_grad,
-                                 albedo, grad_ax, grad_ay, grad_theta_o, &t, &p);
-                if (rc) break;
-                rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");  // warm-up
-                const int reps = 3;
-                if (!rc) rc = check_hip(hipEventRecord(e0, st), "hipEventRecord");
-                for (int r = 0; r < reps && !rc; ++r)
-                    rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");
-                if (!rc) rc = check_hip(hipEventRecord(e1, st), "hipEventRecord");
-                if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
-                float ms = 0.0f;
-                if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                destroy_plan(p);
-                if (!rc && ms / reps < best_t) {
-                    best_t = ms / reps;
-                    best_tiling = t;
-                }
-            }
+    for (int dyn = 0; dyn < 2; ++dyn)
+    for (int mode : modes)
+    for (int b : blocks)
+    for (int ppt : ppts)
+    for (int bpc : bpcs) {
+        if (rc) break;
+        if (b == 512 && bpc > 8) continue;
+        if (mode == 0 && ppt > 64) continue;
+        capvndf_tiling t{b, ppt, bpc, mode, dyn};
+        capvndf_batch_plan* p = nullptr;
+        rc = create_plan(njobs, wox, woy, woz, ax, ay, f0, nsamples_host, seed, with_grad, albedo,
+                         grad_ax, grad_ay, grad_theta_o, &t, &p);
+        if (rc) break;
+        rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");  // warm-up
+        const int reps = 3;
+        if (!rc) rc = check_hip(hipEventRecord(e0, st), "hipEventRecord");
+        for (int r = 0; r < reps && !rc; ++r)
+            rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");
+        if (!rc) rc = check_hip(hipEventRecord(e1, st), "hipEventRecord");
+        if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        destroy_plan(p);
+        if (!rc && ms / reps < best_t) {
+            best_t = ms / reps;
+            best_tiling = t;
         }
-    }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

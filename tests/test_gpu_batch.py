@@ -41,7 +41,9 @@ def _check(plan, j, f0, with_grad):
 
 
 @pytest.mark.parametrize("tiling", [None, (256, 8, 2), (512, 16, 4), (256, 64, 16),
-                                    (256, 8, 4, 1), (512, 128, 8, 1), (256, 32, 16, 1)])
+                                    (256, 8, 4, 1), (512, 128, 8, 1), (256, 32, 16, 1),
+                                    (256, 8, 2, 0, 1), (512, 64, 8, 0, 1), (256, 16, 16, 1, 1),
+                                    (512, 8, 1, 1, 1)])
 def test_batch_matches_oracle(tiling):
     j = _jobs(97, seed=5)
     t = to_dev({k: v for k, v in j.items() if k != "n"})
@@ -56,7 +58,7 @@ def test_batch_matches_oracle(tiling):
     plan.close()
 
 
-@pytest.mark.parametrize("tiling", [None, (256, 16, 4, 1)])
+@pytest.mark.parametrize("tiling", [None, (256, 16, 4, 1), (256, 32, 8, 0, 1), (256, 8, 8, 1, 1)])
 def test_batch_forward_only(tiling):
     j = _jobs(50, seed=6)
     t = to_dev({k: v for k, v in j.items() if k != "n"})
@@ -90,6 +92,31 @@ def test_replays_and_per_request_baseline():
         assert torch.allclose(a, b, rtol=1e-5, atol=2e-6)
 
 
+@pytest.mark.parametrize("tiling", [(256, 16, 8, 0, 1), (256, 8, 8, 1, 1)])
+def test_dynamic_replays_are_bitwise_stable(tiling):
+    """Dynamic chunk assignment changes which owner runs a chunk from replay to
+    replay but not its result slot: every replay gives the same bits, equal to
+    the static assignment's."""
+    j = _jobs(80, seed=13, lo=6, hi=16)
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    static = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True,
+                          tiling=tiling[:4] + (0,))
+    static.run()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in (static.albedo, static.grad_ax, static.grad_ay, static.grad_theta_o)]
+    static.close()
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True,
+                        tiling=tiling)
+    for r in range(5):
+        for o in (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o):
+            o.fill_(float("nan"))
+        plan.run()
+        torch.cuda.synchronize()
+        for a, b in zip(ref, (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o)):
+            assert torch.equal(a, b), f"replay {r}"
+    plan.close()
+
+
 def test_full_batch_sampled():
     """4096 uneven jobs (2^10 .. 2^22 samples); 24 jobs checked by the oracle."""
     j = workloads.batch_jobs(4096, seed=4)
@@ -117,8 +144,9 @@ def test_autotune_small(tmp_path, monkeypatch):
     t = to_dev({k: v for k, v in j.items() if k != "n"})
     best, ms = cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
     assert best[0] in (256, 512) and best[1] % 8 == 0 and best[3] in (0, 1) and ms > 0
+    assert best[4] in (0, 1)
     text = (tmp_path / "tune.txt").read_text().split()
-    assert [int(x) for x in text[1:5]] == list(best)
+    assert [int(x) for x in text[1:6]] == list(best)
     plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
     assert plan.info()["tiling"] == best   # picked up from the cache
     plan.run()
@@ -126,7 +154,7 @@ def test_autotune_small(tmp_path, monkeypatch):
     _check(plan, j, 1.0, True)
 
 
-@pytest.mark.parametrize("tiling", [None, (256, 8, 4, 1)])
+@pytest.mark.parametrize("tiling", [None, (256, 8, 4, 1), (512, 32, 8, 0, 1)])
 @pytest.mark.parametrize("n_samples", [1, 2, 1 << 20])
 def test_single_job(n_samples, tiling):
     """A batch of one job: one sample, one pair, and a job large enough to be
