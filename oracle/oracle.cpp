@@ -29,7 +29,7 @@
 //     VNDF, after Walter et al. 2007, whom the paper cites for it: Fresnel
 //     equations, Snell's law, generalised half vector and its Jacobian.
 //
-// Readings where the paper is silent (each also listed in the design doc):
+// Readings where the paper is silent:
 //   * u1 drives the azimuth and u2 the height, exactly as the cap listing.
 //   * Random numbers: u = (w >> 8) * 2^-24 from Philox words; counter
 //     (lo32(k>>1), unit, tag, hi32(k>>1)), key (lo32(seed), hi32(seed));
