@@ -17,6 +17,11 @@
  *    Calls only enqueue work: they return before the GPU has finished and
  *    never synchronise.  Enqueued work reads inputs and writes outputs
  *    asynchronously, so buffers must stay alive until the stream reaches it.
+ *  - Element-wise calls take any n >= 0 that fits in memory: a call longer
+ *    than 2^31 elements is enqueued as consecutive launches of 2^31 elements
+ *    (results identical to one launch; a HIP error in a later launch leaves
+ *    the earlier ones enqueued).  The estimators accept up to 2^24 chunks of
+ *    16384 samples (about 2.7e11 samples) per call.
  *  - The library never allocates on these calls, except the batch-plan calls
  *    (which own their chunk tables, partial buffers and graph).
  *  - Return value: CAPVNDF_OK (0) or a negative CAPVNDF_ERR_* code.  All

@@ -458,8 +458,14 @@ int32_t check_cells(const char* fn, int64_t ncells, int64_t nsamples, const floa
     if (ncells < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells < 0", fn);
     if (nsamples < 0 || nsamples >= ((int64_t)1 << 40))
         return fail(CAPVNDF_ERR_BAD_SIZE, "%s: nsamples must be in [0, 2^40)", fn);
-    if (ncells > 0 && (double)ncells * (double)lut_chunks_per_cell(nsamples) > 2147483647.0)
-        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells * chunks per cell exceeds the grid limit", fn);
+    // one block of kLutBlock work-items per chunk; a dispatch counts its
+    // work-items in 32 bits
+    if (ncells > 0 && (double)ncells * (double)lut_chunks_per_cell(nsamples) * kLutBlock >
+                          4294967295.0)
+        return fail(CAPVNDF_ERR_BAD_SIZE,
+                    "%s: ncells * chunks per cell (%lld * %lld) exceeds 2^24 chunks of %llu "
+                    "samples; split the cells over several calls", fn, (long long)ncells,
+                    (long long)lut_chunks_per_cell(nsamples), (unsigned long long)(2 * kLutChunkPairs));
     if (ncells > ((int64_t)1 << 32))
         return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells exceeds the 32-bit stream unit", fn);
     const void* req[] = {wox, woy, woz, ax, ay};

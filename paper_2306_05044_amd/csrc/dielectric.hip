@@ -321,26 +321,34 @@ extern "C" int32_t dielectric_sample(int64_t n, const float* wix, const float* w
     }
     const hipStream_t st = as_stream(stream);
     const uint32_t k0 = key_lo(seed), k1 = key_hi(seed);
-    if (vec) {
-        const dim3 grid(tiles_for<kSampleGroups, kSampleBlock>(n)), block(kSampleBlock);
-        if (eu)
-            hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock, true>), grid, block, 0,
-                               st, n, wix, wiy, wiz, ax, ay, u1, u2, u3, e, index_base, k0, k1,
-                               wox, woy, woz, pdf, weight);
-        else
-            hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock, false>), grid, block,
-                               0, st, n, wix, wiy, wiz, ax, ay, u1, u2, u3, e, index_base, k0, k1,
-                               wox, woy, woz, pdf, weight);
-    } else {
-        const dim3 grid(grid_for(n)), block(kBlock);
-        if (eu)
-            hipLaunchKernelGGL(k_dielectric_scalar<true>, grid, block, 0, st, n, wix, wiy, wiz, ax,
-                               ay, u1, u2, u3, e, index_base, k0, k1, wox, woy, woz, pdf, weight);
-        else
-            hipLaunchKernelGGL(k_dielectric_scalar<false>, grid, block, 0, st, n, wix, wiy, wiz, ax,
-                               ay, u1, u2, u3, e, index_base, k0, k1, wox, woy, woz, pdf, weight);
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        const uint64_t ib = index_base + (uint64_t)o;
+        const float *xi = wix + o, *yi = wiy + o, *zi = wiz + o, *axo = ax + o, *ayo = ay + o;
+        const float *v1 = at(u1, o), *v2 = at(u2, o), *v3 = at(u3, o);
+        float *xo = wox + o, *yo = woy + o, *zo = woz + o, *po = pdf + o, *wt = weight + o;
+        if (vec) {
+            const dim3 grid(tiles_for<kSampleGroups, kSampleBlock>(m)), block(kSampleBlock);
+            if (eu)
+                hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock, true>), grid,
+                                   block, 0, st, m, xi, yi, zi, axo, ayo, v1, v2, v3, e, ib, k0,
+                                   k1, xo, yo, zo, po, wt);
+            else
+                hipLaunchKernelGGL((k_dielectric_v4<kSampleGroups, kSampleBlock, false>), grid,
+                                   block, 0, st, m, xi, yi, zi, axo, ayo, v1, v2, v3, e, ib, k0,
+                                   k1, xo, yo, zo, po, wt);
+        } else {
+            const dim3 grid(grid_for(m)), block(kBlock);
+            if (eu)
+                hipLaunchKernelGGL(k_dielectric_scalar<true>, grid, block, 0, st, m, xi, yi, zi,
+                                   axo, ayo, v1, v2, v3, e, ib, k0, k1, xo, yo, zo, po, wt);
+            else
+                hipLaunchKernelGGL(k_dielectric_scalar<false>, grid, block, 0, st, m, xi, yi, zi,
+                                   axo, ayo, v1, v2, v3, e, ib, k0, k1, xo, yo, zo, po, wt);
+        }
+        if (int32_t rc = check_launch("dielectric_sample launch")) return rc;
     }
-    return check_launch("dielectric_sample launch");
+    return CAPVNDF_OK;
 }
 
 extern "C" int32_t dielectric_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz,
@@ -359,12 +367,17 @@ extern "C" int32_t dielectric_pdf(int64_t n, const float* wix, const float* wiy,
         if (!aligned_to(req[i], 16)) vec = false;
     }
     const hipStream_t st = as_stream(stream);
-    if (vec)
-        hipLaunchKernelGGL(k_dielectric_pdf_v4<kPdfGroups>, dim3(tiles_for<kPdfGroups>(n)),
-                           dim3(kBlock), 0, st, n, wix,
-                           wiy, wiz, wox, woy, woz, ax, ay, e, pdf);
-    else
-        hipLaunchKernelGGL(k_dielectric_pdf_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n,
-                           wix, wiy, wiz, wox, woy, woz, ax, ay, e, pdf);
-    return check_launch("dielectric_pdf launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        if (vec)
+            hipLaunchKernelGGL(k_dielectric_pdf_v4<kPdfGroups>, dim3(tiles_for<kPdfGroups>(m)),
+                               dim3(kBlock), 0, st, m, wix + o, wiy + o, wiz + o, wox + o, woy + o,
+                               woz + o, ax + o, ay + o, e, pdf + o);
+        else
+            hipLaunchKernelGGL(k_dielectric_pdf_scalar, dim3(grid_for(m)), dim3(kBlock), 0, st, m,
+                               wix + o, wiy + o, wiz + o, wox + o, woy + o, woz + o, ax + o,
+                               ay + o, e, pdf + o);
+        if (int32_t rc = check_launch("dielectric_pdf launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }

@@ -480,14 +480,22 @@ extern "C" int32_t vndf_sample(int64_t n, const float* wix, const float* wiy, co
         if (p != nullptr && !aligned_to(p, 16)) vec = false;
     const bool eu = u1 != nullptr, wp = pdf != nullptr;
     const hipStream_t st = as_stream(stream);
-    if (method == CAPVNDF_CAP)
-        dispatch_sample<CAPVNDF_CAP>(vec, eu, wp, n, wix, wiy, wiz, ax, ay, u1, u2, index_base,
-                                     key_lo(seed), key_hi(seed), hx, hy, hz, pdf, st);
-    else
-        dispatch_sample<CAPVNDF_DISK2018>(vec, eu, wp, n, wix, wiy, wiz, ax, ay, u1, u2,
-                                          index_base, key_lo(seed), key_hi(seed), hx, hy, hz,
-                                          pdf, st);
-    return check_launch("vndf_sample launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        const uint64_t ib = index_base + (uint64_t)o;
+        if (method == CAPVNDF_CAP)
+            dispatch_sample<CAPVNDF_CAP>(vec, eu, wp, m, at(wix, o), at(wiy, o), at(wiz, o),
+                                         at(ax, o), at(ay, o), at(u1, o), at(u2, o), ib,
+                                         key_lo(seed), key_hi(seed), at(hx, o), at(hy, o),
+                                         at(hz, o), at(pdf, o), st);
+        else
+            dispatch_sample<CAPVNDF_DISK2018>(vec, eu, wp, m, at(wix, o), at(wiy, o), at(wiz, o),
+                                              at(ax, o), at(ay, o), at(u1, o), at(u2, o), ib,
+                                              key_lo(seed), key_hi(seed), at(hx, o), at(hy, o),
+                                              at(hz, o), at(pdf, o), st);
+        if (int32_t rc = check_launch("vndf_sample launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }
 
 extern "C" int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz,
@@ -503,14 +511,18 @@ extern "C" int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const
         if (!aligned_to(req[i], 16)) vec = false;
     }
     const hipStream_t st = as_stream(stream);
-    if (vec)
-        hipLaunchKernelGGL((k_pdf_v4<kPdfGroups, kPdfCached>), dim3(tiles_for<kPdfGroups>(n)),
-                           dim3(kBlock), 0, st, n, wix,
-                           wiy, wiz, hx, hy, hz, ax, ay, pdf);
-    else
-        hipLaunchKernelGGL(k_pdf_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix, wiy,
-                           wiz, hx, hy, hz, ax, ay, pdf);
-    return check_launch("vndf_pdf launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        if (vec)
+            hipLaunchKernelGGL((k_pdf_v4<kPdfGroups, kPdfCached>), dim3(tiles_for<kPdfGroups>(m)),
+                               dim3(kBlock), 0, st, m, wix + o, wiy + o, wiz + o, hx + o, hy + o,
+                               hz + o, ax + o, ay + o, pdf + o);
+        else
+            hipLaunchKernelGGL(k_pdf_scalar, dim3(grid_for(m)), dim3(kBlock), 0, st, m, wix + o,
+                               wiy + o, wiz + o, hx + o, hy + o, hz + o, ax + o, ay + o, pdf + o);
+        if (int32_t rc = check_launch("vndf_pdf launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }
 
 extern "C" int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float* wiz,
@@ -526,14 +538,20 @@ extern "C" int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, c
         if (!aligned_to(req[i], 16)) vec = false;
     }
     const hipStream_t st = as_stream(stream);
-    if (vec)
-        hipLaunchKernelGGL((k_inverse_v4<kInverseGroups, kInverseCached>),
-                           dim3(tiles_for<kInverseGroups>(n)), dim3(kBlock), 0, st, n, wix, wiy, wiz,
-                           hx, hy, hz, ax, ay, u1, u2);
-    else
-        hipLaunchKernelGGL(k_inverse_scalar, dim3(grid_for(n)), dim3(kBlock), 0, st, n, wix, wiy,
-                           wiz, hx, hy, hz, ax, ay, u1, u2);
-    return check_launch("vndf_inverse launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        if (vec)
+            hipLaunchKernelGGL((k_inverse_v4<kInverseGroups, kInverseCached>),
+                               dim3(tiles_for<kInverseGroups>(m)), dim3(kBlock), 0, st, m, wix + o,
+                               wiy + o, wiz + o, hx + o, hy + o, hz + o, ax + o, ay + o, u1 + o,
+                               u2 + o);
+        else
+            hipLaunchKernelGGL(k_inverse_scalar, dim3(grid_for(m)), dim3(kBlock), 0, st, m,
+                               wix + o, wiy + o, wiz + o, hx + o, hy + o, hz + o, ax + o, ay + o,
+                               u1 + o, u2 + o);
+        if (int32_t rc = check_launch("vndf_inverse launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }
 
 extern "C" int32_t capvndf_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, uint64_t k0,
@@ -542,9 +560,13 @@ extern "C" int32_t capvndf_uniforms(uint64_t seed, uint32_t tag, uint32_t unit, 
     if (n == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(u1, "u1")) return rc;
     if (int32_t rc = check_array(u2, "u2")) return rc;
-    hipLaunchKernelGGL(k_uniforms, dim3(grid_for(n)), dim3(kBlock), 0, as_stream(stream), n, k0,
-                       tag, unit, key_lo(seed), key_hi(seed), u1, u2);
-    return check_launch("capvndf_uniforms launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        hipLaunchKernelGGL(k_uniforms, dim3(grid_for(m)), dim3(kBlock), 0, as_stream(stream), m,
+                           k0 + (uint64_t)o, tag, unit, key_lo(seed), key_hi(seed), u1 + o, u2 + o);
+        if (int32_t rc = check_launch("capvndf_uniforms launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }
 
 extern "C" int32_t capvndf_philox_blocks(int64_t n, const uint32_t* ctr, uint32_t key0,
@@ -553,14 +575,19 @@ extern "C" int32_t capvndf_philox_blocks(int64_t n, const uint32_t* ctr, uint32_
     if (n == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(ctr, "ctr")) return rc;
     if (int32_t rc = check_array(out, "out")) return rc;
-    hipLaunchKernelGGL(k_philox_blocks, dim3(grid_for(n)), dim3(kBlock), 0, as_stream(stream), n,
-                       ctr, key0, key1, out);
-    return check_launch("capvndf_philox_blocks launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        hipLaunchKernelGGL(k_philox_blocks, dim3(grid_for(m)), dim3(kBlock), 0, as_stream(stream),
+                           m, ctr + 4 * o, key0, key1, out + 4 * o);
+        if (int32_t rc = check_launch("capvndf_philox_blocks launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }
 
 extern "C" int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters, uint64_t seed,
                                    uint32_t* out, void* stream) {
-    if (lanes < 0 || iters < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_microbench: bad size");
+    if (lanes < 0 || lanes > kSliceElems || iters < 0)
+        return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_microbench: lanes must be in [0, 2^31], iters >= 0");
     if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018)
         return fail(CAPVNDF_ERR_BAD_METHOD, "vndf_microbench: unknown method %d", method);
     if (lanes == 0) return CAPVNDF_OK;
@@ -589,16 +616,20 @@ extern "C" int32_t capvndf_stream_probe(int32_t mode, int64_t n, const float* in
         if (!aligned_to(p, 16))
             return fail(CAPVNDF_ERR_MISALIGNED, "capvndf_stream_probe: arrays must be 16-byte aligned");
     }
-    const dim3 grid(tiles_for(n)), block(kBlock);
     const hipStream_t st = as_stream(stream);
-    if (mode == 0)
-        hipLaunchKernelGGL(k_stream_probe<0>, grid, block, 0, st, n, in0, in1, in2, in3, in4, out0,
-                           out1, out2, out3);
-    else if (mode == 1)
-        hipLaunchKernelGGL(k_stream_probe<1>, grid, block, 0, st, n, in0, in1, in2, in3, in4, out0,
-                           out1, out2, out3);
-    else
-        hipLaunchKernelGGL(k_stream_probe<2>, grid, block, 0, st, n, in0, in1, in2, in3, in4, out0,
-                           out1, out2, out3);
-    return check_launch("capvndf_stream_probe launch");
+    for (int64_t o = 0; o < n; o += kSliceElems) {
+        const int64_t m = slice_len(n, o);
+        const dim3 grid(tiles_for(m)), block(kBlock);
+        if (mode == 0)
+            hipLaunchKernelGGL(k_stream_probe<0>, grid, block, 0, st, m, in0 + o, in1 + o, in2 + o,
+                               in3 + o, in4 + o, out0 + o, out1 + o, out2 + o, out3 + o);
+        else if (mode == 1)
+            hipLaunchKernelGGL(k_stream_probe<1>, grid, block, 0, st, m, in0 + o, in1 + o, in2 + o,
+                               in3 + o, in4 + o, out0 + o, out1 + o, out2 + o, out3 + o);
+        else
+            hipLaunchKernelGGL(k_stream_probe<2>, grid, block, 0, st, m, in0 + o, in1 + o, in2 + o,
+                               in3 + o, in4 + o, out0 + o, out1 + o, out2 + o, out3 + o);
+        if (int32_t rc = check_launch("capvndf_stream_probe launch")) return rc;
+    }
+    return CAPVNDF_OK;
 }

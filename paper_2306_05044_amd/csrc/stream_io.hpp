@@ -88,4 +88,16 @@ inline unsigned tiles_for(int64_t n) {
     return (unsigned)((n + tile - 1) / tile);
 }
 
+// Elements per dispatch.  A dispatch's work-item count is a 32-bit number and
+// the scalar paths run one element per work-item, so the element-wise entry
+// points launch longer calls as consecutive slices of at most this many
+// elements.  Pointers and stream positions advance by whole slices, which keeps
+// each slice's 16-byte alignment and the parity of its first counter.
+constexpr int64_t kSliceElems = (int64_t)1 << 31;
+inline int64_t slice_len(int64_t n, int64_t off) {
+    return n - off < kSliceElems ? n - off : kSliceElems;
+}
+template <class T>
+inline T* at(T* p, int64_t off) { return p == nullptr ? p : p + off; }
+
 }  // namespace capvndf

@@ -78,3 +78,50 @@ def check_conditioned(err, kap, c, name, strict_well=True):
     print(f"{name}: max err {err.max():.3e}, max err/(eps kappa) {ratio.max():.2f}, "
           f"fraction > 2e-6 {(err > 2e-6).mean():.2e}, max kappa {kap.max():.3e}")
     return float((err > 2e-6).mean())
+
+
+# A call of more than 2^31 elements (the element-wise entry points split it
+# into launches of 2^31) with a ragged tail.
+N_LARGE = (1 << 31) + 3 * (1 << 20) + 5
+
+
+def large_device_tuples(n, seed, pad=4):
+    """The streaming workload's distribution (cos theta uniform in [1e-3, 1],
+    azimuth uniform, alpha_x, alpha_y = 10^(-3U)) drawn directly on the GPU
+    from a seeded torch generator, for sizes whose host copies would not fit;
+    arrays hold n + pad elements so that offset views stay in bounds."""
+    import math
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    t = {k: torch.empty(n + pad, device="cuda") for k in ("wx", "wy", "wz", "ax", "ay")}
+    step = 1 << 27
+    for o in range(0, n + pad, step):
+        m = min(step, n + pad - o)
+
+        def r():
+            return torch.rand(m, generator=g, device="cuda", dtype=torch.float64)
+        mu = 1e-3 + (1.0 - 1e-3) * (1.0 - r())
+        phi = 2.0 * math.pi * r()
+        s = torch.sqrt(1.0 - mu * mu)
+        t["wx"][o:o + m] = (s * torch.cos(phi)).float()
+        t["wy"][o:o + m] = (s * torch.sin(phi)).float()
+        t["wz"][o:o + m] = mu.float()
+        t["ax"][o:o + m] = torch.pow(10.0, -3.0 * r()).float()
+        t["ay"][o:o + m] = torch.pow(10.0, -3.0 * r()).float()
+    return t
+
+
+def large_sample_indices(n, count, seed):
+    """Sorted positions: the first elements, both sides of every 2^31 slice
+    boundary, the ragged tail, and `count` random ones."""
+    rng = np.random.default_rng(seed)
+    fixed = [np.arange(0, 40)]
+    for b in range(1 << 31, n, 1 << 31):
+        fixed.append(np.arange(b - 40, b + 40))
+    fixed.append(np.arange(n - 40, n))
+    idx = np.concatenate(fixed + [rng.choice(n, count, replace=False)])
+    return np.unique(idx)
+
+
+def has_device_memory(gib):
+    return torch.cuda.get_device_properties(0).total_memory >= gib * 2 ** 30

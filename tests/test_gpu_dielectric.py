@@ -27,7 +27,8 @@ import torch
 
 import oracle
 import workloads
-from _gpu import EPS32, host, kappa, to_dev
+from _gpu import (EPS32, N_LARGE, has_device_memory, host, kappa, large_device_tuples,
+                  large_sample_indices, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -197,10 +198,37 @@ def test_domain_edges_and_total_reflection():
     assert np.all(np.isfinite(O)) and np.all(np.isfinite(host(pdf)))
 
 
+def _check_pdf_entry(W, O, ax, ay, eta, got, name):
+    """dielectric_pdf output `got` at FP32 directions W (wi) and O (wo) vs the
+    oracle at the same values.  Conditioning: the half vector t = wi + wo or
+    -(wi + eta wo) loses 2^-24 / |t| relatively, and wi.h, which sets F,
+    cancels near grazing."""
+    ref, _ = oracle.dielectric_eval(W, O, ax, ay, eta)
+    Wm, Om = np.stack(W, 1), np.stack(O, 1)
+    refl = Om[:, 2] > 0
+    tv = np.where(refl[:, None], Wm + Om, -(Wm + eta * Om))
+    tn = np.linalg.norm(tv, axis=1)
+    hh = tv * (np.sign(tv[:, 2]) / tn)[:, None]
+    ci = np.einsum("ij,ij->i", Wm, hh)
+    co = np.abs(np.einsum("ij,ij->i", Om, hh))
+    g = np.sqrt(np.maximum(eta * eta - 1 + ci * ci, 0.0))
+    fp = np.abs(_fresnel_slope(np.clip(ci, 0, 1), eta))
+    f = oracle.fresnel_dielectric(np.clip(ci, 0, 1), eta)
+    sel = np.where(refl, f, 1 - f)
+    K = (4.0 / tn + 2.0 / np.maximum(ci, 1e-30) + 2.0 / np.maximum(co, 1e-30)
+         + fp / np.maximum(sel, 1e-30) / np.maximum(ci, 1e-30)
+         + np.where(refl, 0.0, ci / np.maximum(g * g, 1e-30)))
+    both = (ref > 0) & (got > 0)
+    # a zero on exactly one side only where the validity tests are within rounding
+    one = (ref > 0) != (got > 0)
+    assert np.all(K[one] > 1e4) or not one.any(), one.sum()
+    rel = np.zeros(len(got))
+    rel[both] = np.abs(got[both] / ref[both] - 1)
+    _check(rel, K, 128, name, both)
+
+
 def test_pdf_entry_point():
-    """dielectric_pdf at FP32 directions vs the oracle at the same values.
-    Conditioning: the half vector t = wi + wo or -(wi + eta wo) loses
-    2^-24 / |t| relatively, and wi.h, which sets F, cancels near grazing."""
+    """dielectric_pdf at FP32 directions vs the oracle at the same values."""
     n = 65536 + 3
     d = workloads.tuples_streaming(n, seed=8)
     t = to_dev(d)
@@ -210,29 +238,8 @@ def test_pdf_entry_point():
         p = cv.dielectric_pdf(t["wx"], t["wy"], t["wz"], wox, woy, woz, t["ax"], t["ay"], eta)
         O = [host(x).astype(np.float64) for x in (wox, woy, woz)]
         W = [d[k].astype(np.float64) for k in ("wx", "wy", "wz")]
-        ref, _ = oracle.dielectric_eval(W, O, d["ax"], d["ay"], eta)
-        got = host(p).astype(np.float64)
-        Wm, Om = np.stack(W, 1), np.stack(O, 1)
-        refl = Om[:, 2] > 0
-        tv = np.where(refl[:, None], Wm + Om, -(Wm + eta * Om))
-        tn = np.linalg.norm(tv, axis=1)
-        hh = tv * (np.sign(tv[:, 2]) / tn)[:, None]
-        ci = np.einsum("ij,ij->i", Wm, hh)
-        co = np.abs(np.einsum("ij,ij->i", Om, hh))
-        g = np.sqrt(np.maximum(eta * eta - 1 + ci * ci, 0.0))
-        fp = np.abs(_fresnel_slope(np.clip(ci, 0, 1), eta))
-        f = oracle.fresnel_dielectric(np.clip(ci, 0, 1), eta)
-        sel = np.where(refl, f, 1 - f)
-        K = (4.0 / tn + 2.0 / np.maximum(ci, 1e-30) + 2.0 / np.maximum(co, 1e-30)
-             + fp / np.maximum(sel, 1e-30) / np.maximum(ci, 1e-30)
-             + np.where(refl, 0.0, ci / np.maximum(g * g, 1e-30)))
-        both = (ref > 0) & (got > 0)
-        # a zero on exactly one side only where the validity tests are within rounding
-        one = (ref > 0) != (got > 0)
-        assert np.all(K[one] > 1e4) or not one.any(), one.sum()
-        rel = np.zeros(n)
-        rel[both] = np.abs(got[both] / ref[both] - 1)
-        _check(rel, K, 128, f"pdf entry eta {eta:.4f}", both)
+        _check_pdf_entry(W, O, d["ax"], d["ay"], eta, host(p).astype(np.float64),
+                         f"pdf entry eta {eta:.4f}")
 
 
 def test_explicit_uniforms_match_the_stream():
@@ -287,3 +294,39 @@ def test_streaming_full_size_sampled():
     got = [x[ti] for x in outs]
     sub = {k: v[idx] for k, v in d.items()}
     _compare(sub, got, 1.5, _stream_u(1, 0, indices=idx), "2^26 sampled")
+
+
+def test_more_than_one_launch_sampled():
+    """n = 2^31 + 3 * 2^20 + 5 tuples resident in HBM (eta = 1.5): the sampler
+    (vector and scalar paths) and the pdf entry point run as two launches;
+    outputs at the start, on both sides of the 2^31 boundary, at the ragged
+    tail and at 2048 random positions against the oracle at the same stream
+    positions."""
+    if not has_device_memory(160):
+        pytest.skip("needs about 90 GB of device memory")
+    n = N_LARGE
+    idx = large_sample_indices(n, 2048, seed=4)
+    it = torch.from_numpy(idx).cuda()
+    t = large_device_tuples(n, seed=22)
+    u = _stream_u(12, 0, indices=idx)
+    try:
+        for off in (0, 1):  # aligned arrays (vector path), then offset views (scalar path)
+            v = {k: x[off:off + n] for k, x in t.items()}
+            outs = cv.dielectric_sample(v["wx"], v["wy"], v["wz"], v["ax"], v["ay"], 1.5, seed=12)
+            torch.cuda.synchronize()
+            sub = {k: host(x[it]) for k, x in v.items()}
+            _compare(sub, [x[it] for x in outs], 1.5, u, f"2^31+ offset {off}")
+            if off == 0:
+                wox, woy, woz = outs[:3]
+                q = cv.dielectric_pdf(v["wx"], v["wy"], v["wz"], wox, woy, woz, v["ax"], v["ay"],
+                                      1.5)
+                torch.cuda.synchronize()
+                O = [host(x[it]).astype(np.float64) for x in (wox, woy, woz)]
+                W = [sub[k].astype(np.float64) for k in ("wx", "wy", "wz")]
+                _check_pdf_entry(W, O, sub["ax"], sub["ay"], 1.5, host(q[it]).astype(np.float64),
+                                 "pdf entry 2^31+")
+                del wox, woy, woz, q
+            del outs, v
+    finally:
+        del t
+        torch.cuda.empty_cache()

@@ -9,7 +9,8 @@ import torch
 
 import oracle
 import workloads
-from _gpu import check_conditioned, host, kappa, kappa_disk_pdf, to_dev
+from _gpu import (N_LARGE, check_conditioned, has_device_memory, host, kappa, kappa_disk_pdf,
+                  large_device_tuples, large_sample_indices, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -405,3 +406,56 @@ def test_roughness_far_outside_the_workloads(method):
                           strict_well=False)
         check_conditioned(np.abs(P / p_ref - 1.0), kap, 128, "extreme roughness pdf",
                           strict_well=False)
+
+
+def test_more_than_one_launch_sampled():
+    """n = 2^31 + 3 * 2^20 + 5 tuples resident in HBM: the sampler (vector and
+    scalar paths), vndf_pdf, the inverse map and the uniform stream each run as
+    two launches; outputs at the start, on both sides of the 2^31 boundary, at
+    the ragged tail and at 2048 random positions against the oracle at the same
+    stream positions."""
+    if not has_device_memory(160):
+        pytest.skip("needs about 120 GB of device memory")
+    n = N_LARGE
+    idx = large_sample_indices(n, 2048, seed=3)
+    it = torch.from_numpy(idx).cuda()
+    t = large_device_tuples(n, seed=21)
+    try:
+        u1 = np.empty(len(idx))
+        u2 = np.empty(len(idx))
+        for j, k in enumerate(idx):
+            a, b = oracle.uniforms(11, 2, 0, int(k), 1)
+            u1[j], u2[j] = a[0], b[0]
+        for off in (0, 1):  # aligned arrays (vector path), then offset views (scalar path)
+            v = {k: x[off:off + n] for k, x in t.items()}
+            hx, hy, hz, pdf = cv.vndf_sample(v["wx"], v["wy"], v["wz"], v["ax"], v["ay"], seed=11)
+            torch.cuda.synchronize()
+            sub = {k: host(x[it]) for k, x in v.items()}
+            h_ref, p_ref = oracle.vndf_sample((sub["wx"], sub["wy"], sub["wz"]), sub["ax"],
+                                              sub["ay"], u1=u1, u2=u2)
+            _compare(sub, hx[it], hy[it], hz[it], pdf[it], h_ref, p_ref, f"2^31+ offset {off}")
+            assert torch.all(torch.isfinite(pdf)) and torch.all(pdf > 0)
+            if off == 0:
+                H = [host(x[it]).astype(np.float64) for x in (hx, hy, hz)]
+                q = cv.vndf_pdf(v["wx"], v["wy"], v["wz"], hx, hy, hz, v["ax"], v["ay"])
+                g1, g2 = cv.vndf_inverse(v["wx"], v["wy"], v["wz"], hx, hy, hz, v["ax"], v["ay"])
+                torch.cuda.synchronize()
+                ref = oracle.vndf_pdf((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
+                w = np.stack([sub["wx"], sub["wy"], sub["wz"]], 1).astype(np.float64)
+                w /= np.linalg.norm(w, axis=1, keepdims=True)
+                dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
+                rel = np.abs(host(q[it]) / ref - 1.0)
+                assert np.all(rel <= np.maximum(2e-6, 8 * 2.0 ** -24 / dot)), rel.max()
+                r1, r2 = oracle.vndf_inverse((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"],
+                                             sub["ay"])
+                assert np.all(np.abs(host(g2[it]) - r2) <= 32 * 2.0 ** -24)
+                del q, g1, g2
+                s1, s2 = cv.capvndf_uniforms(11, 2, 0, 0, n)
+                torch.cuda.synchronize()
+                assert np.array_equal(host(s1[it]), u1.astype(np.float32))
+                assert np.array_equal(host(s2[it]), u2.astype(np.float32))
+                del s1, s2
+            del hx, hy, hz, pdf, v
+    finally:
+        del t
+        torch.cuda.empty_cache()
