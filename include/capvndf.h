@@ -20,8 +20,9 @@
  *  - Element-wise calls take any n >= 0 that fits in memory: a call longer
  *    than 2^31 elements is enqueued as consecutive launches of 2^31 elements
  *    (results identical to one launch; a HIP error in a later launch leaves
- *    the earlier ones enqueued).  The estimators accept up to 2^24 chunks of
- *    16384 samples (about 2.7e11 samples) per call.
+ *    the earlier ones enqueued).  The estimators accept fewer than 2^24
+ *    chunks of 16384 samples (about 2.7e11 samples) per call; a cell's
+ *    chunks are ceil(nsamples / 16384).
  *  - The library never allocates on these calls, except the batch-plan calls
  *    (which own their chunk tables, partial buffers and graph).
  *  - Return value: CAPVNDF_OK (0) or a negative CAPVNDF_ERR_* code.  All

@@ -463,8 +463,8 @@ int32_t check_cells(const char* fn, int64_t ncells, int64_t nsamples, const floa
     if (ncells > 0 && (double)ncells * (double)lut_chunks_per_cell(nsamples) * kLutBlock >
                           4294967295.0)
         return fail(CAPVNDF_ERR_BAD_SIZE,
-                    "%s: ncells * chunks per cell (%lld * %lld) exceeds 2^24 chunks of %llu "
-                    "samples; split the cells over several calls", fn, (long long)ncells,
+                    "%s: ncells * chunks per cell (%lld * %lld) must be below 2^24 (chunks of "
+                    "%llu samples); split the cells over several calls", fn, (long long)ncells,
                     (long long)lut_chunks_per_cell(nsamples), (unsigned long long)(2 * kLutChunkPairs));
     if (ncells > ((int64_t)1 << 32))
         return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells exceeds the 32-bit stream unit", fn);

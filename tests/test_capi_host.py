@@ -93,6 +93,18 @@ def test_albedo_argument_errors(lib):
     assert lib.albedo_estimate(4, *five, 1 << 40, 0, fake, fake, fake, 1 << 20, None) == -2
     assert lib.albedo_estimate(4, *five, 100, 0, fake, fake, fake, 8, None) == -5
     assert "workspace" in _err(lib)
+    # fewer than 2^24 chunks of 16384 samples (one 256-lane block each, and a
+    # dispatch counts work-items in 32 bits): 2^12 cells of 2^26 samples are
+    # exactly 2^24 chunks, one too many; one sample less per cell still is
+    assert lib.albedo_workspace_size(1 << 12, 1 << 26, 0) == (1 << 24) * 2 * 2 * 4
+    assert lib.albedo_estimate(1 << 12, *five, 1 << 26, 0, fake, fake, fake, 1 << 62,
+                               None) == -2
+    assert "below 2^24" in _err(lib)
+    assert lib.radiance_estimate(1 << 12, *five, None, 1 << 26, 0, None, 0, fake, fake,
+                                 1 << 62, None) == -2
+    # (2^12 - 1) cells pass the size check and fail on the NULL output instead
+    assert lib.albedo_estimate((1 << 12) - 1, *five, 1 << 26, 0, None, fake, fake, 1 << 62,
+                               None) == -1
     assert lib.albedo_estimate(4, *five, 100, 0, fake, fake, None, 0, None) == -5
     assert lib.albedo_estimate(0, *[None] * 5, 100, 0, None, None, None, 0, None) == 0
     assert lib.albedo_estimate_backward(4, *five, 100, 0, None, None, fake, fake, fake, fake, 8,
