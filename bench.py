@@ -364,6 +364,35 @@ def main():
         ref = [o.clone() for o in (plan.albedo, plan.grad_ax)]
         ms_r, _ = timed(plan.run_per_request, max(2, steps // 2), 1)
         dev_a = (plan.albedo - ref[0]).abs().max().item()
+        # The plain-sampler pipeline per request: fill the job's view and
+        # roughness into reusable arrays, draw its uniforms (the estimator's
+        # stream, so the samples are the batch's), run vndf_sample.  Such a
+        # pipeline also needs a weighting and reduction pass, left out here,
+        # so its time is a lower bound.  Timed eagerly and captured in one
+        # graph (which removes the host's launch cost).
+        log("per-request plain-sampler pipeline (lower bound: no weighting pass)")
+        ns = [int(x) for x in j["n"]]
+        nmax = max(ns)
+        vals = [c[k].tolist() for k in ("wx", "wy", "wz", "ax", "ay")]
+        bi = [torch.empty(nmax, device=dev) for _ in range(5)]
+        bu = [torch.empty(nmax, device=dev) for _ in range(2)]
+        bo = [torch.empty(nmax, device=dev) for _ in range(4)]
+
+        def plain():
+            for q, m in enumerate(ns):
+                for b, v in zip(bi, vals):
+                    b[:m].fill_(v[q])
+                u1, u2 = cv.capvndf_uniforms(4, 3, q, 0, m, out=(bu[0][:m], bu[1][:m]))
+                cv.vndf_sample(bi[0][:m], bi[1][:m], bi[2][:m], bi[3][:m], bi[4][:m], u1=u1,
+                               u2=u2, out=tuple(o[:m] for o in bo))
+        ms_plain, _ = timed(plain, 2, 1)
+        t0 = time.perf_counter()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plain()
+        capture_s = time.perf_counter() - t0
+        ms_plain_graph, _ = timed(graph.replay, 3, 1)
+        del graph, bi, bu, bo
         info = plan.info()
         out["batched"] = {"jobs": 4096, "total_samples": info["total_samples"],
                           "tiling": info["tiling"], "chunks": info["nchunks"],
@@ -373,7 +402,14 @@ def main():
                           "default_tiling_dynamic_ms": round(ms_default_dyn, 4),
                           "autotune_s": round(tune_s, 2),
                           "gsamples_per_s_fwd_adj": round(info["total_samples"] / ms_b / 1e6, 2),
-                          "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}")}
+                          "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}"),
+                          "per_request_plain_sampler": {
+                              "what": "per job: 5 fills, the job's uniforms, vndf_sample; no "
+                                      "weighting or reduction pass (a lower bound)",
+                              "eager_ms": round(ms_plain, 2),
+                              "graph_ms": round(ms_plain_graph, 2),
+                              "graph_capture_s": round(capture_s, 2),
+                              "speedup_vs_graph": round(ms_plain_graph / ms_b, 2)}}
         plan.close()
         # a mix of short jobs (2^10 .. 2^14 samples), where wavefront-owned
         # chunks can beat block-owned ones: the autotuner decides

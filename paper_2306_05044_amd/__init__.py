@@ -421,10 +421,17 @@ def albedo_batch_autotune(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_g
     return best.as_tuple(), ms.value
 
 
-def capvndf_uniforms(seed, tag, unit, k0, n, device="cuda", stream=None):
-    """(u1, u2) of samples k0..k0+n-1 of Philox stream (seed, tag, unit)."""
-    u1 = torch.empty(n, dtype=torch.float32, device=device)
-    u2 = torch.empty(n, dtype=torch.float32, device=device)
+def capvndf_uniforms(seed, tag, unit, k0, n, device="cuda", out=None, stream=None):
+    """(u1, u2) of samples k0..k0+n-1 of Philox stream (seed, tag, unit);
+    ``out`` optionally gives the two float32 tensors of n elements to fill."""
+    if out is None:
+        u1 = torch.empty(n, dtype=torch.float32, device=device)
+        u2 = torch.empty(n, dtype=torch.float32, device=device)
+    else:
+        u1, u2 = out
+        _dev(u1, "u1")
+        _dev(u2, "u2")
+        _same_len(n, u1=u1, u2=u2)
     _check("capvndf_uniforms", load_library().capvndf_uniforms(
         seed, tag, unit, k0, n, _ptr(u1), _ptr(u2), _stream(stream)))
     return u1, u2
