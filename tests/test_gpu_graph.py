@@ -1,7 +1,8 @@
 """The library's calls enqueue kernels on the caller's stream only (no
 allocation, no memset, no synchronisation), so a caller can capture them in a
-graph.  Captured here with torch's graph API: the sampler, the dielectric
-sampler and the one-pass albedo value and gradient; the graph is replayed
+graph.  Captured here with torch's graph API: the sampler, the pdf and inverse map at
+its normals, the dielectric sampler and its pdf, the one-pass albedo value and
+gradient, and the direct-illumination estimator; the graph is replayed
 several times with unrelated eager work and synchronisation in between, and
 every replay must equal the eager results bit for bit."""
 
@@ -32,20 +33,32 @@ def test_hot_path_in_a_captured_graph():
     n = 1 << 14
     outs = tuple(torch.empty_like(t["wx"]) for _ in range(4))
     douts = tuple(torch.empty_like(t["wx"]) for _ in range(5))
+    pouts = tuple(torch.empty_like(t["wx"]) for _ in range(4))  # pdf, u1, u2, dielectric pdf
     ws = torch.empty(cv.albedo_workspace_size(64, n, 2) // 4 + 4, device="cuda")
-    vals = [torch.empty(64, device="cuda") for _ in range(4)]
+    wr = torch.empty(cv.albedo_workspace_size(64, n, 0) // 4 + 4, device="cuda")
+    vals = [torch.empty(64, device="cuda") for _ in range(5)]
+    lobes = torch.tensor([[0.0, 0.0, 1.0, 4.0, 2.0], [0.6, 0.0, 0.8, 30.0, 5.0]],
+                         dtype=torch.float32, device="cuda")
 
     def run():
         cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=3, out=outs)
+        cv.vndf_pdf(t["wx"], t["wy"], t["wz"], outs[0], outs[1], outs[2], t["ax"], t["ay"],
+                    out=pouts[0])
+        cv.vndf_inverse(t["wx"], t["wy"], t["wz"], outs[0], outs[1], outs[2], t["ax"], t["ay"],
+                        out=(pouts[1], pouts[2]))
         cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, seed=4, out=douts)
+        cv.dielectric_pdf(t["wx"], t["wy"], t["wz"], douts[0], douts[1], douts[2], t["ax"],
+                          t["ay"], 1.5, out=pouts[3])
         r = cv.albedo_value_and_grad(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], n, 5,
                                      workspace=ws)
         for v, x in zip(vals, r):
             v.copy_(x)
+        vals[4].copy_(cv.radiance_estimate(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], n, 6,
+                                           lobes, workspace=wr))
 
     run()
     torch.cuda.synchronize()
-    eager = [x.clone() for x in outs + douts + tuple(vals)]
+    eager = [x.clone() for x in outs + douts + pouts + tuple(vals)]
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -59,12 +72,12 @@ def test_hot_path_in_a_captured_graph():
     torch.cuda.synchronize()
 
     for rep in range(4):
-        for x in outs + douts + tuple(vals):
+        for x in outs + douts + pouts + tuple(vals):
             x.fill_(float("nan"))
         junk = torch.randn(1 << 16, device="cuda")
         _ = (junk * 3).sum().item()  # unrelated eager work and a synchronisation
         graph.replay()
         torch.cuda.synchronize()
-        for k, (a, b) in enumerate(zip(eager, outs + douts + tuple(vals))):
+        for k, (a, b) in enumerate(zip(eager, outs + douts + pouts + tuple(vals))):
             assert torch.equal(a, b), f"replay {rep}, output {k}"
     assert np.isfinite(eager[0].cpu().numpy()).all()
