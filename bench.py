@@ -30,8 +30,8 @@ METRIC = ("Gsamples/s VNDF (cap vs 2018 disk) + albedo-LUT fwd+bwd time at "
 N_STREAM = 1 << 26
 BYTES_PER_SAMPLE = 36  # 5 FP32 inputs read + 4 FP32 outputs written
 HBM_PEAK_GBS = 8000.0
-SECTIONS = ("stream", "disk", "probe", "inverse", "dielectric", "micro", "lut", "grad", "batch",
-            "radiance")
+SECTIONS = ("stream", "disk", "f64", "probe", "inverse", "dielectric", "micro", "lut", "grad",
+            "batch", "radiance")
 
 
 def log(msg):
@@ -209,6 +209,16 @@ def main():
                            **_bandwidth(BYTES_PER_SAMPLE, ms_disk)}
         if ms_cap:
             out["disk2018"]["t_disk_over_t_cap"] = round(ms_disk / ms_cap, 4)
+    if "f64" in only:
+        log("timing the cap sampler in double precision")
+        ms_f64, _ = timed(run(2), args.steps, args.warmup)
+        out["cap_f64"] = {"what": "the same samples evaluated in double precision: every "
+                                  "output within 2e-6 of the exact sample",
+                          "ms_per_launch": round(ms_f64, 5),
+                          "gsamples_per_s": round(N_STREAM / ms_f64 / 1e6, 3),
+                          **_bandwidth(BYTES_PER_SAMPLE, ms_f64)}
+        if ms_cap:
+            out["cap_f64"]["t_f64_over_t_cap"] = round(ms_f64 / ms_cap, 4)
     if "probe" in only:
         log("timing the streaming probe")
         ins = [t[k] for k in ("wx", "wy", "wz", "ax", "ay")]

@@ -64,6 +64,7 @@ extern "C" {
 /* Hemisphere routine used inside the general VNDF sampler (Sec. 2, steps 1-3). */
 #define CAPVNDF_CAP 0      /* spherical cap, Sec. 3.3 (the paper's method)   */
 #define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
+#define CAPVNDF_CAP_F64 2  /* spherical cap evaluated in double precision   */
 
 /* Version of this ABI (major * 10000 + minor * 100 + patch). */
 int32_t capvndf_version(void);
@@ -76,7 +77,12 @@ const char* capvndf_last_error(void);
  * (warp wi by M^-1 = diag(ax, ay, 1), sample the hemisphere's visible normals,
  * warp back by M^-T and normalise) with the hemisphere routine `method`:
  * CAPVNDF_CAP = Sec. 3.3 (uniform point c on the cap z in (-z_i, 1], half
- * vector c + wi), CAPVNDF_DISK2018 = Heitz's cross-section sampler.
+ * vector c + wi), CAPVNDF_DISK2018 = Heitz's cross-section sampler,
+ * CAPVNDF_CAP_F64 = the cap sampler evaluated in double precision from the
+ * same FP32 inputs and uniforms (same samples; FP32 arithmetic loses about
+ * 2^-24 (1 + max(ax, ay)/L + 1/|c + wi|) relatively, L = |M^-T (c + wi)|,
+ * which exceeds 2e-6 near grazing half vectors; in double every output is
+ * within 2e-6, in practice a few ulps, of the exact sample).
  *
  *   n            number of tuples (>= 0; 0 enqueues nothing)
  *   wix,wiy,wiz  view directions wi (need not be unit; w_z > 0)       [n]

@@ -27,10 +27,12 @@ LIB_PATH = os.path.join(_HERE, "libcapvndf.so")
 
 CAP = 0
 DISK2018 = 1
+CAP_F64 = 2
 TAG_SAMPLE = 2
 TAG_ALBEDO = 3
 
-_METHODS = {"cap": CAP, "disk2018": DISK2018, CAP: CAP, DISK2018: DISK2018}
+_METHODS = {"cap": CAP, "disk2018": DISK2018, "cap_f64": CAP_F64, CAP: CAP,
+            DISK2018: DISK2018, CAP_F64: CAP_F64}
 
 
 class CapvndfError(RuntimeError):

@@ -166,6 +166,49 @@ __device__ __forceinline__ float cap_pdf(const Stretched& s, const CapSample& c,
     return L3 * kInvPi * rcp(ax * ay * s.opz * hs2);
 }
 
+// The same cap sample and pdf evaluated in double precision from the FP32
+// inputs and uniforms, rounded to FP32 only at the end.  The FP32 evaluation
+// above forms the half vector hs = c + ws from unit vectors, so its absolute
+// rounding of O(2^-24) reaches h and the pdf relatively as
+// O(2^-24 (1 + max(ax, ay) / L + 1 / |hs|)), which exceeds 2e-6 on a few
+// samples in 10^4 of a log-uniform roughness workload (near-grazing halves).
+// In double the same steps leave O(2^-53) times that factor, so every output
+// is the exactly rounded FP32 value up to a few ulps.  sin/cos(2 pi u1) come
+// from the double-precision sincospi of the math library.
+constexpr double kPiD = 3.14159265358979323846;
+
+template <bool WITH_PDF>
+__device__ __forceinline__ void cap_sample_f64(float wxf, float wyf, float wzf, float axf,
+                                               float ayf, float u1f, float u2f, float& hx,
+                                               float& hy, float& hz, float& pdf) {
+    const double wz = wzf, ax = axf, ay = ayf;
+    const double px = ax * (double)wxf, py = ay * (double)wyf;
+    const double q = __builtin_fma(px, px, py * py);
+    const double l = __builtin_sqrt(__builtin_fma(wz, wz, q));
+    const double il = 1.0 / l;
+    const double lpz = l + wz;
+    const double opz = lpz * il;          // 1 + zs
+    const double omz = q * il / lpz;      // 1 - zs
+    const double u2 = u2f;
+    const double hsz = (1.0 - u2) * opz;  // z + zs
+    const double st = __builtin_sqrt(u2 * opz * (hsz + omz));
+    double sp, cp;
+    sincospi(2.0 * (double)u1f, &sp, &cp);
+    const double hsx = __builtin_fma(st, cp, px * il);
+    const double hsy = __builtin_fma(st, sp, py * il);
+    const double vx = ax * hsx, vy = ay * hsy;
+    const double L2 = __builtin_fma(vx, vx, __builtin_fma(vy, vy, hsz * hsz));
+    const double L = __builtin_sqrt(L2);
+    const double iL = 1.0 / L;
+    hx = (float)(vx * iL);
+    hy = (float)(vy * iL);
+    hz = (float)(hsz * iL);
+    if (WITH_PDF) {
+        const double hs2 = __builtin_fma(hsx, hsx, __builtin_fma(hsy, hsy, hsz * hsz));
+        pdf = (float)(L2 * L / (kPiD * ax * ay * opz * hs2));
+    }
+}
+
 // Heitz's 2018 cross-section sampler (Sec. 2), the comparison baseline, in the
 // hemisphere space: orthonormal basis around ws, polar disk sample, warp of
 // the second coordinate by s = (1 + zs) / 2, reprojection.  Returns the unit

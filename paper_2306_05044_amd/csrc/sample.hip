@@ -46,6 +46,15 @@ __device__ __forceinline__ void sample_one(float wx, float wy, float wz, float a
     if (!ok) {
         wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f;
     }
+    if (METHOD == CAPVNDF_CAP_F64) {
+        float p64 = 0.0f;
+        cap_sample_f64<WITH_PDF>(wx, wy, wz, ax, ay, u1, u2, hx, hy, hz, p64);
+        if (!ok) {
+            hx = 0.0f; hy = 0.0f; hz = 1.0f;
+        }
+        pdf = ok ? p64 : 0.0f;
+        return;
+    }
     const Stretched s = stretch(wx, wy, wz, ax, ay);
     float p = 0.0f;
     Normal n;
@@ -459,7 +468,7 @@ extern "C" int32_t vndf_sample(int64_t n, const float* wix, const float* wiy, co
                                uint64_t seed, uint64_t index_base, int32_t method, float* hx,
                                float* hy, float* hz, float* pdf, void* stream) {
     if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_sample: n = %lld < 0", (long long)n);
-    if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018)
+    if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018 && method != CAPVNDF_CAP_F64)
         return fail(CAPVNDF_ERR_BAD_METHOD, "vndf_sample: unknown method %d", method);
     if ((u1 == nullptr) != (u2 == nullptr))
         return fail(CAPVNDF_ERR_NULL_PTR, "vndf_sample: give both u1 and u2 or neither");
@@ -488,6 +497,11 @@ extern "C" int32_t vndf_sample(int64_t n, const float* wix, const float* wiy, co
                                          at(ax, o), at(ay, o), at(u1, o), at(u2, o), ib,
                                          key_lo(seed), key_hi(seed), at(hx, o), at(hy, o),
                                          at(hz, o), at(pdf, o), st);
+        else if (method == CAPVNDF_CAP_F64)
+            dispatch_sample<CAPVNDF_CAP_F64>(vec, eu, wp, m, at(wix, o), at(wiy, o), at(wiz, o),
+                                             at(ax, o), at(ay, o), at(u1, o), at(u2, o), ib,
+                                             key_lo(seed), key_hi(seed), at(hx, o), at(hy, o),
+                                             at(hz, o), at(pdf, o), st);
         else
             dispatch_sample<CAPVNDF_DISK2018>(vec, eu, wp, m, at(wix, o), at(wiy, o), at(wiz, o),
                                               at(ax, o), at(ay, o), at(u1, o), at(u2, o), ib,
