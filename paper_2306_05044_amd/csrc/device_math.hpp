@@ -172,10 +172,61 @@ __device__ __forceinline__ float cap_pdf(const Stretched& s, const CapSample& c,
 // rounding of O(2^-24) reaches h and the pdf relatively as
 // O(2^-24 (1 + max(ax, ay) / L + 1 / |hs|)), which exceeds 2e-6 on a few
 // samples in 10^4 of a log-uniform roughness workload (near-grazing halves).
-// In double the same steps leave O(2^-53) times that factor, so every output
-// is the exactly rounded FP32 value up to a few ulps.  sin/cos(2 pi u1) come
-// from the double-precision sincospi of the math library.
+// In double the same steps leave O(2^-50) times that factor.  The double
+// arithmetic is kept to what that needs: reciprocals and reciprocal square
+// roots from the hardware estimates refined by two Newton steps each (each
+// step squares the relative error), and sin/cos(2 pi u1) by an exact
+// quadrant reduction (u1 has 24 fraction bits) and Taylor polynomials on
+// [-pi/4, pi/4] whose truncation error is below 1e-18.
 constexpr double kPiD = 3.14159265358979323846;
+constexpr double kHalfPiD = 1.57079632679489661923;
+
+__device__ __forceinline__ double rcp_f64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * __builtin_fma(-x, y, 2.0);
+    y = y * __builtin_fma(-x, y, 2.0);
+    return y;
+}
+
+__device__ __forceinline__ double rsq_f64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * __builtin_fma(-hx * y, y, 1.5);
+    y = y * __builtin_fma(-hx * y, y, 1.5);
+    return y;
+}
+
+__device__ __forceinline__ void sincos_turns_f64(float u, double* sn, double* cs) {
+    const double v = 4.0 * (double)u;  // exact
+    const double k = __builtin_rint(v);
+    const double x = (v - k) * kHalfPiD;  // v - k exact, |x| <= pi/4
+    const double x2 = x * x;
+    // sin x = x (1 - x^2/3! + x^4/5! - ... - x^16/17!), cos x = 1 - x^2/2! + ... + x^16/16!
+    double ps = 1.0 / 355687428096000.0;
+    ps = __builtin_fma(ps, x2, -1.0 / 1307674368000.0);
+    ps = __builtin_fma(ps, x2, 1.0 / 6227020800.0);
+    ps = __builtin_fma(ps, x2, -1.0 / 39916800.0);
+    ps = __builtin_fma(ps, x2, 1.0 / 362880.0);
+    ps = __builtin_fma(ps, x2, -1.0 / 5040.0);
+    ps = __builtin_fma(ps, x2, 1.0 / 120.0);
+    ps = __builtin_fma(ps, x2, -1.0 / 6.0);
+    const double sx = __builtin_fma(ps * x2, x, x);
+    double pc = 1.0 / 20922789888000.0;
+    pc = __builtin_fma(pc, x2, -1.0 / 87178291200.0);
+    pc = __builtin_fma(pc, x2, 1.0 / 479001600.0);
+    pc = __builtin_fma(pc, x2, -1.0 / 3628800.0);
+    pc = __builtin_fma(pc, x2, 1.0 / 40320.0);
+    pc = __builtin_fma(pc, x2, -1.0 / 720.0);
+    pc = __builtin_fma(pc, x2, 1.0 / 24.0);
+    pc = __builtin_fma(pc, x2, -0.5);
+    const double cx = __builtin_fma(pc, x2, 1.0);
+    // the angle is (k + x / (pi/2)) quarter turns
+    const int q = (int)k & 3;
+    const double s1 = (q & 1) ? cx : sx;
+    const double c1 = (q & 1) ? sx : cx;
+    *sn = (q & 2) ? -s1 : s1;
+    *cs = ((q + 1) & 2) ? -c1 : c1;
+}
 
 template <bool WITH_PDF>
 __device__ __forceinline__ void cap_sample_f64(float wxf, float wyf, float wzf, float axf,
@@ -184,28 +235,29 @@ __device__ __forceinline__ void cap_sample_f64(float wxf, float wyf, float wzf, 
     const double wz = wzf, ax = axf, ay = ayf;
     const double px = ax * (double)wxf, py = ay * (double)wyf;
     const double q = __builtin_fma(px, px, py * py);
-    const double l = __builtin_sqrt(__builtin_fma(wz, wz, q));
-    const double il = 1.0 / l;
+    const double l2 = __builtin_fma(wz, wz, q);
+    const double il = rsq_f64(l2);
+    const double l = l2 * il;
     const double lpz = l + wz;
-    const double opz = lpz * il;          // 1 + zs
-    const double omz = q * il / lpz;      // 1 - zs
+    const double opz = lpz * il;                // 1 + zs
+    const double omz = q * il * rcp_f64(lpz);   // 1 - zs
     const double u2 = u2f;
-    const double hsz = (1.0 - u2) * opz;  // z + zs
-    const double st = __builtin_sqrt(u2 * opz * (hsz + omz));
+    const double hsz = (1.0 - u2) * opz;        // z + zs
+    const double s2 = u2 * opz * (hsz + omz);   // sin^2 of the cap angle
+    const double st = s2 > 0.0 ? s2 * rsq_f64(s2) : 0.0;
     double sp, cp;
-    sincospi(2.0 * (double)u1f, &sp, &cp);
+    sincos_turns_f64(u1f, &sp, &cp);
     const double hsx = __builtin_fma(st, cp, px * il);
     const double hsy = __builtin_fma(st, sp, py * il);
     const double vx = ax * hsx, vy = ay * hsy;
     const double L2 = __builtin_fma(vx, vx, __builtin_fma(vy, vy, hsz * hsz));
-    const double L = __builtin_sqrt(L2);
-    const double iL = 1.0 / L;
+    const double iL = rsq_f64(L2);
     hx = (float)(vx * iL);
     hy = (float)(vy * iL);
     hz = (float)(hsz * iL);
     if (WITH_PDF) {
         const double hs2 = __builtin_fma(hsx, hsx, __builtin_fma(hsy, hsy, hsz * hsz));
-        pdf = (float)(L2 * L / (kPiD * ax * ay * opz * hs2));
+        pdf = (float)(L2 * L2 * iL * rcp_f64(kPiD * ax * ay * opz * hs2));
     }
 }
 

@@ -30,6 +30,13 @@ namespace {
 #ifndef CAPVNDF_INVERSE_CACHED
 #define CAPVNDF_INVERSE_CACHED 0
 #endif
+// vec4 groups per lane of the double-precision sampler, whose registers per
+// tuple are about twice the FP32 sampler's.  Measured at 2^26: one group
+// (94 VGPRs) 0.4505 ms, two (124) 0.478 ms, four (158) 0.4545 ms.
+#ifndef CAPVNDF_F64_GROUPS
+#define CAPVNDF_F64_GROUPS 1
+#endif
+constexpr int kF64Groups = CAPVNDF_F64_GROUPS;
 constexpr int kPdfGroups = CAPVNDF_PDF_GROUPS;
 constexpr bool kPdfCached = CAPVNDF_PDF_CACHED != 0;
 constexpr int kInverseGroups = CAPVNDF_INVERSE_GROUPS;
@@ -82,19 +89,19 @@ __device__ __forceinline__ void stream_u(uint64_t k, uint32_t key0, uint32_t key
 }
 
 // Vector path (index_base even, arrays 16-byte aligned).  A block owns a tile
-// of kBlock * 4 * kGroups consecutive tuples and each lane kGroups groups of
+// of kBlock * 4 * G consecutive tuples and each lane G groups of
 // four (see group_start: every wavefront reads a contiguous run per array).
 // All loads of a lane are issued before any arithmetic to keep enough bytes
 // in flight.  Groups that straddle n finish their tuples one by one.
-template <int METHOD, bool EXPLICIT_U, bool WITH_PDF>
+template <int METHOD, bool EXPLICIT_U, bool WITH_PDF, int G = kGroups>
 __global__ __launch_bounds__(kBlock) void k_sample_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
     const float* __restrict__ wiz, const float* __restrict__ ax, const float* __restrict__ ay,
     const float* __restrict__ u1p, const float* __restrict__ u2p, uint64_t index_base,
     uint32_t key0, uint32_t key1, float* __restrict__ hx, float* __restrict__ hy,
     float* __restrict__ hz, float* __restrict__ pdf) {
-    const int64_t tile = (int64_t)blockIdx.x * kTile;
-    f4 x[kGroups], y[kGroups], z[kGroups], a[kGroups], b[kGroups], r1[kGroups], r2[kGroups];
+    const int64_t tile = (int64_t)blockIdx.x * kBlock * 4 * G;
+    f4 x[G], y[G], z[G], a[G], b[G], r1[G], r2[G];
     load_groups(x, wix, tile, n);
     load_groups(y, wiy, tile, n);
     load_groups(z, wiz, tile, n);
@@ -105,8 +112,8 @@ __global__ __launch_bounds__(kBlock) void k_sample_v4(
         load_groups(r2, u2p, tile, n);
     }
 #pragma unroll
-    for (int g = 0; g < kGroups; ++g) {
-        const int64_t i0 = group_start<kGroups>(tile, g);
+    for (int g = 0; g < G; ++g) {
+        const int64_t i0 = group_start<G>(tile, g);
         if (i0 + 4 <= n) {
             if (!EXPLICIT_U) {
                 const uint64_t pair = (index_base >> 1) + (uint64_t)(i0 >> 1);
@@ -432,8 +439,9 @@ void launch_sample(bool vec, int64_t n, const float* wix, const float* wiy, cons
                    const float* ax, const float* ay, const float* u1, const float* u2,
                    uint64_t index_base, uint32_t k0, uint32_t k1, float* hx, float* hy, float* hz,
                    float* pdf, hipStream_t st) {
+    constexpr int G = METHOD == CAPVNDF_CAP_F64 ? kF64Groups : kGroups;
     if (vec) {
-        hipLaunchKernelGGL((k_sample_v4<METHOD, EU, WP>), dim3(tiles_for(n)),
+        hipLaunchKernelGGL((k_sample_v4<METHOD, EU, WP, G>), dim3(tiles_for<G>(n)),
                            dim3(kBlock), 0, st, n, wix, wiy, wiz, ax, ay, u1, u2, index_base, k0,
                            k1, hx, hy, hz, pdf);
     } else {
