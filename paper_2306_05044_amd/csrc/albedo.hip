@@ -704,11 +704,24 @@ bool cache_lookup(const std::string& sig, capvndf_tiling* out) {
     if (!path || !*path) return false;
     FILE* f = fopen(path, "r");
     if (!f) return false;
-    char key[256];
+    char line[512], key[256];
     int b, p, c, w, dy;
     float ms;
     bool found = false;
-    while (fscanf(f, "%255s %d %d %d %d %d %f", key, &b, &p, &c, &w, &dy, &ms) == 7) {
+    // line by line, exactly seven whitespace-separated fields: lines of
+    // another layout (an older one without the dynamic field, a truncated
+    // write) are skipped
+    while (fgets(line, sizeof(line), f)) {
+        int fields = 0;
+        for (const char* q = line; *q;) {
+            while (*q == ' ' || *q == '\t' || *q == '\n' || *q == '\r') ++q;
+            if (!*q) break;
+            ++fields;
+            while (*q && *q != ' ' && *q != '\t' && *q != '\n' && *q != '\r') ++q;
+        }
+        if (fields != 7 ||
+            sscanf(line, "%255s %d %d %d %d %d %f", key, &b, &p, &c, &w, &dy, &ms) != 7)
+            continue;
         capvndf_tiling t{b, p, c, w, dy};
         if (sig == key && valid_tiling(t)) {
             *out = t;  // last matching line wins

@@ -152,6 +152,18 @@ def test_autotune_small(tmp_path, monkeypatch):
     plan.run()
     torch.cuda.synchronize()
     _check(plan, j, 1.0, True)
+    plan.close()
+    # lines of another layout for the same problem are skipped, not misread:
+    # a six-field line (no dynamic field) whose time would parse as a valid
+    # dynamic flag, and a truncated line
+    sig = text[0]
+    other = (512, 16, 2, 1) if tuple(best[:4]) != (512, 16, 2, 1) else (256, 16, 2, 1)
+    with open(tmp_path / "tune.txt", "a") as f:
+        f.write(f"{sig} {other[0]} {other[1]} {other[2]} {other[3]} 1.250000\n")
+        f.write(f"{sig} {other[0]} {other[1]}\n")
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
+    assert plan.info()["tiling"] == best
+    plan.close()
 
 
 @pytest.mark.parametrize("tiling", [None, (256, 8, 4, 1), (512, 32, 8, 0, 1)])
