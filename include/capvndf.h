@@ -66,7 +66,10 @@ extern "C" {
 #define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
 #define CAPVNDF_CAP_F64 2  /* spherical cap evaluated in double precision   */
 
-/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+/* Version of this ABI (major * 10000 + minor * 100 + patch): 2.0.0.  Major 2
+ * added the `dynamic` field to capvndf_tiling (a layout change) and the
+ * CAPVNDF_CAP_F64 method. */
+#define CAPVNDF_VERSION 20000
 int32_t capvndf_version(void);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -33,6 +33,6 @@ int32_t check_array(const void* p, const char* name) {
 
 }  // namespace capvndf
 
-extern "C" int32_t capvndf_version(void) { return 10000; }
+extern "C" int32_t capvndf_version(void) { return CAPVNDF_VERSION; }
 
 extern "C" const char* capvndf_last_error(void) { return capvndf::g_last_error; }

@@ -48,7 +48,14 @@ def test_binding_covers_the_header():
 
 
 def test_version(lib):
-    assert lib.capvndf_version() == 10000
+    import re
+    hdr = open(os.path.join(ROOT, "include", "capvndf.h")).read()
+    assert lib.capvndf_version() == int(re.search(r"#define CAPVNDF_VERSION (\d+)", hdr).group(1))
+    # the binding's tiling struct matches the header's field list
+    import paper_2306_05044_amd as cv
+    fields = re.search(r"typedef struct capvndf_tiling \{(.*?)\}", hdr, re.S).group(1)
+    names = re.findall(r"int32_t (\w+);", fields)
+    assert [f[0] for f in cv.Tiling._fields_] == names
 
 
 def _err(lib):
