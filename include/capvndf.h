@@ -114,7 +114,10 @@ int32_t vndf_sample(int64_t n, const float* wix, const float* wiy, const float* 
  * pdf = G1(wi) max(0, wi.h) D(h) / w_z with D and G1 of Appendix A.
  *
  *   n; wix,wiy,wiz [n]; hx,hy,hz unit normals [n]; ax, ay [n]; pdf out [n].
- * pdf is 0 when w_z <= 0, h_z <= 0, wi.h <= 0 or alpha <= 0.
+ * pdf is 0 when w_z <= 0, h_z <= 0, wi.h <= 0 or alpha <= 0.  Evaluated in
+ * double precision with an exact wi.h, so grazing normals keep full relative
+ * accuracy (the result is the FP32 rounding of the exact value up to a few
+ * ulps).
  * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, HIP.
  */
 int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz,

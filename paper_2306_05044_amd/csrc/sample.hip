@@ -177,21 +177,40 @@ __global__ __launch_bounds__(kBlock) void k_sample_scalar(
 
 // pdf of Eq. (1) at a given unit h: G1(wi) = 2 w_z / (l + w_z) with
 // l = |M^-1 wi|, D(h) = 1 / (pi ax ay k^2) with k = |M^T h|^2, so
-// pdf = 2 (wi.h) / ((l + w_z) pi ax ay k^2).
-__device__ __forceinline__ float pdf_one(float wx, float wy, float wz, float hx, float hy,
-                                         float hz, float ax, float ay) {
-    const bool ok0 = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f) && (hz > 0.0f);
+// pdf = 2 (wi.h) / ((l + w_z) pi ax ay k^2).  Evaluated in double: the
+// three products of wi.h are exact there (24 x 24 bits) and are summed with
+// error-free transformations, so the dot product, which cancels near
+// grazing, keeps its full relative accuracy; the other factors are sums of
+// squares.  With K = k ax^2 ay^2 = (hx ay)^2 + (hy ax)^2 + (hz ax ay)^2,
+// pdf = 2 (wi.h) ax^3 ay^3 / ((l + w_z) pi K^2): one reciprocal.  The kernel
+// is bound by HBM traffic, which hides the double arithmetic.
+__device__ __forceinline__ double two_sum(double a, double b, double& err) {
+    const double s = a + b;
+    const double bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
+__device__ __forceinline__ float pdf_one(float wxf, float wyf, float wzf, float hxf, float hyf,
+                                         float hzf, float axf, float ayf) {
+    const bool ok0 = (wzf > 0.0f) && (axf > 0.0f) && (ayf > 0.0f) && (hzf > 0.0f);
     if (!ok0) {
-        wz = 1.0f; ax = 1.0f; ay = 1.0f; hz = 1.0f;
+        wzf = 1.0f; axf = 1.0f; ayf = 1.0f; hzf = 1.0f;
     }
-    const float d = __builtin_fmaf(wx, hx, __builtin_fmaf(wy, hy, wz * hz));
-    const float px = ax * wx, py = ay * wy;
-    const float l = fsqrt(__builtin_fmaf(px, px, __builtin_fmaf(py, py, wz * wz)));
-    const float iax = rcp(ax), iay = rcp(ay);
-    const float sx = hx * iax, sy = hy * iay;
-    const float k = __builtin_fmaf(sx, sx, __builtin_fmaf(sy, sy, hz * hz));
-    const float p = 2.0f * kInvPi * d * rcp((l + wz) * ax * ay * k * k);
-    return (ok0 && d > 0.0f) ? p : 0.0f;
+    const double wx = wxf, wy = wyf, wz = wzf, hx = hxf, hy = hyf, hz = hzf;
+    const double ax = axf, ay = ayf;
+    double e1, e2;
+    const double s12 = two_sum(wx * hx, wy * hy, e1);
+    const double s = two_sum(s12, wz * hz, e2);
+    const double d = s + (e1 + e2);
+    const double px = ax * wx, py = ay * wy;
+    const double l2 = __builtin_fma(px, px, __builtin_fma(py, py, wz * wz));
+    const double l = l2 * rsq_f64(l2);
+    const double axy = ax * ay;
+    const double kx = hx * ay, ky = hy * ax, kz = hz * axy;
+    const double K = __builtin_fma(kx, kx, __builtin_fma(ky, ky, kz * kz));
+    const double p = 2.0 * d * (axy * axy * axy) * rcp_f64((l + wz) * kPiD * K * K);
+    return (ok0 && d > 0.0) ? (float)p : 0.0f;
 }
 
 template <int G, bool CACHED_OUT>

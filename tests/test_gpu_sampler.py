@@ -155,7 +155,8 @@ def test_domain_edges(method):
 
 def test_pdf_entry_point():
     """vndf_pdf at the GPU's FP32 normals vs the oracle's Eq. (1) at the same
-    FP32 values; relative tolerance max(2e-6, 8 eps / (wi.h))."""
+    FP32 values: every element within 2e-6 relative (the entry point works in
+    double with an exact wi.h, so grazing normals lose nothing)."""
     d = workloads.tuples_streaming(65536 + 3, seed=8)
     t = to_dev(d)
     hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=2)
@@ -166,8 +167,8 @@ def test_pdf_entry_point():
     w /= np.linalg.norm(w, axis=1, keepdims=True)
     dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
     rel = np.abs(host(pdf) / ref - 1.0)
-    lim = np.maximum(2e-6, 8 * 2.0 ** -24 / dot)
-    assert np.all(rel <= lim), (rel / lim).max()
+    assert np.all(rel <= 2e-6), rel.max()
+    print(f"vndf_pdf: max rel {rel.max():.2e}, min wi.h {dot.min():.2e}")
     # zero outside the domain
     neg = -t["wz"][:16].clone()
     p0 = cv.vndf_pdf(t["wx"][:16].clone(), t["wy"][:16].clone(), neg, hx[:16].clone(),
@@ -261,10 +262,42 @@ def test_inverse_map(n):
     assert np.median(e2) < 1e-6
 
 
+def test_pdf_entry_point_at_grazing_normals():
+    """Normals at wi.h from 1e-6 to 1e-2 (h = t + eps wi normalised, t the unit
+    tangent towards the pole): the FP32 dot product would lose up to
+    2^-24 / (wi.h) relatively (several percent at 1e-6); the double-precision
+    entry point stays within 2e-6 of the oracle on every element."""
+    d = workloads.tuples_streaming(4096, seed=12)
+    w = np.stack([d["wx"], d["wy"], d["wz"]], 1).astype(np.float64)
+    w /= np.linalg.norm(w, axis=1, keepdims=True)
+    wif = w.astype(np.float32)
+    w = wif.astype(np.float64)
+    ez = np.array([0.0, 0.0, 1.0])
+    tng = ez[None, :] - w[:, 2:3] * w
+    tng /= np.linalg.norm(tng, axis=1, keepdims=True)
+    eps = 10.0 ** np.linspace(-6, -2, 4096)
+    h = tng + eps[:, None] * w
+    h /= np.linalg.norm(h, axis=1, keepdims=True)
+    hf = h.astype(np.float32)
+    keep = (hf[:, 2] > 0) & (np.einsum("ij,ij->i", wif.astype(np.float64), hf.astype(np.float64)) > 0)
+    t = to_dev({"wx": wif[keep, 0].copy(), "wy": wif[keep, 1].copy(), "wz": wif[keep, 2].copy(),
+                "hx": hf[keep, 0].copy(), "hy": hf[keep, 1].copy(), "hz": hf[keep, 2].copy(),
+                "ax": d["ax"][keep], "ay": d["ay"][keep]})
+    got = host(cv.vndf_pdf(t["wx"], t["wy"], t["wz"], t["hx"], t["hy"], t["hz"], t["ax"],
+                           t["ay"])).astype(np.float64)
+    H = [hf[keep, j].astype(np.float64) for j in range(3)]
+    W = tuple(wif[keep, j] for j in range(3))
+    ref = oracle.vndf_pdf(W, H, d["ax"][keep], d["ay"][keep])
+    rel = np.abs(got / ref - 1.0)
+    print(f"grazing vndf_pdf: {keep.sum()} normals, max rel {rel.max():.2e}")
+    assert keep.sum() > 3500 and np.all(ref > 0)
+    assert np.all(rel <= 2e-6), rel.max()
+
+
 def test_inverse_and_pdf_full_size_sampled():
     """2^26 streaming tuples in the benchmark's launch configuration: the
     inverse map and vndf_pdf over all the GPU's normals, 2^16 sampled outputs
-    against the oracle at the same FP32 normals (rules as above), range and
+    against the oracle at the same FP32 normals (pdf within 2e-6), range and
     round-trip properties on all of them."""
     n = 1 << 26
     d = workloads.tuples_streaming(n, seed=1)
@@ -301,7 +334,7 @@ def test_inverse_and_pdf_full_size_sampled():
     w /= np.linalg.norm(w, axis=1, keepdims=True)
     dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
     rel = np.abs(host(pdf[it]) / ref - 1.0)
-    assert np.all(rel <= np.maximum(2e-6, 8 * eps / dot)), rel.max()
+    assert np.all(rel <= 2e-6), rel.max()
 
 
 def test_inverse_edges_and_scalar_path():
@@ -447,7 +480,7 @@ def test_more_than_one_launch_sampled():
                 w /= np.linalg.norm(w, axis=1, keepdims=True)
                 dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
                 rel = np.abs(host(q[it]) / ref - 1.0)
-                assert np.all(rel <= np.maximum(2e-6, 8 * 2.0 ** -24 / dot)), rel.max()
+                assert np.all(rel <= 2e-6), rel.max()
                 r1, r2 = oracle.vndf_inverse((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"],
                                              sub["ay"])
                 assert np.all(np.abs(host(g2[it]) - r2) <= 32 * 2.0 ** -24)
