@@ -135,9 +135,11 @@ int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const float* wiz
  *
  *   n; wix,wiy,wiz [n]; hx,hy,hz unit visible normals [n]; ax, ay [n];
  *   u1, u2 [n] out: in [0, 1) (u2 clamped there, since rounding can
- *   carry a normal at the rim of the cap past 1); both -1 outside the domain (w_z <= 0,
- *   alpha <= 0, h_z <= 0 or wi.h <= 0).  u1 is undefined at the apex of the
- *   cap (u2 = 0) and returned as atan2 gives it there.
+ *   carry a normal at the rim of the cap past 1); both -1 outside the
+ *   domain (w_z <= 0, alpha <= 0, h_z <= 0 or wi.h <= 0).  u1 is undefined
+ *   at the apex of the cap (u2 = 0) and returned as atan2 gives it there.
+ * The geometry is evaluated in double and the azimuth in FP32: u2 is the
+ * rounding of the exact value, u1 within a few 2^-24 turns of it.
  * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, HIP.
  */
 int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, const float* wiz,

@@ -260,27 +260,40 @@ __global__ __launch_bounds__(kBlock) void k_pdf_scalar(
 // n = M^T h / |M^T h| reflects ws into the cap point c = 2 (n . ws) n - ws
 // (reflection law); then 1 - u2 = (c_z + zs) / (1 + zs), i.e.
 // u2 = (1 + zs - 2 (n . ws) n_z) / (1 + zs), and u1 = atan2(c_y, c_x) / (2 pi)
-// in [0, 1).  Outside the domain both are -1.
-__device__ __forceinline__ void inverse_one(float wx, float wy, float wz, float hx, float hy,
-                                            float hz, float ax, float ay, float& u1, float& u2) {
-    const float d0 = __builtin_fmaf(wx, hx, __builtin_fmaf(wy, hy, wz * hz));
-    const bool ok = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f) && (hz > 0.0f) && (d0 > 0.0f);
+// in [0, 1).  Outside the domain both are -1.  The geometry runs in double
+// (u2 cancels near the apex of the cap, and c_xy shrinks there), with
+// n taken along (hx ay, hy ax, hz ax ay), which needs no division; only the
+// azimuth of the double-accurate c is taken in FP32, which keeps its error at
+// a few 2^-24 turns however small c_xy is.
+__device__ __forceinline__ void inverse_one(float wxf, float wyf, float wzf, float hxf, float hyf,
+                                            float hzf, float axf, float ayf, float& u1, float& u2) {
+    double e1, e2;
+    const double s12 = two_sum((double)wxf * hxf, (double)wyf * hyf, e1);
+    const double d0 = two_sum(s12, (double)wzf * hzf, e2) + (e1 + e2);
+    const bool ok = (wzf > 0.0f) && (axf > 0.0f) && (ayf > 0.0f) && (hzf > 0.0f) && (d0 > 0.0);
     if (!ok) {
-        wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f; hx = 0.0f; hy = 0.0f; hz = 1.0f;
+        wxf = 0.0f; wyf = 0.0f; wzf = 1.0f; axf = 1.0f; ayf = 1.0f; hxf = 0.0f; hyf = 0.0f;
+        hzf = 1.0f;
     }
-    const Stretched s = stretch(wx, wy, wz, ax, ay);
-    const float mx = hx * rcp(ax), my = hy * rcp(ay);
-    const float im = rsq(__builtin_fmaf(mx, mx, __builtin_fmaf(my, my, hz * hz)));
-    const float nx = mx * im, ny = my * im, nz = hz * im;
-    const float d2 = 2.0f * __builtin_fmaf(nx, s.wsx, __builtin_fmaf(ny, s.wsy, nz * s.zs));
-    const float cx = __builtin_fmaf(d2, nx, -s.wsx);
-    const float cy = __builtin_fmaf(d2, ny, -s.wsy);
-    const float v2 = __builtin_fmaf(-d2, nz, s.opz) * rcp(s.opz);
-    float t = atan2f(cy, cx) * 0.159154943091895336f;
+    const double ax = axf, ay = ayf, wz = wzf;
+    const double px = ax * (double)wxf, py = ay * (double)wyf;
+    const double l2 = __builtin_fma(px, px, __builtin_fma(py, py, wz * wz));
+    const double il = rsq_f64(l2);
+    const double wsx = px * il, wsy = py * il, zs = wz * il;
+    const double opz = (l2 * il + wz) * il;  // 1 + zs
+    const double mx = (double)hxf * ay, my = (double)hyf * ax, mz = (double)hzf * (ax * ay);
+    const double im = rsq_f64(__builtin_fma(mx, mx, __builtin_fma(my, my, mz * mz)));
+    const double nx = mx * im, ny = my * im, nz = mz * im;
+    const double d2 = 2.0 * __builtin_fma(nx, wsx, __builtin_fma(ny, wsy, nz * zs));
+    const double cx = __builtin_fma(d2, nx, -wsx);
+    const double cy = __builtin_fma(d2, ny, -wsy);
+    const float v2 = (float)(__builtin_fma(-d2, nz, opz) * rcp_f64(opz));
+    float t = atan2f((float)cy, (float)cx) * 0.159154943091895336f;
     t = t < 0.0f ? t + 1.0f : t;
     t = t >= 1.0f ? 0.0f : t;
     u1 = ok ? t : -1.0f;
-    // rounding can carry a normal at the rim of the cap to u2 >= 1: clamp into [0, 1)
+    // a normal at the rim of the cap, rounded to FP32, can map to u2 >= 1:
+    // clamp into [0, 1)
     u2 = ok ? fminf(fmaxf(v2, 0.0f), 0x1.fffffep-1f) : -1.0f;
 }
 

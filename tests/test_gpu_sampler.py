@@ -235,9 +235,11 @@ def _circ(a, b):
 @pytest.mark.parametrize("n", [65536 + 3, 4096])
 def test_inverse_map(n):
     """vndf_inverse on the GPU's own FP32 normals vs the oracle's inverse of the
-    same FP32 values (Sec. 3.2 reflection law).  Arithmetic bound with identical
-    inputs: |du2| <= 32 eps; |du1| <= 32 eps / |c_xy| (c the cap point), tested
-    where |c_xy| > 1e-3 (u1 is undefined at the apex)."""
+    same FP32 values (Sec. 3.2 reflection law).  The entry point's geometry is
+    double precision, so with identical inputs |du2| <= 2 eps (its final
+    rounding) and |du1| <= 4 eps turns (the FP32 azimuth of an accurate cap
+    point), tested where |c_xy| > 1e-6 (u1 is undefined at the apex, and the
+    oracle's own azimuth loses 1e-16 / |c_xy| there)."""
     d = workloads.tuples_streaming(n, seed=31)
     t = to_dev(d)
     u1, u2 = cv.capvndf_uniforms(9, 2, 0, 0, n)
@@ -246,14 +248,18 @@ def test_inverse_map(n):
     H = [host(x).astype(np.float64) for x in (hx, hy, hz)]
     r1, r2 = oracle.vndf_inverse((d["wx"], d["wy"], d["wz"]), H, d["ax"], d["ay"])
     eps = 2.0 ** -24
-    assert np.all(np.abs(host(g2) - r2) <= 32 * eps)
+    e2 = np.abs(host(g2) - r2)
+    assert np.all(e2 <= 2 * eps), e2.max() / eps
     ax, ay = d["ax"].astype(np.float64), d["ay"].astype(np.float64)
     ws = np.stack([d["wx"] * ax, d["wy"] * ay, d["wz"].astype(np.float64)], 1)
     zs = ws[:, 2] / np.linalg.norm(ws, axis=1)
     cz = 1.0 - r2 * (1.0 + zs)
     cxy = np.sqrt(np.maximum(0.0, 1.0 - cz * cz))
-    ok = cxy > 1e-3
-    assert np.all(_circ(host(g1)[ok], r1[ok]) <= 32 * eps / cxy[ok])
+    ok = cxy > 1e-6
+    e1 = _circ(host(g1)[ok], r1[ok])
+    print(f"inverse map: max |du2| {e2.max() / eps:.2f} eps, max |du1| {e1.max() / eps:.2f} eps, "
+          f"min |c_xy| checked {cxy[ok].min():.2e}")
+    assert np.all(e1 <= 4 * eps), e1.max() / eps
     assert np.all((host(g1) >= 0) & (host(g1) < 1) & (host(g2) >= 0) & (host(g2) < 1))
     # round trip through FP32 normals: error follows the conditioning of the
     # map u -> h; the bulk is at rounding level
@@ -297,7 +303,7 @@ def test_pdf_entry_point_at_grazing_normals():
 def test_inverse_and_pdf_full_size_sampled():
     """2^26 streaming tuples in the benchmark's launch configuration: the
     inverse map and vndf_pdf over all the GPU's normals, 2^16 sampled outputs
-    against the oracle at the same FP32 normals (pdf within 2e-6), range and
+    against the oracle at the same FP32 normals (rules as above), range and
     round-trip properties on all of them."""
     n = 1 << 26
     d = workloads.tuples_streaming(n, seed=1)
@@ -322,13 +328,13 @@ def test_inverse_and_pdf_full_size_sampled():
     r1, r2 = oracle.vndf_inverse((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
     eps = 2.0 ** -24
     G1, G2 = host(g1[it]), host(g2[it])
-    assert np.all(np.abs(G2 - r2) <= 32 * eps)
+    assert np.all(np.abs(G2 - r2) <= 2 * eps)
     ws = np.stack([sub["wx"] * sub["ax"], sub["wy"] * sub["ay"], sub["wz"]], 1)
     zs = ws[:, 2] / np.linalg.norm(ws, axis=1)
     cz = 1.0 - r2 * (1.0 + zs)
     cxy = np.sqrt(np.maximum(0.0, 1.0 - cz * cz))
-    ok = cxy > 1e-3
-    assert np.all(_circ(G1[ok], r1[ok]) <= 32 * eps / cxy[ok])
+    ok = cxy > 1e-6
+    assert np.all(_circ(G1[ok], r1[ok]) <= 4 * eps)
     ref = oracle.vndf_pdf((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
     w = np.stack([sub["wx"], sub["wy"], sub["wz"]], 1)
     w /= np.linalg.norm(w, axis=1, keepdims=True)
@@ -483,7 +489,7 @@ def test_more_than_one_launch_sampled():
                 assert np.all(rel <= 2e-6), rel.max()
                 r1, r2 = oracle.vndf_inverse((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"],
                                              sub["ay"])
-                assert np.all(np.abs(host(g2[it]) - r2) <= 32 * 2.0 ** -24)
+                assert np.all(np.abs(host(g2[it]) - r2) <= 2 * 2.0 ** -24)
                 del q, g1, g2
                 s1, s2 = cv.capvndf_uniforms(11, 2, 0, 0, n)
                 torch.cuda.synchronize()
