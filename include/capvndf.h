@@ -191,8 +191,11 @@ int32_t dielectric_sample(int64_t n, const float* wix, const float* wiy, const f
  * generalised half vector), normalised to the upper side,
  *   pdf = F(wi.h) VNDF(h) / (4 |wo.h|)                         (reflection),
  *   pdf = (1 - F(wi.h)) VNDF(h) eta^2 |wo.h| / (wi.h + eta wo.h)^2 (transmission).
- * 0 when wi.h <= 0, when a transmitted wo lies on the front side of h
- * (wo.h >= 0), for wo_z = 0 and outside the domain.
+ * 0 when wi.h <= 0, when a reflected wo lies behind h (wo.h <= 0) or a
+ * transmitted one in front of it (wo.h >= 0), for wo_z = 0 and outside the
+ * domain.  Evaluated in double precision at the given vectors as written
+ * (FP32 directions are unit only up to rounding): the result is the FP32
+ * rounding of that value up to a few ulps.
  *   n; wix,wiy,wiz [n]; wox,woy,woz [n]; ax, ay [n]; eta as above; pdf out [n].
  * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, BAD_ARG (eta), HIP.
  */

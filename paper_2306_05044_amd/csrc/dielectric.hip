@@ -195,40 +195,65 @@ __global__ __launch_bounds__(kBlock) void k_dielectric_scalar(
 // t = wi + wo (wo above: reflection) or t = -(wi + eta wo) (wo below:
 // transmission), h = t / |t| turned to the upper side.  With the VNDF of
 // Eq. (1) written as p_h = 2 (wi.h) / ((l + w_z) pi ax ay k^2), k = |M^T h|^2:
-//   reflection    pdf = F p_h / (4 wi.h) = F / (2 (l + w_z) pi ax ay k^2),
+//   reflection    pdf = F p_h / (4 |wo.h|) = F (wi.h / |wo.h|) / (2 (l + w_z) pi ax ay k^2),
 //   transmission  pdf = (1 - F) p_h eta^2 |wo.h| / |t|^2,
-// since (wi.h + eta wo.h)^2 = |t|^2.  Zero unless wi.h > 0 (and wo.h < 0 for
-// transmission), outside the domain, and for wo_z = 0.
-__device__ __forceinline__ float dielectric_pdf_one(float wx, float wy, float wz, float ox,
-                                                    float oy, float oz, float ax, float ay,
+// since (wi.h + eta wo.h)^2 = |t|^2 for any lengths of wi and wo.  For exactly
+// unit vectors wi.h = wo.h in reflection; FP32 inputs are unit only up to
+// rounding, which moves wi.h - wo.h by about 1e-7 / |t|, so the ratio is kept
+// and the density is the one of the definition at the given vectors.  Zero
+// unless wi.h > 0 (and wo.h > 0 for reflection, wo.h < 0 for transmission),
+// outside the domain, and for wo_z = 0.
+//
+// Evaluated in double precision:
+// the half vector t = +-(wi + k wo) (k = 1 reflection, eta transmission), the
+// cosines wi.h and wo.h and the Fresnel terms all cancel in FP32 near grazing
+// angles, the critical angle or wo ~ -wi; in double the same steps keep the
+// result at the FP32 rounding of the exact density up to a few ulps.  M^T h
+// is taken along (hx ay, hy ax, hz ax ay) to avoid divisions.  The kernel is
+// bound by HBM traffic, which hides the double arithmetic.
+__device__ __forceinline__ float dielectric_pdf_one(float wxf, float wyf, float wzf, float oxf,
+                                                    float oyf, float ozf, float axf, float ayf,
                                                     const Eta& e) {
-    const bool ok0 = (wz > 0.0f) && (ax > 0.0f) && (ay > 0.0f) && (oz != 0.0f);
+    const bool ok0 = (wzf > 0.0f) && (axf > 0.0f) && (ayf > 0.0f) && (ozf != 0.0f);
     if (!ok0) {
-        wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f; ox = 0.0f; oy = 0.0f; oz = 1.0f;
+        wxf = 0.0f; wyf = 0.0f; wzf = 1.0f; axf = 1.0f; ayf = 1.0f; oxf = 0.0f; oyf = 0.0f;
+        ozf = 1.0f;
     }
-    // t = sgn (wi + k wo): k = 1, sgn = 1 for reflection; k = eta, sgn = -1 for transmission
-    const bool refl = oz > 0.0f;
-    const float k = refl ? 1.0f : e.eta;
-    const float sgn = refl ? 1.0f : -1.0f;
-    const float tx = sgn * __builtin_fmaf(k, ox, wx);
-    const float ty = sgn * __builtin_fmaf(k, oy, wy);
-    const float tz = sgn * __builtin_fmaf(k, oz, wz);
-    const float t2 = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, tz * tz));
-    const float it = copysignf(rsq(t2), tz);
-    const float hx = tx * it, hy = ty * it, hz = tz * it;
-    const float ci = __builtin_fmaf(wx, hx, __builtin_fmaf(wy, hy, wz * hz));
-    const float co = __builtin_fmaf(ox, hx, __builtin_fmaf(oy, hy, oz * hz));
-    float g;
-    const float f = fresnel(ci, e, g);
-    const float px = ax * wx, py = ay * wy;
-    const float l = fsqrt(__builtin_fmaf(px, px, __builtin_fmaf(py, py, wz * wz)));
-    const float sx = hx * rcp(ax), sy = hy * rcp(ay);
-    const float kk = __builtin_fmaf(sx, sx, __builtin_fmaf(sy, sy, hz * hz));
-    const float base = kInvPi * rcp((l + wz) * ax * ay * kk * kk);
-    const float p = refl ? 0.5f * f * base
-                         : (1.0f - f) * 2.0f * ci * base * e.eta2 * fabsf(co) * rcp(t2);
-    const bool valid = ok0 && ci > 0.0f && hz > 0.0f && (refl || co < 0.0f);
-    return valid ? p : 0.0f;
+    const double wx = wxf, wy = wyf, wz = wzf, ox = oxf, oy = oyf, oz = ozf;
+    const double ax = axf, ay = ayf;
+    const bool refl = ozf > 0.0f;
+    const double eta = e.eta;
+    const double k = refl ? 1.0 : eta;
+    const double sgn = refl ? 1.0 : -1.0;
+    const double tx = sgn * __builtin_fma(k, ox, wx);
+    const double ty = sgn * __builtin_fma(k, oy, wy);
+    const double tz = sgn * __builtin_fma(k, oz, wz);
+    const double t2 = __builtin_fma(tx, tx, __builtin_fma(ty, ty, tz * tz));
+    const double it = __builtin_copysign(rsq_f64(t2), tz);
+    const double hx = tx * it, hy = ty * it, hz = tz * it;
+    const double ci = __builtin_fma(wx, hx, __builtin_fma(wy, hy, wz * hz));
+    const double co = __builtin_fma(ox, hx, __builtin_fma(oy, hy, oz * hz));
+    // Fresnel (as fresnel() above) with g = sqrt(eta^2 - 1 + ci^2)
+    const double g2 = __builtin_fma(ci, ci, __builtin_fma(eta, eta, -1.0));
+    const double g = g2 > 0.0 ? g2 * rsq_f64(g2) : 0.0;
+    const double rs = (ci - g) * rcp_f64(ci + g);
+    const double ec = eta * eta * ci;
+    const double rp = (ec - g) * rcp_f64(ec + g);
+    const double f = g2 > 0.0 ? 0.5 * __builtin_fma(rs, rs, rp * rp) : 1.0;
+    const double px = ax * wx, py = ay * wy;
+    const double l2 = __builtin_fma(px, px, __builtin_fma(py, py, wz * wz));
+    const double l = l2 * rsq_f64(l2);
+    const double axy = ax * ay;
+    const double kx = hx * ay, ky = hy * ax, kz = hz * axy;
+    const double K = __builtin_fma(kx, kx, __builtin_fma(ky, ky, kz * kz));
+    // the VNDF density at h (Eq. (1)) times 1 / (2 ci): pi ax ay k^2 = pi K^2 / (ax ay)^3
+    const double base = (axy * axy * axy) * rcp_f64((l + wz) * kPiD * K * K);
+    const bool side = refl ? co > 0.0 : co < 0.0;
+    const double p = refl ? 0.5 * f * base * ci * rcp_f64(side ? co : 1.0)
+                          : (1.0 - f) * 2.0 * ci * base * (eta * eta) * __builtin_fabs(co) *
+                                rcp_f64(t2);
+    const bool valid = ok0 && ci > 0.0 && hz > 0.0 && side;
+    return valid ? (float)p : 0.0f;
 }
 
 template <int G>

@@ -104,7 +104,7 @@ def _compare(d, outs, eta, u, name):
     """outs: GPU (wox, woy, woz, pdf, weight) as tensors or arrays; u: the
     stream's uniforms at the same tuples."""
     wi = (d["wx"], d["wy"], d["wz"])
-    ref = oracle.dielectric_sample(wi, d["ax"], d["ay"], eta, u=u)
+    ref = oracle.dielectric_sample(wi, d["ax"], d["ay"], float(np.float32(eta)), u=u)
     outs = [host(x) if torch.is_tensor(x) else x for x in outs]
     wo = np.stack([x.astype(np.float64) for x in outs[:3]], 1)
     pdf = outs[3].astype(np.float64)
@@ -200,31 +200,25 @@ def test_domain_edges_and_total_reflection():
 
 def _check_pdf_entry(W, O, ax, ay, eta, got, name):
     """dielectric_pdf output `got` at FP32 directions W (wi) and O (wo) vs the
-    oracle at the same values.  Conditioning: the half vector t = wi + wo or
-    -(wi + eta wo) loses 2^-24 / |t| relatively, and wi.h, which sets F,
-    cancels near grazing."""
-    ref, _ = oracle.dielectric_eval(W, O, ax, ay, eta)
+    oracle at the same values and the same (FP32) eta.  The entry point works
+    in double, so every density is within 2e-6 relative; a zero on one side
+    only is allowed where a validity test (wi.h > 0, wo.h < 0 for
+    transmission) sits within 1e-12 of its threshold."""
+    eta32 = float(np.float32(eta))
+    ref, _ = oracle.dielectric_eval(W, O, ax, ay, eta32)
     Wm, Om = np.stack(W, 1), np.stack(O, 1)
     refl = Om[:, 2] > 0
-    tv = np.where(refl[:, None], Wm + Om, -(Wm + eta * Om))
-    tn = np.linalg.norm(tv, axis=1)
-    hh = tv * (np.sign(tv[:, 2]) / tn)[:, None]
+    tv = np.where(refl[:, None], Wm + Om, -(Wm + eta32 * Om))
+    hh = tv * (np.sign(tv[:, 2]) / np.linalg.norm(tv, axis=1))[:, None]
     ci = np.einsum("ij,ij->i", Wm, hh)
-    co = np.abs(np.einsum("ij,ij->i", Om, hh))
-    g = np.sqrt(np.maximum(eta * eta - 1 + ci * ci, 0.0))
-    fp = np.abs(_fresnel_slope(np.clip(ci, 0, 1), eta))
-    f = oracle.fresnel_dielectric(np.clip(ci, 0, 1), eta)
-    sel = np.where(refl, f, 1 - f)
-    K = (4.0 / tn + 2.0 / np.maximum(ci, 1e-30) + 2.0 / np.maximum(co, 1e-30)
-         + fp / np.maximum(sel, 1e-30) / np.maximum(ci, 1e-30)
-         + np.where(refl, 0.0, ci / np.maximum(g * g, 1e-30)))
+    co = np.einsum("ij,ij->i", Om, hh)
+    edge = (np.abs(ci) < 1e-12) | (~refl & (np.abs(co) < 1e-12))
     both = (ref > 0) & (got > 0)
-    # a zero on exactly one side only where the validity tests are within rounding
     one = (ref > 0) != (got > 0)
-    assert np.all(K[one] > 1e4) or not one.any(), one.sum()
-    rel = np.zeros(len(got))
-    rel[both] = np.abs(got[both] / ref[both] - 1)
-    _check(rel, K, 128, name, both)
+    assert not (one & ~edge).any(), (one & ~edge).sum()
+    rel = np.abs(got[both] / ref[both] - 1)
+    print(f"{name}: {both.sum()} densities, max rel {rel.max():.2e}")
+    assert np.all(rel <= 2e-6), rel.max()
 
 
 def test_pdf_entry_point():
