@@ -145,24 +145,61 @@ def cpu_baseline(d):
 
 def oracle_checks(checks):
     """The CPU leg's second part: the FP64 oracle at the cells whose GPU values
-    the estimator sections kept (same Philox streams), max |GPU - oracle|."""
+    the estimator sections kept (same Philox streams): max |GPU - oracle| and
+    the oracle's own throughput there (one host thread per cell)."""
     import numpy as np
     import oracle
     errs = {}
+    threads = min(os.cpu_count() or 1, 16)
     if "albedo_lut" in checks:
         c = checks["albedo_lut"]
         g = c["grid"]
         wo = (g["wx"], g["wy"], g["wz"])
-        a1 = oracle.albedo(wo, g["ax"], g["ay"], c["n"], 2, f0=1.0, units=c["cells"])
-        a5 = oracle.albedo(wo, g["ax"], g["ay"], c["n"], 2, f0=0.0, units=c["cells"])
-        errs["albedo_lut"] = max(np.abs(c["s1"] - a1).max(), np.abs(c["s5"] - a5).max(),
-                                 np.abs(c["a004"] - (0.04 * a1 + 0.96 * a5)).max())
+        t0 = time.perf_counter()
+        a1 = oracle.albedo(wo, g["ax"], g["ay"], c["n"], 2, f0=1.0, units=c["cells"],
+                           nthreads=threads)
+        dt = time.perf_counter() - t0
+        a5 = oracle.albedo(wo, g["ax"], g["ay"], c["n"], 2, f0=0.0, units=c["cells"],
+                           nthreads=threads)
+        err = max(np.abs(c["s1"] - a1).max(), np.abs(c["s5"] - a5).max(),
+                  np.abs(c["a004"] - (0.04 * a1 + 0.96 * a5)).max())
+        ns = len(c["cells"]) * c["n"]
+        errs["albedo_lut"] = {
+            "max_abs_err_vs_oracle": float(f"{err:.3e}"), "err_checked_cells": len(c["cells"]),
+            "oracle": {"gsamples_per_s": round(ns / dt / 1e9, 6),
+                       "cores": min(threads, len(c["cells"])),
+                       "kind": "oracle", "sample": f"{len(c['cells'])} cells x {c['n']} "
+                       f"samples, FP64 estimator, one Fresnel sum ({dt:.2f} s)"}}
+    for key in ("albedo_grad", "batched"):
+        if key not in checks:
+            continue
+        c = checks[key]
+        t0 = time.perf_counter()
+        ref = oracle.albedo_grad(c["wo"], c["ax"], c["ay"], c["n"], c["seed"], f0=1.0,
+                                 units=c["units"], nthreads=threads)
+        dt = time.perf_counter() - t0
+        got = c["got"]
+        e_val = float(np.abs(got[0] - ref[0]).max())
+        ratio = max(float((np.abs(g_ - r_) / (1e-4 + 1e-3 * np.abs(r_))).max())
+                    for g_, r_ in zip(got[1:], ref[1:]))
+        ns = int(np.sum(np.broadcast_to(c["n"], (len(c["cells"]),))))
+        errs[key] = {
+            "max_abs_err_vs_oracle": float(f"{e_val:.3e}"),
+            "max_grad_err_over_tolerance": round(ratio, 4),
+            "grad_tolerance": "1e-4 + 1e-3 |g| against the oracle's dual-number gradient",
+            "err_checked_cells": len(c["cells"]),
+            "oracle": {"gsamples_per_s": round(ns / dt / 1e9, 6),
+                       "cores": min(threads, len(c["cells"])),
+                       "kind": "oracle", "sample": f"{len(c['cells'])} cells, {ns} samples, "
+                       f"FP64 value + dual-number gradient ({dt:.2f} s)"}}
     if "direct_illumination" in checks:
         c = checks["direct_illumination"]
         g = c["grid"]
         ref = oracle.radiance((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], c["n"], 2,
                               c["lobes"].astype(np.float64), units=c["cells"])
-        errs["direct_illumination"] = np.abs(c["value"] - ref).max()
+        errs["direct_illumination"] = {
+            "max_abs_err_vs_oracle": float(f"{np.abs(c['value'] - ref).max():.3e}"),
+            "err_checked_cells": len(c["cells"])}
     return errs
 
 
@@ -315,7 +352,7 @@ def main():
         s1, s5 = fwd()
         a004 = fused()[0]
         torch.cuda.synchronize()
-        cells = np.array([0, 1000, 2047, 3333, 4095])
+        cells = np.linspace(0, 4095, 16).astype(np.int64)
         checks["albedo_lut"] = {"grid": {k: v[cells] for k, v in g.items()}, "cells": cells,
                                 "n": n, "s1": s1.cpu().numpy()[cells],
                                 "s5": s5.cpu().numpy()[cells],
@@ -351,6 +388,21 @@ def main():
                                           1 << 18, 3), max(3, args.steps // 10), 2)
         out["albedo_grad"] = {"cells": 1024, "samples_per_cell": 1 << 18,
                               "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4)}
+        # one clean pass for the oracle comparison in the CPU leg
+        for p_ in (ax, ay, th):
+            p_.grad = None
+        a = cv.albedo(ax, ay, th, ph, f0, 1 << 18, 3)
+        a.sum().backward()
+        with torch.no_grad():
+            st = torch.sin(th)
+            wo = (st * torch.cos(ph), st * torch.sin(ph), torch.cos(th))
+        torch.cuda.synchronize()
+        cells = np.linspace(0, 1023, 16).astype(np.int64)
+        checks["albedo_grad"] = {
+            "wo": tuple(x.detach().cpu().numpy()[cells] for x in wo),
+            "ax": gg["ax"][cells], "ay": gg["ay"][cells], "n": 1 << 18, "seed": 3,
+            "cells": cells, "units": cells,
+            "got": [x.detach().cpu().numpy()[cells] for x in (a, ax.grad, ay.grad, th.grad)]}
     if "batch" in only:
         log("batched estimator: 4096 uneven jobs, forward + adjoint (autotuned tiling)")
         j = workloads.batch_jobs(4096, seed=4)
@@ -374,6 +426,13 @@ def main():
         ref = [o.clone() for o in (plan.albedo, plan.grad_ax)]
         ms_r, _ = timed(plan.run_per_request, max(2, steps // 2), 1)
         dev_a = (plan.albedo - ref[0]).abs().max().item()
+        jobs = np.sort(np.random.default_rng(0).choice(np.flatnonzero(j["n"] <= 1 << 18), 16,
+                                                       replace=False))
+        checks["batched"] = {
+            "wo": tuple(j[k][jobs] for k in ("wx", "wy", "wz")), "ax": j["ax"][jobs],
+            "ay": j["ay"][jobs], "n": j["n"][jobs], "seed": 4, "cells": jobs, "units": jobs,
+            "got": [x.cpu().numpy()[jobs] for x in (plan.albedo, plan.grad_ax, plan.grad_ay,
+                                                    plan.grad_theta_o)]}
         # The plain-sampler pipeline per request: fill the job's view and
         # roughness into reusable arrays, draw its uniforms (the estimator's
         # stream, so the samples are the batch's), run vndf_sample.  Such a
@@ -496,9 +555,8 @@ def main():
             result["cpu_baseline"] = cpu_baseline(d)
         if checks:
             log("checking the estimators at sampled cells against the FP64 oracle")
-            for key, err in oracle_checks(checks).items():
-                result[key]["max_abs_err_vs_oracle"] = float(f"{err:.3e}")
-                result[key]["err_checked_cells"] = int(len(checks[key]["cells"]))
+            for key, res in oracle_checks(checks).items():
+                result[key].update(res)
     print(json.dumps(result), flush=True)
 
 
