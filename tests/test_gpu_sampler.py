@@ -570,3 +570,33 @@ def test_f64_full_size_every_sample():
     del out
     h_ref, p_ref = oracle.vndf_sample((d["wx"], d["wy"], d["wz"]), d["ax"], d["ay"], seed=1)
     _flat(H, P, h_ref, p_ref, "f64 2^26 all samples")
+
+
+def test_evaluation_entry_points_vector_and_scalar_paths_agree():
+    """vndf_pdf, vndf_inverse and dielectric_pdf give the same bits on aligned
+    arrays (vector path) and on copies offset by one element (scalar path),
+    ragged tail included."""
+    n = 4096 + 7
+    d = workloads.tuples_streaming(n, seed=41)
+    t = to_dev(d)
+    hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=5)
+    ox, oy, oz, _, _ = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5,
+                                            seed=5)
+    arrs = {"wx": t["wx"], "wy": t["wy"], "wz": t["wz"], "hx": hx, "hy": hy, "hz": hz,
+            "ox": ox, "oy": oy, "oz": oz, "ax": t["ax"], "ay": t["ay"]}
+    mis = {}
+    for k, v in arrs.items():
+        buf = torch.zeros(n + 1, device="cuda")
+        buf[1:].copy_(v)
+        mis[k] = buf[1:]
+
+    def run(a):
+        p = cv.vndf_pdf(a["wx"], a["wy"], a["wz"], a["hx"], a["hy"], a["hz"], a["ax"], a["ay"])
+        u = cv.vndf_inverse(a["wx"], a["wy"], a["wz"], a["hx"], a["hy"], a["hz"], a["ax"],
+                            a["ay"])
+        q = cv.dielectric_pdf(a["wx"], a["wy"], a["wz"], a["ox"], a["oy"], a["oz"], a["ax"],
+                              a["ay"], 1.5)
+        return (p,) + tuple(u) + (q,)
+
+    for x, y in zip(run(arrs), run(mis)):
+        assert torch.equal(x, y)
