@@ -24,7 +24,11 @@ namespace {
 // (3 % faster than a non-temporal store).
 constexpr int kSampleGroups = 2;
 constexpr int kSampleBlock = 256;  // 3 % faster than 128 threads for this kernel
-constexpr int kPdfGroups = 1;
+#ifndef CAPVNDF_DIELECTRIC_PDF_GROUPS
+#define CAPVNDF_DIELECTRIC_PDF_GROUPS 1
+#endif
+constexpr int kPdfGroups = CAPVNDF_DIELECTRIC_PDF_GROUPS;
+constexpr int kPdfBlock = 128;  // 256 threads: 4 % slower for this kernel
 
 // Random numbers of the dielectric sampler: one Philox block per tuple,
 // counter (lo32(k), 0, 5, hi32(k)) with k = index_base + i, key (lo32(seed),
@@ -256,25 +260,25 @@ __device__ __forceinline__ float dielectric_pdf_one(float wxf, float wyf, float 
     return valid ? (float)p : 0.0f;
 }
 
-template <int G>
-__global__ __launch_bounds__(kBlock) void k_dielectric_pdf_v4(
+template <int G, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_dielectric_pdf_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
     const float* __restrict__ wiz, const float* __restrict__ woxp, const float* __restrict__ woyp,
     const float* __restrict__ wozp, const float* __restrict__ ax, const float* __restrict__ ay,
     Eta e, float* __restrict__ pdf) {
-    const int64_t tile = (int64_t)blockIdx.x * kBlock * 4 * G;
+    const int64_t tile = (int64_t)blockIdx.x * BLOCK * 4 * G;
     f4 x[G], y[G], z[G], ox[G], oy[G], oz[G], a[G], b[G];
-    load_groups(x, wix, tile, n);
-    load_groups(y, wiy, tile, n);
-    load_groups(z, wiz, tile, n);
-    load_groups(ox, woxp, tile, n);
-    load_groups(oy, woyp, tile, n);
-    load_groups(oz, wozp, tile, n);
-    load_groups(a, ax, tile, n);
-    load_groups(b, ay, tile, n);
+    load_groups<G, BLOCK, true>(x, wix, tile, n);
+    load_groups<G, BLOCK, true>(y, wiy, tile, n);
+    load_groups<G, BLOCK, true>(z, wiz, tile, n);
+    load_groups<G, BLOCK, true>(ox, woxp, tile, n);
+    load_groups<G, BLOCK, true>(oy, woyp, tile, n);
+    load_groups<G, BLOCK, true>(oz, wozp, tile, n);
+    load_groups<G, BLOCK, true>(a, ax, tile, n);
+    load_groups<G, BLOCK, true>(b, ay, tile, n);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t i0 = group_start<G>(tile, g);
+        const int64_t i0 = group_start<G, BLOCK, true>(tile, g);
         if (i0 + 4 <= n) {
             f4 o;
 #pragma unroll
@@ -395,9 +399,10 @@ extern "C" int32_t dielectric_pdf(int64_t n, const float* wix, const float* wiy,
     for (int64_t o = 0; o < n; o += kSliceElems) {
         const int64_t m = slice_len(n, o);
         if (vec)
-            hipLaunchKernelGGL(k_dielectric_pdf_v4<kPdfGroups>, dim3(tiles_for<kPdfGroups>(m)),
-                               dim3(kBlock), 0, st, m, wix + o, wiy + o, wiz + o, wox + o, woy + o,
-                               woz + o, ax + o, ay + o, e, pdf + o);
+            hipLaunchKernelGGL((k_dielectric_pdf_v4<kPdfGroups, kPdfBlock>),
+                               dim3(tiles_for<kPdfGroups, kPdfBlock>(m)), dim3(kPdfBlock), 0, st,
+                               m, wix + o, wiy + o, wiz + o, wox + o, woy + o, woz + o, ax + o,
+                               ay + o, e, pdf + o);
         else
             hipLaunchKernelGGL(k_dielectric_pdf_scalar, dim3(grid_for(m)), dim3(kBlock), 0, st, m,
                                wix + o, wiy + o, wiz + o, wox + o, woy + o, woz + o, ax + o,

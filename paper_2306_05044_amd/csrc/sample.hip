@@ -14,10 +14,11 @@ namespace {
 
 // Launch shapes of the evaluation kernels, whose outputs are small next to
 // their inputs (pdf: 32 B in, 4 B out; inverse map: 32 B in, 8 B out): vec4
-// groups per lane and whether the outputs go through the cache.  Measured at
-// 2^26: a cached pdf store is 4 % faster than a non-temporal one, while the
-// inverse map's two outputs are 6 % faster non-temporal; the group count
-// does not matter for either.
+// groups per lane, threads per block (wavefront tiles) and whether the
+// outputs go through the cache.  Measured at 2^26: a cached pdf store is 4 %
+// faster than a non-temporal one, while the inverse map's two outputs are
+// 6 % faster non-temporal; 256-thread blocks beat 128 by 3 % (pdf) and 4 %
+// (inverse); lane-interleaved groups were no better.
 #ifndef CAPVNDF_PDF_GROUPS
 #define CAPVNDF_PDF_GROUPS 4
 #endif
@@ -37,6 +38,14 @@ namespace {
 #define CAPVNDF_F64_GROUPS 1
 #endif
 constexpr int kF64Groups = CAPVNDF_F64_GROUPS;
+#ifndef CAPVNDF_PDF_BLOCK
+#define CAPVNDF_PDF_BLOCK 256
+#endif
+#ifndef CAPVNDF_INVERSE_BLOCK
+#define CAPVNDF_INVERSE_BLOCK 256
+#endif
+constexpr int kPdfBlock = CAPVNDF_PDF_BLOCK;
+constexpr int kInverseBlock = CAPVNDF_INVERSE_BLOCK;
 constexpr int kPdfGroups = CAPVNDF_PDF_GROUPS;
 constexpr bool kPdfCached = CAPVNDF_PDF_CACHED != 0;
 constexpr int kInverseGroups = CAPVNDF_INVERSE_GROUPS;
@@ -213,25 +222,25 @@ __device__ __forceinline__ float pdf_one(float wxf, float wyf, float wzf, float 
     return (ok0 && d > 0.0) ? (float)p : 0.0f;
 }
 
-template <int G, bool CACHED_OUT>
-__global__ __launch_bounds__(kBlock) void k_pdf_v4(
+template <int G, bool CACHED_OUT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_pdf_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
     const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
     const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
     float* __restrict__ pdf) {
-    const int64_t tile = (int64_t)blockIdx.x * kBlock * 4 * G;
+    const int64_t tile = (int64_t)blockIdx.x * BLOCK * 4 * G;
     f4 x[G], y[G], z[G], hx[G], hy[G], hz[G], a[G], b[G];
-    load_groups(x, wix, tile, n);
-    load_groups(y, wiy, tile, n);
-    load_groups(z, wiz, tile, n);
-    load_groups(hx, hxp, tile, n);
-    load_groups(hy, hyp, tile, n);
-    load_groups(hz, hzp, tile, n);
-    load_groups(a, ax, tile, n);
-    load_groups(b, ay, tile, n);
+    load_groups<G, BLOCK, true>(x, wix, tile, n);
+    load_groups<G, BLOCK, true>(y, wiy, tile, n);
+    load_groups<G, BLOCK, true>(z, wiz, tile, n);
+    load_groups<G, BLOCK, true>(hx, hxp, tile, n);
+    load_groups<G, BLOCK, true>(hy, hyp, tile, n);
+    load_groups<G, BLOCK, true>(hz, hzp, tile, n);
+    load_groups<G, BLOCK, true>(a, ax, tile, n);
+    load_groups<G, BLOCK, true>(b, ay, tile, n);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t i0 = group_start<G>(tile, g);
+        const int64_t i0 = group_start<G, BLOCK, true>(tile, g);
         if (i0 + 4 <= n) {
             f4 o;
 #pragma unroll
@@ -297,25 +306,25 @@ __device__ __forceinline__ void inverse_one(float wxf, float wyf, float wzf, flo
     u2 = ok ? fminf(fmaxf(v2, 0.0f), 0x1.fffffep-1f) : -1.0f;
 }
 
-template <int G, bool CACHED_OUT>
-__global__ __launch_bounds__(kBlock) void k_inverse_v4(
+template <int G, bool CACHED_OUT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_inverse_v4(
     int64_t n, const float* __restrict__ wix, const float* __restrict__ wiy,
     const float* __restrict__ wiz, const float* __restrict__ hxp, const float* __restrict__ hyp,
     const float* __restrict__ hzp, const float* __restrict__ ax, const float* __restrict__ ay,
     float* __restrict__ u1p, float* __restrict__ u2p) {
-    const int64_t tile = (int64_t)blockIdx.x * kBlock * 4 * G;
+    const int64_t tile = (int64_t)blockIdx.x * BLOCK * 4 * G;
     f4 x[G], y[G], z[G], hx[G], hy[G], hz[G], a[G], b[G];
-    load_groups(x, wix, tile, n);
-    load_groups(y, wiy, tile, n);
-    load_groups(z, wiz, tile, n);
-    load_groups(hx, hxp, tile, n);
-    load_groups(hy, hyp, tile, n);
-    load_groups(hz, hzp, tile, n);
-    load_groups(a, ax, tile, n);
-    load_groups(b, ay, tile, n);
+    load_groups<G, BLOCK, true>(x, wix, tile, n);
+    load_groups<G, BLOCK, true>(y, wiy, tile, n);
+    load_groups<G, BLOCK, true>(z, wiz, tile, n);
+    load_groups<G, BLOCK, true>(hx, hxp, tile, n);
+    load_groups<G, BLOCK, true>(hy, hyp, tile, n);
+    load_groups<G, BLOCK, true>(hz, hzp, tile, n);
+    load_groups<G, BLOCK, true>(a, ax, tile, n);
+    load_groups<G, BLOCK, true>(b, ay, tile, n);
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t i0 = group_start<G>(tile, g);
+        const int64_t i0 = group_start<G, BLOCK, true>(tile, g);
         if (i0 + 4 <= n) {
             f4 o1, o2;
 #pragma unroll
@@ -568,8 +577,8 @@ extern "C" int32_t vndf_pdf(int64_t n, const float* wix, const float* wiy, const
     for (int64_t o = 0; o < n; o += kSliceElems) {
         const int64_t m = slice_len(n, o);
         if (vec)
-            hipLaunchKernelGGL((k_pdf_v4<kPdfGroups, kPdfCached>), dim3(tiles_for<kPdfGroups>(m)),
-                               dim3(kBlock), 0, st, m, wix + o, wiy + o, wiz + o, hx + o, hy + o,
+            hipLaunchKernelGGL((k_pdf_v4<kPdfGroups, kPdfCached, kPdfBlock>),
+                               dim3(tiles_for<kPdfGroups, kPdfBlock>(m)), dim3(kPdfBlock), 0, st, m, wix + o, wiy + o, wiz + o, hx + o, hy + o,
                                hz + o, ax + o, ay + o, pdf + o);
         else
             hipLaunchKernelGGL(k_pdf_scalar, dim3(grid_for(m)), dim3(kBlock), 0, st, m, wix + o,
@@ -595,8 +604,10 @@ extern "C" int32_t vndf_inverse(int64_t n, const float* wix, const float* wiy, c
     for (int64_t o = 0; o < n; o += kSliceElems) {
         const int64_t m = slice_len(n, o);
         if (vec)
-            hipLaunchKernelGGL((k_inverse_v4<kInverseGroups, kInverseCached>),
-                               dim3(tiles_for<kInverseGroups>(m)), dim3(kBlock), 0, st, m, wix + o,
+            hipLaunchKernelGGL((k_inverse_v4<kInverseGroups, kInverseCached, kInverseBlock>),
+                               dim3(tiles_for<kInverseGroups, kInverseBlock>(m)),
+                               dim3(kInverseBlock), 0,
+                               st, m, wix + o,
                                wiy + o, wiz + o, hx + o, hy + o, hz + o, ax + o, ay + o, u1 + o,
                                u2 + o);
         else

@@ -36,6 +36,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 #ifndef CAPVNDF_STREAM_WAVE_TILES
 #define CAPVNDF_STREAM_WAVE_TILES 1
 #endif
+
 constexpr int kBlock = CAPVNDF_STREAM_BLOCK;
 constexpr bool kWaveTiles = CAPVNDF_STREAM_WAVE_TILES != 0;
 constexpr int kGroups = CAPVNDF_STREAM_GROUPS;
@@ -54,9 +55,9 @@ __device__ __forceinline__ void store4(float* p, f4 v) {
 
 // First element of group g of this lane in the tile starting at `tile` (a
 // tile holds kBlock * 4 * G elements; the groups of all lanes partition it).
-template <int G, int BLOCK = kBlock>
+template <int G, int BLOCK = kBlock, bool WT = kWaveTiles>
 __device__ __forceinline__ int64_t group_start(int64_t tile, int g) {
-    if (kWaveTiles) {
+    if (WT) {
         const int64_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         return tile + wave * 256 * G + ((int64_t)g * 64 + lane) * 4;
     }
@@ -66,12 +67,12 @@ __device__ __forceinline__ int64_t group_start(int64_t tile, int g) {
 // Load the G groups of this lane from one array (the vector path's loads are
 // issued array by array; groups past n are left unset, and the kernels finish
 // them one element at a time).
-template <int G, int BLOCK = kBlock>
+template <int G, int BLOCK = kBlock, bool WT = kWaveTiles>
 __device__ __forceinline__ void load_groups(f4 (&dst)[G], const float* __restrict__ src,
                                             int64_t tile, int64_t n) {
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-        const int64_t i0 = group_start<G, BLOCK>(tile, g);
+        const int64_t i0 = group_start<G, BLOCK, WT>(tile, g);
         if (i0 + 4 <= n) dst[g] = load4(src + i0);
     }
 }
