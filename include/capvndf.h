@@ -423,7 +423,8 @@ int32_t capvndf_philox_blocks(int64_t n, const uint32_t* ctr, uint32_t key0, uin
  * sampler called 64 times per lane): each of `lanes` lanes draws its view
  * direction and roughness once, then calls the sampler `iters` times on
  * cheap low-discrepancy uniforms and a view elevation that changes every call,
- * folding h into one word written to out[lane] (device, [lanes]).
+ * folding h into one word written to out[lane] (device, [lanes]).  method:
+ * CAPVNDF_CAP, CAPVNDF_DISK2018 or CAPVNDF_CAP_F64; lanes <= 2^31.
  */
 int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters, uint64_t seed,
                         uint32_t* out, void* stream);

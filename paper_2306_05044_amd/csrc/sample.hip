@@ -653,7 +653,7 @@ extern "C" int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters,
                                    uint32_t* out, void* stream) {
     if (lanes < 0 || lanes > kSliceElems || iters < 0)
         return fail(CAPVNDF_ERR_BAD_SIZE, "vndf_microbench: lanes must be in [0, 2^31], iters >= 0");
-    if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018)
+    if (method != CAPVNDF_CAP && method != CAPVNDF_DISK2018 && method != CAPVNDF_CAP_F64)
         return fail(CAPVNDF_ERR_BAD_METHOD, "vndf_microbench: unknown method %d", method);
     if (lanes == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(out, "out")) return rc;
@@ -661,6 +661,9 @@ extern "C" int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters,
     if (method == CAPVNDF_CAP)
         hipLaunchKernelGGL(k_microbench<CAPVNDF_CAP>, dim3(grid_for(lanes)), dim3(kBlock), 0, st,
                            lanes, iters, key_lo(seed), key_hi(seed), out);
+    else if (method == CAPVNDF_CAP_F64)
+        hipLaunchKernelGGL(k_microbench<CAPVNDF_CAP_F64>, dim3(grid_for(lanes)), dim3(kBlock), 0,
+                           st, lanes, iters, key_lo(seed), key_hi(seed), out);
     else
         hipLaunchKernelGGL(k_microbench<CAPVNDF_DISK2018>, dim3(grid_for(lanes)), dim3(kBlock), 0,
                            st, lanes, iters, key_lo(seed), key_hi(seed), out);
