@@ -453,15 +453,19 @@ inline int64_t lut_chunks_per_cell(int64_t nsamples) {
     return c == 0 ? 1 : (int64_t)c;
 }
 
+// Size and pointer checks of the per-cell estimators.  lut_grid: the call
+// launches one kLutBlock block per chunk of each cell (the table estimators,
+// not the batch plans, whose persistent grid is small).
 int32_t check_cells(const char* fn, int64_t ncells, int64_t nsamples, const float* wox,
-                    const float* woy, const float* woz, const float* ax, const float* ay) {
+                    const float* woy, const float* woz, const float* ax, const float* ay,
+                    bool lut_grid = true) {
     if (ncells < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells < 0", fn);
     if (nsamples < 0 || nsamples >= ((int64_t)1 << 40))
         return fail(CAPVNDF_ERR_BAD_SIZE, "%s: nsamples must be in [0, 2^40)", fn);
     // one block of kLutBlock work-items per chunk; a dispatch counts its
     // work-items in 32 bits
-    if (ncells > 0 && (double)ncells * (double)lut_chunks_per_cell(nsamples) * kLutBlock >
-                          4294967295.0)
+    if (lut_grid && ncells > 0 &&
+        (double)ncells * (double)lut_chunks_per_cell(nsamples) * kLutBlock > 4294967295.0)
         return fail(CAPVNDF_ERR_BAD_SIZE,
                     "%s: ncells * chunks per cell (%lld * %lld) must be below 2^24 (chunks of "
                     "%llu samples); split the cells over several calls", fn, (long long)ncells,
@@ -810,7 +814,8 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
         return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_batch_plan_create: njobs must be in [1, 2^31 - 2]");
     if (nsamples_host == nullptr)
         return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_plan_create: nsamples_host is NULL");
-    if (int32_t rc = check_cells("albedo_batch_plan_create", njobs, 0, wox, woy, woz, ax, ay))
+    if (int32_t rc =
+            check_cells("albedo_batch_plan_create", njobs, 0, wox, woy, woz, ax, ay, false))
         return rc;
     if (int32_t rc = check_array(albedo, "albedo")) return rc;
     if (f0 != nullptr)
@@ -852,8 +857,21 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     // Chunk table: job-major, pair ranges of chunk_pairs (one block's or, per
     // wave, one wavefront's lanes times pairs_per_thread).
     const int64_t chunk_pairs = (int64_t)(t.per_wave ? 64 : t.block) * t.pairs_per_thread;
+    // count first: chunk indices are int32 on the device, and the tables are
+    // sized exactly (no growth while they are built)
+    int64_t count = 0;
+    for (int64_t j = 0; j < njobs; ++j)
+        count += ((nsamples_host[j] + 1) / 2 + chunk_pairs - 1) / chunk_pairs;
+    if (count > (int64_t)0x7ffffffe)
+        return fail(CAPVNDF_ERR_BAD_SIZE,
+                    "albedo_batch_plan_create: %lld chunks of %lld sample pairs exceed 2^31 - 2; "
+                    "raise pairs_per_thread or split the jobs over several plans",
+                    (long long)count, (long long)chunk_pairs);
     std::vector<int32_t> chunk_job;
     std::vector<int64_t> pbeg, pend;
+    chunk_job.reserve((size_t)count);
+    pbeg.reserve((size_t)count);
+    pend.reserve((size_t)count);
     std::vector<int32_t> job_chunks((size_t)njobs + 1, 0);
     for (int64_t j = 0; j < njobs; ++j) {
         job_chunks[j] = (int32_t)chunk_job.size();
@@ -862,8 +880,6 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
             chunk_job.push_back((int32_t)j);
             pbeg.push_back(b);
             pend.push_back(std::min(b + chunk_pairs, np));
-            if (chunk_job.size() > (size_t)0x7fffffff)
-                return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_batch_plan_create: too many chunks");
         }
     }
     job_chunks[njobs] = (int32_t)chunk_job.size();

@@ -181,3 +181,15 @@ def test_single_job(n_samples, tiling):
     _check(plan, j, 1.0, True)
     assert plan.info()["total_samples"] == n_samples
     plan.close()
+
+
+def test_too_many_chunks_is_refused_before_building():
+    """2048 jobs of 2^40 - 1 samples in chunks of 512 pairs are 2^41 chunks:
+    refused with a message before any table is built (no host blow-up)."""
+    n = 2048
+    t = {k: torch.full((n,), v, device="cuda") for k, v in
+         (("wx", 0.0), ("wy", 0.0), ("wz", 1.0), ("ax", 0.5), ("ay", 0.5))}
+    with pytest.raises(cv.CapvndfError) as e:
+        cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                     np.full(n, (1 << 40) - 1, dtype=np.int64), 4, tiling=(256, 8, 2, 1, 0))
+    assert "exceed 2^31 - 2" in str(e.value)
