@@ -393,7 +393,8 @@ void albedo_batch_plan_destroy(capvndf_batch_plan* plan);
  * is stored there under the problem signature for later plans.  Candidates:
  * block 256 or 512 threads x pairs_per_thread 8..64 (block-owned chunks) or
  * 8..128 (wavefront-owned chunks) x blocks_per_cu 2..16 (2..8 for 512), each
- * with static and dynamic chunk assignment.
+ * with static and dynamic chunk assignment.  Candidates the planner refuses
+ * for their size (more than 2^31 - 2 chunks) are skipped; BAD_SIZE if all are.
  * Arguments as albedo_batch_plan_create; outputs are overwritten.
  */
 int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const float* woy,

@@ -411,7 +411,12 @@ def albedo_batch_autotune(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_g
     ((block, ppt, bpc, per_wave, dynamic), ms)."""
     lib = load_library()
     n = wox.numel()
+    for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0).items():
+        _dev(t, k)
+    _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
     ns = torch.as_tensor(nsamples, dtype=torch.int64).cpu().contiguous()
+    if ns.numel() != n:
+        raise ValueError("nsamples must have one entry per job")
     outs = [torch.empty_like(wox) for _ in range(4)]
     best = Tiling()
     ms = ctypes.c_float()

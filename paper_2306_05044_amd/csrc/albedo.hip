@@ -1080,6 +1080,8 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
     if (!rc) rc = check_hip(hipEventCreate(&e1), "hipEventCreate");
     float best_t = 3.4e38f;
     capvndf_tiling best_tiling = default_tiling();
+    int tried = 0;
+    int32_t size_rc = CAPVNDF_OK;  // kept for when no candidate can be built
     int64_t total = 0;
     for (int64_t j = 0; j < njobs && nsamples_host; ++j) total += nsamples_host[j];
     for (int dyn = 0; dyn < 2; ++dyn)
@@ -1094,7 +1096,13 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
         capvndf_batch_plan* p = nullptr;
         rc = create_plan(njobs, wox, woy, woz, ax, ay, f0, nsamples_host, seed, with_grad, albedo,
                          grad_ax, grad_ay, grad_theta_o, &t, &p);
+        if (rc == CAPVNDF_ERR_BAD_SIZE) {  // e.g. too many chunks at this size: skip it
+            size_rc = rc;
+            rc = CAPVNDF_OK;
+            continue;
+        }
         if (rc) break;
+        ++tried;
         rc = check_hip(hipGraphLaunch(p->exec, st), "hipGraphLaunch");  // warm-up
         const int reps = 3;
         if (!rc) rc = check_hip(hipEventRecord(e0, st), "hipEventRecord");
@@ -1104,6 +1112,7 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
         if (!rc) rc = check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0.0f;
         if (!rc) rc = check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (rc) (void)hipStreamSynchronize(st);  // no replay may be pending when it is freed
         destroy_plan(p);
         if (!rc && ms / reps < best_t) {
             best_t = ms / reps;
@@ -1113,6 +1122,7 @@ extern "C" int32_t albedo_batch_autotune(int64_t njobs, const float* wox, const 
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (rc) return rc;
+    if (tried == 0) return size_rc;  // its message is the last failure's
     *best = best_tiling;
     if (best_ms) *best_ms = best_t;
     int device = 0;

@@ -193,3 +193,13 @@ def test_too_many_chunks_is_refused_before_building():
         cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
                      np.full(n, (1 << 40) - 1, dtype=np.int64), 4, tiling=(256, 8, 2, 1, 0))
     assert "exceed 2^31 - 2" in str(e.value)
+
+
+def test_autotune_refuses_when_no_tiling_fits():
+    n = 2048
+    t = {k: torch.full((n,), v, device="cuda") for k, v in
+         (("wx", 0.0), ("wy", 0.0), ("wz", 1.0), ("ax", 0.5), ("ay", 0.5))}
+    with pytest.raises(cv.CapvndfError) as e:
+        cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                                 np.full(n, (1 << 40) - 1, dtype=np.int64), 4)
+    assert e.value.code == -2 and "exceed 2^31 - 2" in str(e.value)
