@@ -375,7 +375,8 @@ int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream);
 /* Same jobs and outputs as albedo_batch_run, launched the per-request way:
  * per job one albedo_value_and_grad-style estimate kernel plus its finishing
  * kernel, no graph.  The baseline the batch is measured against.  Errors as
- * albedo_batch_run. */
+ * albedo_batch_run, and BAD_SIZE (nothing enqueued) when a job has 2^24 or
+ * more chunks of 16384 samples, more than one launch of this path covers. */
 int32_t albedo_batch_run_per_request(capvndf_batch_plan* plan, void* stream);
 
 /* Tiling and chunk statistics of a plan. */

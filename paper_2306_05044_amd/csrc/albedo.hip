@@ -1027,6 +1027,15 @@ extern "C" int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream) {
 extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* stream) {
     if (p == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_run_per_request: plan is NULL");
     if (int32_t rc = check_plan_device(p, "albedo_batch_run_per_request")) return rc;
+    // one kLutBlock block per chunk of a job: each launch must fit a 32-bit
+    // work-item count; checked for every job before anything is enqueued
+    for (int64_t j = 0; j < p->njobs; ++j)
+        if (lut_chunks_per_cell(p->nsamp_host[j]) * kLutBlock > (int64_t)0xffffffff)
+            return fail(CAPVNDF_ERR_BAD_SIZE,
+                        "albedo_batch_run_per_request: job %lld has %lld samples, more than one "
+                        "launch of this path covers (2^24 - 1 chunks of %llu samples)",
+                        (long long)j, (long long)p->nsamp_host[j],
+                        (unsigned long long)(2 * kLutChunkPairs));
     const hipStream_t st = as_stream(stream);
     const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
     for (int64_t j = 0; j < p->njobs; ++j) {

@@ -203,3 +203,17 @@ def test_autotune_refuses_when_no_tiling_fits():
         cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
                                  np.full(n, (1 << 40) - 1, dtype=np.int64), 4)
     assert e.value.code == -2 and "exceed 2^31 - 2" in str(e.value)
+
+
+def test_per_request_path_refuses_a_job_beyond_one_launch():
+    """A job of 2^38 samples is 2^24 per-request chunks of 16384 samples,
+    one more than a launch of 256-lane blocks can count: refused before
+    anything is enqueued (the plan itself, with large chunks, is fine)."""
+    t = {k: torch.full((1,), v, device="cuda") for k, v in
+         (("wx", 0.0), ("wy", 0.0), ("wz", 1.0), ("ax", 0.5), ("ay", 0.5))}
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                        np.array([1 << 38], dtype=np.int64), 4, tiling=(512, 4096, 1, 0, 0))
+    with pytest.raises(cv.CapvndfError) as e:
+        plan.run_per_request()
+    assert e.value.code == -2 and "more than one launch" in str(e.value)
+    plan.close()
