@@ -120,10 +120,17 @@ def _compare(d, outs, eta, u, name):
     full[both] = rel
     _check(full, k_pdf, 128, name + " pdf", both)
     _check(np.abs(wt - ref["weight"]), k_w, 64, name + " weight", ok)
-    # every GPU sample, ambiguous ones included, is a valid sample or no sample
-    assert np.all(np.isfinite(wo)) and np.all(pdf >= 0) and np.all((wt >= 0) & (wt <= 1 + 1e-6))
+    # every GPU sample, ambiguous ones included, is a valid sample or no
+    # sample: finite, a weight in [0, 1] and a unit direction, each up to the
+    # same per-sample error bound as the comparisons above (wo loses up to
+    # 64 2^-24 K_wo near the critical angle, and its length with it)
+    assert np.all(np.isfinite(wo)) and np.all(pdf >= 0)
+    w_hi = 1.0 + np.maximum(1e-6, 64 * EPS32 * k_w)
+    assert np.all((wt >= 0) & (wt <= w_hi)), f"{name}: weight above 1 by {np.max(wt - w_hi):.3e}"
     gv = pdf > 0
-    assert np.all(np.abs(np.linalg.norm(wo[gv], axis=1) - 1.0) < 1e-4)
+    dn = np.abs(np.linalg.norm(wo, axis=1) - 1.0)
+    n_hi = np.maximum(1e-4, 64 * EPS32 * k_wo)
+    assert np.all(dn[gv] <= n_hi[gv]), f"{name}: |wo| off by {np.max(dn[gv] - n_hi[gv]):.3e}"
     return ref
 
 
@@ -267,27 +274,24 @@ def test_determinism():
         assert torch.equal(x, y)
 
 
-def test_streaming_full_size_sampled():
-    """2^26 anisotropic tuples in the benchmark's launch configuration
-    (eta = 1.5); 2^16 sampled outputs against the oracle, invariants on all."""
+@pytest.mark.parametrize("eta", [1.5, 1.0 / 1.5])
+def test_streaming_full_size_every_sample(eta):
+    """All 2^26 anisotropic tuples in the benchmark's launch configuration
+    against the oracle on every sample (rules as above), and the invariants
+    on all of them."""
     n = 1 << 26
     d = workloads.tuples_streaming(n, seed=1)
     t = to_dev(d)
-    outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 1.5, seed=1)
+    outs = cv.dielectric_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], eta, seed=1)
     torch.cuda.synchronize()
+    del t
     wox, woy, woz, pdf, w = outs
     assert torch.all(torch.isfinite(pdf)) and torch.all(pdf >= 0)
-    assert torch.all((w >= 0) & (w <= 1.000001))
     valid = pdf > 0
-    norm = torch.sqrt(wox.double() ** 2 + woy.double() ** 2 + woz.double() ** 2)
-    assert torch.max(torch.abs(norm[valid] - 1.0)).item() < 1e-3
-    assert valid.double().mean().item() > 0.97
-    rng = np.random.default_rng(5)
-    idx = np.sort(rng.choice(n, 1 << 13, replace=False))
-    ti = torch.from_numpy(idx).cuda()
-    got = [x[ti] for x in outs]
-    sub = {k: v[idx] for k, v in d.items()}
-    _compare(sub, got, 1.5, _stream_u(1, 0, indices=idx), "2^26 sampled")
+    assert valid.double().mean().item() > (0.97 if eta > 1 else 0.5)
+    got = [host(x) for x in outs]
+    del outs, wox, woy, woz, pdf, w, valid
+    _compare(d, got, eta, _stream_u(1, 0, n=n), f"2^26 every sample eta {eta:.4f}")
 
 
 def test_more_than_one_launch_sampled():
