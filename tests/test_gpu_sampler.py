@@ -300,15 +300,15 @@ def test_pdf_entry_point_at_grazing_normals():
     assert np.all(rel <= 2e-6), rel.max()
 
 
-def test_inverse_and_pdf_full_size_sampled():
+def test_inverse_and_pdf_full_size_every_sample():
     """2^26 streaming tuples in the benchmark's launch configuration: the
-    inverse map and vndf_pdf over all the GPU's normals, 2^16 sampled outputs
-    against the oracle at the same FP32 normals (rules as above), range and
-    round-trip properties on all of them."""
+    inverse map and vndf_pdf over all the GPU's normals, every output against
+    the oracle at the same FP32 normals (u2 within 2 eps, u1 within 4 eps
+    turns where |c_xy| > 1e-6, pdf within 2e-6), range and round-trip
+    properties on all of them."""
     n = 1 << 26
     d = workloads.tuples_streaming(n, seed=1)
     t = to_dev(d)
-    del d
     hx, hy, hz, _ = cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=1)
     g1, g2 = cv.vndf_inverse(t["wx"], t["wy"], t["wz"], hx, hy, hz, t["ax"], t["ay"])
     pdf = cv.vndf_pdf(t["wx"], t["wy"], t["wz"], hx, hy, hz, t["ax"], t["ay"])
@@ -319,27 +319,27 @@ def test_inverse_and_pdf_full_size_sampled():
     u1s, u2s = cv.capvndf_uniforms(1, 2, 0, 0, n)
     e2 = (g2 - u2s).abs()
     assert torch.median(e2).item() < 1e-6
-    del u1s, u2s, e2
-    rng = np.random.default_rng(2)
-    idx = np.sort(rng.choice(n, size=1 << 16, replace=False))
-    it = torch.from_numpy(idx).cuda()
-    sub = {k: host(v[it]).astype(np.float64) for k, v in t.items()}
-    H = [host(x[it]).astype(np.float64) for x in (hx, hy, hz)]
-    r1, r2 = oracle.vndf_inverse((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
+    del u1s, u2s, e2, t
+    H = [host(x).astype(np.float64) for x in (hx, hy, hz)]
+    G1, G2, Pg = host(g1), host(g2), host(pdf).astype(np.float64)
+    del hx, hy, hz, g1, g2, pdf
+    wi = (d["wx"], d["wy"], d["wz"])
+    r1, r2 = oracle.vndf_inverse(wi, H, d["ax"], d["ay"])
     eps = 2.0 ** -24
-    G1, G2 = host(g1[it]), host(g2[it])
-    assert np.all(np.abs(G2 - r2) <= 2 * eps)
-    ws = np.stack([sub["wx"] * sub["ax"], sub["wy"] * sub["ay"], sub["wz"]], 1)
+    assert np.all(np.abs(G2 - r2) <= 2 * eps), np.abs(G2 - r2).max() / eps
+    ax, ay = d["ax"].astype(np.float64), d["ay"].astype(np.float64)
+    ws = np.stack([d["wx"] * ax, d["wy"] * ay, d["wz"].astype(np.float64)], 1)
     zs = ws[:, 2] / np.linalg.norm(ws, axis=1)
+    del ws
     cz = 1.0 - r2 * (1.0 + zs)
     cxy = np.sqrt(np.maximum(0.0, 1.0 - cz * cz))
     ok = cxy > 1e-6
-    assert np.all(_circ(G1[ok], r1[ok]) <= 4 * eps)
-    ref = oracle.vndf_pdf((sub["wx"], sub["wy"], sub["wz"]), H, sub["ax"], sub["ay"])
-    w = np.stack([sub["wx"], sub["wy"], sub["wz"]], 1)
-    w /= np.linalg.norm(w, axis=1, keepdims=True)
-    dot = np.einsum("ij,ij->i", w, np.stack(H, 1))
-    rel = np.abs(host(pdf[it]) / ref - 1.0)
+    e1 = _circ(G1[ok], r1[ok])
+    assert np.all(e1 <= 4 * eps), e1.max() / eps
+    del r1, r2, cz, cxy, ok, e1
+    ref = oracle.vndf_pdf(wi, H, d["ax"], d["ay"])
+    rel = np.abs(Pg / ref - 1.0)
+    print(f"2^26 every sample: inverse within 2/4 eps, vndf_pdf max rel {rel.max():.2e}")
     assert np.all(rel <= 2e-6), rel.max()
 
 
