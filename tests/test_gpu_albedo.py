@@ -65,7 +65,7 @@ def test_lut_edges():
 
 
 def test_lut_full_size_sampled():
-    """64 x 64 cells x 2^20 samples (the LUT workload); 6 cells vs oracle."""
+    """64 x 64 cells x 2^20 samples (the LUT workload); 64 cells vs oracle."""
     g = workloads.lut_grid(64, 64)
     t = to_dev(g)
     n = 1 << 20
@@ -73,7 +73,8 @@ def test_lut_full_size_sampled():
     torch.cuda.synchronize()
     S1, S5 = host(s1), host(s5)
     assert np.all(S1 >= 0) and np.all(S1 <= 1.0 + 1e-6) and np.all(S5 >= 0) and np.all(S5 <= S1)
-    cells = np.array([0, 63, 64 * 31 + 7, 64 * 40 + 50, 4032, 4095])
+    cells = np.unique(np.concatenate([np.linspace(0, 4095, 60).astype(np.int64),
+                                      [63, 64 * 31 + 7, 64 * 40 + 50, 4032]]))
     sub = {k: v[cells] for k, v in g.items()}
     a1, a5 = _oracle_sums(sub, n, 2, units=cells)
     assert np.abs(S1[cells] - a1).max() <= ATOL_A
@@ -112,20 +113,43 @@ def test_backward_subgrid(n):
 
 
 def test_backward_full_size_sampled():
-    """32 x 32 anisotropic cells x 2^18 samples; 4 cells vs the oracle."""
+    """32 x 32 anisotropic cells x 2^18 samples; 32 cells vs the oracle."""
     g = _grad_cells(32)
     t = to_dev(g)
     n = 1 << 18
     gx, gy, gt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
     torch.cuda.synchronize()
     assert torch.all(torch.isfinite(gx)) and torch.all(torch.isfinite(gy))
-    cells = np.array([0, 33, 517, 1023])
+    cells = np.unique(np.concatenate([np.linspace(0, 1023, 28).astype(np.int64),
+                                      [33, 517, 1000, 1022]]))
     sub = {k: v[cells] for k, v in g.items()}
     _, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
                                        n, 3, units=cells)
     _check_grad(host(gx)[cells], rx, "full d/d alpha_x")
     _check_grad(host(gy)[cells], ry, "full d/d alpha_y")
     _check_grad(host(gt)[cells], rt, "full d/d theta_o")
+
+
+def test_value_and_grad_full_size_sampled():
+    """The LUT workload (64 x 64 cells x 2^20 samples) through the one-pass
+    value and Jacobian that the autograd Function and the benchmark's
+    forward + backward run, with F0 = 0.04: 32 cells vs the oracle's value
+    and dual-number gradient."""
+    g = workloads.lut_grid(64, 64)
+    t = to_dev(g)
+    n = 1 << 20
+    f0 = torch.full((4096,), 0.04, device="cuda")
+    a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2,
+                                             f0=f0)
+    torch.cuda.synchronize()
+    cells = np.linspace(0, 4095, 32).astype(np.int64)
+    sub = {k: v[cells] for k, v in g.items()}
+    ra, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"],
+                                        sub["ay"], n, 2, f0=0.04, units=cells)
+    assert np.abs(host(a)[cells] - ra).max() <= ATOL_A
+    _check_grad(host(gx)[cells], rx, "LUT d/d alpha_x")
+    _check_grad(host(gy)[cells], ry, "LUT d/d alpha_y")
+    _check_grad(host(gt)[cells], rt, "LUT d/d theta_o")
 
 
 @pytest.mark.parametrize("n", [1 << 12, 4097, 1])
