@@ -118,7 +118,7 @@ def test_dynamic_replays_are_bitwise_stable(tiling):
 
 
 def test_full_batch_sampled():
-    """4096 uneven jobs (2^10 .. 2^22 samples); 24 jobs checked by the oracle."""
+    """4096 uneven jobs (2^10 .. 2^22 samples); 72 jobs checked by the oracle."""
     j = workloads.batch_jobs(4096, seed=4)
     t = to_dev({k: v for k, v in j.items() if k != "n"})
     plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True)
@@ -127,7 +127,9 @@ def test_full_batch_sampled():
     rng = np.random.default_rng(1)
     small = np.flatnonzero(j["n"] <= (1 << 16))
     large = np.flatnonzero(j["n"] >= (1 << 21))
-    idx = np.concatenate([rng.choice(small, 20, replace=False), rng.choice(large, 4, replace=False)])
+    mid = np.flatnonzero((j["n"] > (1 << 16)) & (j["n"] < (1 << 21)))
+    idx = np.concatenate([rng.choice(small, 48, replace=False), rng.choice(mid, 16, replace=False),
+                          rng.choice(large, 8, replace=False)])
     sub = {k: v[idx] for k, v in j.items()}
     A, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
                                        sub["n"], 4, units=idx)

@@ -64,14 +64,15 @@ def test_constant_radiance_and_edges():
 
 
 def test_radiance_full_table_sampled():
-    """64 x 64 cells x 2^20 samples under 4 lobes; 4 cells vs the oracle."""
+    """64 x 64 cells x 2^20 samples under 4 lobes; 32 cells vs the oracle."""
     g = workloads.lut_grid(64, 64)
     t = to_dev(g)
     n = 1 << 20
     r = cv.radiance_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2,
                              torch.from_numpy(LOBES).cuda())
     torch.cuda.synchronize()
-    cells = np.array([5, 1234, 2900, 4095])
+    cells = np.unique(np.concatenate([np.linspace(0, 4095, 28).astype(np.int64),
+                                      [5, 1234, 2900, 4094]]))
     sub = {k: v[cells] for k, v in g.items()}
     ref = oracle.radiance((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"], n, 2,
                           LOBES.astype(np.float64), units=cells)
