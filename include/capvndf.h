@@ -85,7 +85,7 @@ const char* capvndf_last_error(void);
  * same FP32 inputs and uniforms (same samples; FP32 arithmetic loses about
  * 2^-24 (1 + max(ax, ay)/L + 1/|c + wi|) relatively, L = |M^-T (c + wi)|,
  * which exceeds 2e-6 near grazing half vectors; in double every output is
- * within 2e-6, in practice a few ulps, of the exact sample; 1.00-1.04x the
+ * within 2e-6, in practice a few ulps, of the exact sample; 1.00-1.05x the
  * FP32 method's time on this part).
  *
  *   n            number of tuples (>= 0; 0 enqueues nothing)
