@@ -66,10 +66,11 @@ extern "C" {
 #define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
 #define CAPVNDF_CAP_F64 2  /* spherical cap evaluated in double precision   */
 
-/* Version of this ABI (major * 10000 + minor * 100 + patch): 2.0.0.  Major 2
+/* Version of this ABI (major * 10000 + minor * 100 + patch): 2.1.0.  Major 2
  * added the `dynamic` field to capvndf_tiling (a layout change) and the
- * CAPVNDF_CAP_F64 method. */
-#define CAPVNDF_VERSION 20000
+ * CAPVNDF_CAP_F64 method; minor 1 added albedo_view_from_angles and
+ * albedo_apply_jacobian. */
+#define CAPVNDF_VERSION 20100
 int32_t capvndf_version(void);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -311,6 +312,50 @@ int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy, co
                           const float* ax, const float* ay, const float* f0, int64_t nsamples,
                           uint64_t seed, const float* lobes, int32_t nlobes, float* radiance,
                           void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * albedo_view_from_angles -- view directions from spherical angles,
+ *   wo = (sin theta cos phi, sin theta sin phi, cos theta),
+ * the parametrisation whose polar derivative albedo_estimate_backward and
+ * albedo_value_and_grad report (theta_o is the angle to the macro-normal,
+ * Sec. 2's frame with the surface normal along +z).  FP32 with the library's
+ * sincosf (a few ulps).
+ *
+ *   n                    number of directions (>= 0)
+ *   theta_o, phi_o [n]   angles in radians (device, FP32)
+ *   wox, woy, woz  [n]   out (device, FP32); may not alias the inputs
+ * Errors: BAD_SIZE (n < 0), NULL_PTR, MISALIGNED, HIP.
+ */
+int32_t albedo_view_from_angles(int64_t n, const float* theta_o, const float* phi_o, float* wox,
+                                float* woy, float* woz, void* stream);
+
+/*
+ * albedo_apply_jacobian -- the chain rule through the per-cell Jacobian of
+ * the albedo (each cell's A depends only on that cell's parameters, so the
+ * Jacobian is diagonal): with g = dL/dA,
+ *   grad_ax = g * d_ax,  grad_ay = g * d_ay,  grad_theta_o = g * d_theta_o
+ * for the derivatives from albedo_value_and_grad, and
+ *   grad_f0 = g * (s_f1 - s_f5),
+ * dA/dF0 exactly, from the two sums of albedo_estimate on the same stream
+ * (Schlick's F is linear in F0).  One correctly rounded FP32 multiply per
+ * output (and one subtraction for F0).
+ *
+ *   n                     number of cells (>= 0)
+ *   grad_albedo [n]       g (device, FP32)
+ *   d_ax, d_ay, d_theta_o [n] each NULL to skip that output
+ *   s_f1, s_f5  [n]       both NULL to skip grad_f0
+ *   grad_ax, grad_ay, grad_theta_o, grad_f0 [n] out; NULL exactly where
+ *                         the matching input is NULL; distinct from each
+ *                         other, but each may alias any input (every input
+ *                         of an element is read before its outputs are
+ *                         written)
+ * Errors: BAD_SIZE (n < 0), NULL_PTR (also for an output without its input
+ * or the reverse), MISALIGNED, HIP.
+ */
+int32_t albedo_apply_jacobian(int64_t n, const float* grad_albedo, const float* d_ax,
+                              const float* d_ay, const float* d_theta_o, const float* s_f1,
+                              const float* s_f5, float* grad_ax, float* grad_ay,
+                              float* grad_theta_o, float* grad_f0, void* stream);
 
 /*
  * Batched estimation of many jobs with uneven sample counts (forward value

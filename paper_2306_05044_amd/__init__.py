@@ -77,6 +77,8 @@ _SIGNATURES = {
                                ctypes.c_size_t, _P], _I32),
     "radiance_estimate": ([_I64, _P, _P, _P, _P, _P, _P, _I64, _U64, _P, _I32, _P, _P,
                            ctypes.c_size_t, _P], _I32),
+    "albedo_view_from_angles": ([_I64, _P, _P, _P, _P, _P, _P], _I32),
+    "albedo_apply_jacobian": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
     "albedo_batch_plan_create": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _I32, _P, _P, _P, _P,
                                   ctypes.POINTER(Tiling), _P, ctypes.POINTER(_P)], _I32),
     "albedo_batch_run": ([_P, _P], _I32),
@@ -342,6 +344,45 @@ def radiance_estimate(wox, woy, woz, ax, ay, nsamples, seed, lobes, f0=None, wor
                                ws.numel() * 4, _stream(stream))
     _check("radiance_estimate", rc)
     return out
+
+
+def albedo_view_from_angles(theta_o, phi_o, out=None, stream=None):
+    """View directions (sin t cos p, sin t sin p, cos t) from their angles;
+    returns (wox, woy, woz)."""
+    lib = load_library()
+    _dev(theta_o, "theta_o")
+    _dev(phi_o, "phi_o")
+    n = theta_o.numel()
+    _same_len(n, phi_o=phi_o)
+    wox, woy, woz = out if out is not None else [torch.empty_like(theta_o) for _ in range(3)]
+    for k, t in dict(wox=wox, woy=woy, woz=woz).items():
+        _dev(t, k)
+    _same_len(n, wox=wox, woy=woy, woz=woz)
+    _check("albedo_view_from_angles",
+           lib.albedo_view_from_angles(n, _ptr(theta_o), _ptr(phi_o), _ptr(wox), _ptr(woy),
+                                       _ptr(woz), _stream(stream)))
+    return wox, woy, woz
+
+
+def albedo_apply_jacobian(grad_albedo, d_ax=None, d_ay=None, d_theta_o=None, s_f1=None,
+                          s_f5=None, stream=None):
+    """Chain rule through the diagonal Jacobian: g * d_ax, g * d_ay,
+    g * d_theta_o and g * (s_f1 - s_f5) (None where the input is None)."""
+    lib = load_library()
+    _dev(grad_albedo, "grad_albedo")
+    n = grad_albedo.numel()
+    ins = dict(d_ax=d_ax, d_ay=d_ay, d_theta_o=d_theta_o, s_f1=s_f1, s_f5=s_f5)
+    for k, t in ins.items():
+        _dev(t, k)
+    _same_len(n, **ins)
+    if (s_f1 is None) != (s_f5 is None):
+        raise ValueError("give both s_f1 and s_f5 or neither")
+    outs = [None if t is None else torch.empty_like(grad_albedo) for t in (d_ax, d_ay, d_theta_o, s_f1)]
+    _check("albedo_apply_jacobian",
+           lib.albedo_apply_jacobian(n, _ptr(grad_albedo), _ptr(d_ax), _ptr(d_ay),
+                                     _ptr(d_theta_o), _ptr(s_f1), _ptr(s_f5), *[_ptr(o) for o in outs],
+                                     _stream(stream)))
+    return tuple(outs)
 
 
 class BatchPlan:

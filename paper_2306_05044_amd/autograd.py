@@ -5,8 +5,10 @@ A cell's albedo depends only on that cell's parameters, so the Jacobian is
 diagonal: three numbers per cell.  When any input needs a gradient, forward
 runs ``albedo_value_and_grad``, which produces the value and those three
 derivatives in one pass over the samples, and backward scales them by the
-incoming gradient.  Otherwise forward runs the value-only kernel.  Nothing
-but the inputs' derivatives is saved (no samples).
+incoming gradient (``albedo_apply_jacobian``).  Otherwise forward runs the
+value-only kernel.  The view direction comes from its angles in
+``albedo_view_from_angles``, so every arithmetic step runs in the library's
+kernels.  Nothing but the inputs' derivatives is saved (no samples).
 """
 
 from __future__ import annotations
@@ -26,35 +28,38 @@ class AlbedoFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, ax, ay, theta_o, phi_o, f0, nsamples, seed):
-        from . import albedo_estimate, albedo_value_and_grad
-        # view direction from its spherical angles (argument marshalling)
-        st = torch.sin(theta_o)
-        wox = (st * torch.cos(phi_o)).contiguous().reshape(-1)
-        woy = (st * torch.sin(phi_o)).contiguous().reshape(-1)
-        woz = torch.cos(theta_o).contiguous().reshape(-1)
-        axf, ayf = ax.contiguous().reshape(-1), ay.contiguous().reshape(-1)
+        from . import albedo_estimate, albedo_value_and_grad, albedo_view_from_angles
+        flat = [t.contiguous().reshape(-1) for t in (ax, ay, theta_o, phi_o, f0)]
+        axf, ayf, thf, phf, f0f = flat
+        wox, woy, woz = albedo_view_from_angles(thf, phf)
         need = any(ctx.needs_input_grad[:3])
         a, gx, gy, gt = albedo_value_and_grad(
-            wox, woy, woz, axf, ayf, int(nsamples), int(seed), f0=f0.contiguous().reshape(-1),
-            with_grad=need)
-        shape = ax.shape
-        saved = [gx.reshape(shape), gy.reshape(shape), gt.reshape(shape)] if need else [None] * 3
+            wox, woy, woz, axf, ayf, int(nsamples), int(seed), f0=f0f, with_grad=need)
+        saved = [gx, gy, gt] if need else [None] * 3
         if ctx.needs_input_grad[4]:
             # the estimate is linear in F0: dA/dF0 = S1 - S5 on the same stream
-            s1, s5 = albedo_estimate(wox, woy, woz, axf, ayf, int(nsamples), int(seed))
-            saved.append((s1 - s5).reshape(shape))
+            saved += list(albedo_estimate(wox, woy, woz, axf, ayf, int(nsamples), int(seed)))
         else:
-            saved.append(None)
+            saved += [None, None]
         ctx.save_for_backward(*saved)
-        return a.reshape(shape)
+        ctx.shape = ax.shape
+        return a.reshape(ax.shape)
 
     @staticmethod
     def backward(ctx, grad_a):
-        jx, jy, jt, jf = ctx.saved_tensors
-        g = grad_a.to(torch.float32)
+        from . import albedo_apply_jacobian
+        jx, jy, jt, s1, s5 = ctx.saved_tensors
         need = ctx.needs_input_grad
-        return (g * jx if need[0] else None, g * jy if need[1] else None,
-                g * jt if need[2] else None, None, g * jf if need[4] else None, None, None)
+        g = grad_a.to(torch.float32).contiguous().reshape(-1)
+        ox, oy, ot, of = albedo_apply_jacobian(
+            g, jx if need[0] else None, jy if need[1] else None, jt if need[2] else None,
+            s1 if need[4] else None, s5 if need[4] else None)
+        shape = ctx.shape
+
+        def out(t):
+            return None if t is None else t.reshape(shape)
+
+        return out(ox), out(oy), out(ot), None, out(of), None, None
 
 
 def albedo(ax, ay, theta_o, phi_o, f0, nsamples, seed):

@@ -645,6 +645,103 @@ extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const flo
 }
 
 // ===========================================================================
+// Element-wise helpers of the differentiable albedo: the view direction from
+// its spherical angles, and the chain rule through the diagonal Jacobian.
+// ===========================================================================
+namespace capvndf {
+namespace {
+
+constexpr int kEltBlock = 256;
+constexpr int64_t kEltMaxBlocks = (int64_t)1 << 20;  // grid-stride beyond this
+
+inline unsigned elt_grid(int64_t n) {
+    const int64_t b = (n + kEltBlock - 1) / kEltBlock;
+    return (unsigned)(b < kEltMaxBlocks ? b : kEltMaxBlocks);
+}
+
+// wo = (sin t cos p, sin t sin p, cos t), the parametrisation whose polar
+// derivative the adjoint reports.
+__global__ __launch_bounds__(kEltBlock) void k_view_from_angles(
+    int64_t n, const float* __restrict__ theta, const float* __restrict__ phi,
+    float* __restrict__ wox, float* __restrict__ woy, float* __restrict__ woz) {
+    const int64_t stride = (int64_t)gridDim.x * kEltBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kEltBlock + threadIdx.x; i < n; i += stride) {
+        float st, ct, sp, cp;
+        sincosf(theta[i], &st, &ct);
+        sincosf(phi[i], &sp, &cp);
+        wox[i] = st * cp;
+        woy[i] = st * sp;
+        woz[i] = ct;
+    }
+}
+
+// out_k = g * d_k for the three parameter derivatives that are given, and
+// g * (s_f1 - s_f5) for F0 (the estimate is linear in F0).  Every input of an
+// element is read before any output of it is written, so outputs may alias
+// inputs (no __restrict__).
+__global__ __launch_bounds__(kEltBlock) void k_apply_jacobian(
+    int64_t n, const float* g, const float* dx, const float* dy, const float* dt,
+    const float* s1, const float* s5, float* ox, float* oy, float* ot, float* of) {
+    const int64_t stride = (int64_t)gridDim.x * kEltBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kEltBlock + threadIdx.x; i < n; i += stride) {
+        const float gi = g[i];
+        const float vx = dx ? dx[i] : 0.0f;
+        const float vy = dy ? dy[i] : 0.0f;
+        const float vt = dt ? dt[i] : 0.0f;
+        const float vf = s1 ? s1[i] - s5[i] : 0.0f;
+        if (dx) ox[i] = gi * vx;
+        if (dy) oy[i] = gi * vy;
+        if (dt) ot[i] = gi * vt;
+        if (s1) of[i] = gi * vf;
+    }
+}
+
+}  // namespace
+}  // namespace capvndf
+
+extern "C" int32_t albedo_view_from_angles(int64_t n, const float* theta_o, const float* phi_o,
+                                           float* wox, float* woy, float* woz, void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_view_from_angles: n < 0");
+    if (n == 0) return CAPVNDF_OK;
+    const void* req[] = {theta_o, phi_o, wox, woy, woz};
+    const char* names[] = {"theta_o", "phi_o", "wox", "woy", "woz"};
+    for (int i = 0; i < 5; ++i)
+        if (int32_t rc = check_array(req[i], names[i])) return rc;
+    hipLaunchKernelGGL(k_view_from_angles, dim3(elt_grid(n)), dim3(kEltBlock), 0,
+                       as_stream(stream), n, theta_o, phi_o, wox, woy, woz);
+    return check_launch("albedo_view_from_angles launch");
+}
+
+extern "C" int32_t albedo_apply_jacobian(int64_t n, const float* grad_albedo, const float* d_ax,
+                                         const float* d_ay, const float* d_theta_o,
+                                         const float* s_f1, const float* s_f5, float* grad_ax,
+                                         float* grad_ay, float* grad_theta_o, float* grad_f0,
+                                         void* stream) {
+    if (n < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_apply_jacobian: n < 0");
+    // every output goes with its input(s): both given or both NULL
+    const void* in[] = {d_ax, d_ay, d_theta_o, s_f1, s_f5};
+    const void* out[] = {grad_ax, grad_ay, grad_theta_o, grad_f0, grad_f0};
+    const char* names[] = {"d_ax", "d_ay", "d_theta_o", "s_f1", "s_f5"};
+    for (int i = 0; i < 5; ++i)
+        if ((in[i] == nullptr) != (out[i] == nullptr))
+            return fail(CAPVNDF_ERR_NULL_PTR,
+                        "albedo_apply_jacobian: %s and its gradient output must be given together",
+                        names[i]);
+    if (n == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(grad_albedo, "grad_albedo")) return rc;
+    const char* onames[] = {"grad_ax", "grad_ay", "grad_theta_o", "grad_f0", "grad_f0"};
+    for (int i = 0; i < 5; ++i)
+        if (in[i] != nullptr) {
+            if (int32_t rc = check_array(in[i], names[i])) return rc;
+            if (int32_t rc = check_array(out[i], onames[i])) return rc;
+        }
+    hipLaunchKernelGGL(k_apply_jacobian, dim3(elt_grid(n)), dim3(kEltBlock), 0, as_stream(stream),
+                       n, grad_albedo, d_ax, d_ay, d_theta_o, s_f1, s_f5, grad_ax, grad_ay,
+                       grad_theta_o, grad_f0);
+    return check_launch("albedo_apply_jacobian launch");
+}
+
+// ===========================================================================
 // Batch plans.
 // ===========================================================================
 struct capvndf_batch_plan {

@@ -141,6 +141,35 @@ def test_albedo_argument_errors(lib):
     lib.albedo_batch_plan_destroy(None)  # no-op
 
 
+def test_gradient_helper_argument_errors(lib):
+    P = ctypes.c_void_p
+    fake, odd = P(0x1000), P(0x1002)
+    assert lib.albedo_view_from_angles(-1, fake, fake, fake, fake, fake, None) == -2
+    assert lib.albedo_view_from_angles(0, None, None, None, None, None, None) == 0
+    assert lib.albedo_view_from_angles(4, fake, None, fake, fake, fake, None) == -1
+    assert "phi_o" in _err(lib)
+    assert lib.albedo_view_from_angles(4, fake, fake, odd, fake, fake, None) == -3
+    none4 = [None] * 4
+    assert lib.albedo_apply_jacobian(-1, fake, *[None] * 5, *none4, None) == -2
+    # an input without its output, and the reverse
+    assert lib.albedo_apply_jacobian(4, fake, fake, None, None, None, None, *none4, None) == -1
+    assert "d_ax" in _err(lib)
+    assert lib.albedo_apply_jacobian(4, fake, None, None, None, None, None, None, None, fake, None,
+                                     None) == -1
+    assert "d_theta_o" in _err(lib)
+    # F0 needs both sums
+    assert lib.albedo_apply_jacobian(4, fake, None, None, None, fake, None, None, None, None, fake,
+                                     None) == -1
+    assert "s_f5" in _err(lib)
+    assert lib.albedo_apply_jacobian(4, None, fake, None, None, None, None, fake, None, None, None,
+                                     None) == -1
+    assert "grad_albedo" in _err(lib)
+    assert lib.albedo_apply_jacobian(4, fake, odd, None, None, None, None, fake, None, None, None,
+                                     None) == -3
+    assert lib.albedo_apply_jacobian(0, None, fake, None, None, None, None, fake, None, None, None,
+                                     None) == 0
+
+
 def test_dielectric_argument_errors(lib):
     P = ctypes.c_void_p
     fake = P(0x1000)  # never dereferenced: validation fails first

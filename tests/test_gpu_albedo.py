@@ -239,6 +239,48 @@ def test_autograd_f0_gradient():
     assert np.abs(host(a.detach()) - (0.3 * s1 + 0.7 * s5)).max() <= ATOL_A
 
 
+def test_view_from_angles():
+    """wo = (sin t cos p, sin t sin p, cos t) in FP32, against float64 at the
+    same FP32 angles, over the hemisphere and a ragged length."""
+    rng = np.random.default_rng(21)
+    n = 100003
+    th = rng.uniform(0.0, np.pi / 2, n).astype(np.float32)
+    ph = rng.uniform(-np.pi, np.pi, n).astype(np.float32)
+    th[:4] = [0.0, np.float32(np.pi / 2), 1e-6, 1.5]
+    wx, wy, wz = cv.albedo_view_from_angles(torch.from_numpy(th).cuda(), torch.from_numpy(ph).cuda())
+    t, p = th.astype(np.float64), ph.astype(np.float64)
+    ref = (np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t))
+    for got, want in zip((wx, wy, wz), ref):
+        assert np.abs(host(got).astype(np.float64) - want).max() <= 4e-7
+    assert cv.albedo_view_from_angles(torch.empty(0, device="cuda"),
+                                      torch.empty(0, device="cuda"))[0].numel() == 0
+
+
+def test_apply_jacobian_is_the_fp32_product():
+    """Each output is one correctly rounded FP32 product (F0: of the sums'
+    difference), so it equals torch's on the same inputs bit for bit; also
+    with outputs written over their inputs."""
+    rng = np.random.default_rng(22)
+    n = 70001
+    g, dx, dy, dt, s1, s5 = (torch.from_numpy(rng.standard_normal(n).astype(np.float32)).cuda()
+                             for _ in range(6))
+    ox, oy, ot, of = cv.albedo_apply_jacobian(g, dx, dy, dt, s1, s5)
+    assert torch.equal(ox, g * dx) and torch.equal(oy, g * dy) and torch.equal(ot, g * dt)
+    assert torch.equal(of, g * (s1 - s5))
+    only = cv.albedo_apply_jacobian(g, d_theta_o=dt)
+    assert only[0] is None and only[1] is None and only[3] is None
+    assert torch.equal(only[2], g * dt)
+    # in place: grad_ax over d_ax, grad_f0 over s_f1
+    want_x, want_f = g * dx, g * (s1 - s5)
+    lib = cv.load_library()
+    P = lambda t: cv._ptr(t)  # noqa: E731
+    rc = lib.albedo_apply_jacobian(n, P(g), P(dx), None, None, P(s1), P(s5), P(dx), None, None,
+                                   P(s1), cv._stream(None))
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(dx, want_x) and torch.equal(s1, want_f)
+
+
 def test_estimator_determinism():
     g = workloads.lut_grid(8, 8)
     t = to_dev(g)

@@ -2,7 +2,8 @@
 allocation, no memset, no synchronisation), so a caller can capture them in a
 graph.  Captured here with torch's graph API: the sampler, the pdf and inverse map at
 its normals, the dielectric sampler and its pdf, the one-pass albedo value and
-gradient, and the direct-illumination estimator; the graph is replayed
+gradient, the direct-illumination estimator, and the autograd helpers (view
+directions from angles, the Jacobian product); the graph is replayed
 several times with unrelated eager work and synchronisation in between, and
 every replay must equal the eager results bit for bit."""
 
@@ -39,6 +40,10 @@ def test_hot_path_in_a_captured_graph():
     vals = [torch.empty(64, device="cuda") for _ in range(5)]
     lobes = torch.tensor([[0.0, 0.0, 1.0, 4.0, 2.0], [0.6, 0.0, 0.8, 30.0, 5.0]],
                          dtype=torch.float32, device="cuda")
+    th = torch.linspace(0.0, 1.5, 64, device="cuda")
+    ph = torch.linspace(-3.0, 3.0, 64, device="cuda")
+    vdirs = tuple(torch.empty(64, device="cuda") for _ in range(3))
+    jvals = [torch.empty(64, device="cuda") for _ in range(4)]
 
     def run():
         cv.vndf_sample(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], seed=3, out=outs)
@@ -55,10 +60,14 @@ def test_hot_path_in_a_captured_graph():
             v.copy_(x)
         vals[4].copy_(cv.radiance_estimate(c["wx"], c["wy"], c["wz"], c["ax"], c["ay"], n, 6,
                                            lobes, workspace=wr))
+        cv.albedo_view_from_angles(th, ph, out=vdirs)
+        j = cv.albedo_apply_jacobian(vals[0], vals[1], vals[2], vals[3], vals[0], vals[4])
+        for v, x in zip(jvals, j):
+            v.copy_(x)
 
     run()
     torch.cuda.synchronize()
-    eager = [x.clone() for x in outs + douts + pouts + tuple(vals)]
+    eager = [x.clone() for x in outs + douts + pouts + tuple(vals) + vdirs + tuple(jvals)]
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -72,12 +81,12 @@ def test_hot_path_in_a_captured_graph():
     torch.cuda.synchronize()
 
     for rep in range(4):
-        for x in outs + douts + pouts + tuple(vals):
+        for x in outs + douts + pouts + tuple(vals) + vdirs + tuple(jvals):
             x.fill_(float("nan"))
         junk = torch.randn(1 << 16, device="cuda")
         _ = (junk * 3).sum().item()  # unrelated eager work and a synchronisation
         graph.replay()
         torch.cuda.synchronize()
-        for k, (a, b) in enumerate(zip(eager, outs + douts + pouts + tuple(vals))):
+        for k, (a, b) in enumerate(zip(eager, outs + douts + pouts + tuple(vals) + vdirs + tuple(jvals))):
             assert torch.equal(a, b), f"replay {rep}, output {k}"
     assert np.isfinite(eager[0].cpu().numpy()).all()
