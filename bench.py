@@ -113,12 +113,22 @@ def alu_roofline(kind, samples, ms):
             h.update(fh.read())
     if rec.get("source_digest") != h.hexdigest()[:16]:
         return None
-    ips = rec["valu_lane_instr_per_sample"][kind]
+    ips = rec["valu_lane_instr_per_sample"].get(kind)
+    if ips is None:
+        return None
     peak = rec["peak_lane_instr_per_s"] / 1e12
     achieved = ips * samples / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2),
             "unit": "T VALU lane-instr/s", "frac": round(achieved / peak, 4),
             "lane_instr_per_sample": round(ips, 1)}
+
+
+def batch_kernel(tiling):
+    """Counter-summary key of the batch kernel a tiling (block, pairs per
+    thread, blocks per CU, per_wave, dynamic) runs, with gradients."""
+    block, _, _, per_wave, dynamic = tiling
+    name = "k_batch_wave" if per_wave else "k_batch"
+    return f"batch:{name}<{block}, true, {'true' if dynamic else 'false'}>"
 
 
 def cpu_baseline(d):
@@ -486,6 +496,9 @@ def main():
                           "default_tiling_dynamic_ms": round(ms_default_dyn, 4),
                           "autotune_s": round(tune_s, 2),
                           "gsamples_per_s_fwd_adj": round(info["total_samples"] / ms_b / 1e6, 2),
+                          # over the whole replay (persistent kernel + finishing pass)
+                          "roofline": alu_roofline(batch_kernel(info["tiling"]), info["total_samples"],
+                                                   ms_b),
                           "max_abs_albedo_diff_batch_vs_per_request": float(f"{dev_a:.3e}"),
                           "per_request_plain_sampler": {
                               "what": "per job: 5 fills, the job's uniforms, vndf_sample; no "
@@ -540,7 +553,8 @@ def main():
                                          "value": r.cpu().numpy()[cells]}
         out["direct_illumination"] = {
             "cells": 4096, "samples_per_cell": n, "lobes": 4, "ms": round(ms_r, 4),
-            "gsamples_per_s": round(4096 * n / ms_r / 1e6, 2)}
+            "gsamples_per_s": round(4096 * n / ms_r / 1e6, 2),
+            "roofline": alu_roofline("radiance", 4096 * n, ms_r)}
 
     result = {"metric": METRIC, "unit": "Gsamples/s", "n_gpus": 1, "steps": args.steps,
               "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
