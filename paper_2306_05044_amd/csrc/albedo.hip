@@ -225,18 +225,19 @@ __global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
     }
 }
 
-// Direct illumination: one sum of F G2/G1 L(wl) per cell.
+// Direct illumination: one sum of F G2/G1 L(wl) per cell, NL lobes.
+template <int NL>
 __global__ __launch_bounds__(kLutBlock) void k_radiance(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
-    const float* __restrict__ lobep, int32_t nlobes, uint64_t nsamples, int32_t cpc,
-    uint32_t k0, uint32_t k1, float* __restrict__ partial) {
+    const float* __restrict__ lobep, uint64_t nsamples, int32_t cpc, uint32_t k0, uint32_t k1,
+    float* __restrict__ partial) {
     const int64_t b = blockIdx.x;
     const int64_t cell = b / cpc;
     const int64_t chunk = b - cell * cpc;
     const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
     const float f0 = f0p ? f0p[cell] : 1.0f;
-    const Lobes lobes = load_lobes(lobep, nlobes);
+    const Lobes<NL> lobes = load_lobes<NL>(lobep);
     Comp acc[1] = {Comp{0.0f, 0.0f}};
     const uint64_t npairs = (nsamples + 1) / 2;
     const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
@@ -634,9 +635,29 @@ extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const flo
     const int64_t cpc = lut_chunks_per_cell(nsamples);
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
-    hipLaunchKernelGGL(k_radiance, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox, woy,
-                       woz, ax, ay, f0, lobes, nlobes, (uint64_t)nsamples, (int32_t)cpc,
-                       key_lo(seed), key_hi(seed), part);
+    const dim3 grid((unsigned)(ncells * cpc)), block(kLutBlock);
+    const uint64_t ns = (uint64_t)nsamples;
+    const uint32_t k0 = key_lo(seed), k1 = key_hi(seed);
+    static_assert(kMaxLobes == 8, "the switch below covers 0 .. 8 lobes");
+#define CAPVNDF_LAUNCH_RADIANCE(NL)                                                                \
+    case NL:                                                                                       \
+        hipLaunchKernelGGL(k_radiance<NL>, grid, block, 0, st, wox, woy, woz, ax, ay, f0, lobes,  \
+                           ns, (int32_t)cpc, k0, k1, part);                                        \
+        break;
+    switch (nlobes) {
+        CAPVNDF_LAUNCH_RADIANCE(0)
+        CAPVNDF_LAUNCH_RADIANCE(1)
+        CAPVNDF_LAUNCH_RADIANCE(2)
+        CAPVNDF_LAUNCH_RADIANCE(3)
+        CAPVNDF_LAUNCH_RADIANCE(4)
+        CAPVNDF_LAUNCH_RADIANCE(5)
+        CAPVNDF_LAUNCH_RADIANCE(6)
+        CAPVNDF_LAUNCH_RADIANCE(7)
+        CAPVNDF_LAUNCH_RADIANCE(8)
+        default:
+            return fail(CAPVNDF_ERR_BAD_SIZE, "radiance_estimate: nlobes must be in [0, %d]", kMaxLobes);
+    }
+#undef CAPVNDF_LAUNCH_RADIANCE
     if (int32_t rc = check_launch("radiance_estimate launch")) return rc;
     hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
                        part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr, radiance,

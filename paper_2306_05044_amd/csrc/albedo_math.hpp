@@ -84,44 +84,46 @@ __device__ __forceinline__ FwdTerm albedo_fwd(const CellConst& c, float u1, floa
 // Synthetic incident radiance for the direct-illumination estimator: up to
 // kMaxLobes spherical-Gaussian lobes L(w) = sum lambda exp(kappa (mu.w - 1)),
 // held per lane (uniform values) with kappa pre-scaled by log2(e) for the
-// hardware base-2 exponential.
+// hardware base-2 exponential.  The lobe count is a compile-time parameter:
+// with a run-time count the compiler evaluated all kMaxLobes lobes and
+// selected the live ones.
 constexpr int kMaxLobes = 8;
 
+template <int NL>
 struct Lobes {
-    float mx[kMaxLobes], my[kMaxLobes], mz[kMaxLobes], k2[kMaxLobes], lam[kMaxLobes];
-    int n;
+    static constexpr int kN = NL > 0 ? NL : 1;
+    float mx[kN], my[kN], mz[kN], k2[kN], lam[kN];
 };
 
-__device__ __forceinline__ Lobes load_lobes(const float* __restrict__ p, int n) {
-    Lobes l;
-    l.n = n;
+template <int NL>
+__device__ __forceinline__ Lobes<NL> load_lobes(const float* __restrict__ p) {
+    Lobes<NL> l;
 #pragma unroll
-    for (int k = 0; k < kMaxLobes; ++k) {
-        const bool on = k < n;
-        l.mx[k] = on ? p[5 * k] : 0.0f;
-        l.my[k] = on ? p[5 * k + 1] : 0.0f;
-        l.mz[k] = on ? p[5 * k + 2] : 1.0f;
-        l.k2[k] = on ? p[5 * k + 3] * 1.4426950408889634f : 0.0f;
-        l.lam[k] = on ? p[5 * k + 4] : 0.0f;
+    for (int k = 0; k < NL; ++k) {
+        l.mx[k] = p[5 * k];
+        l.my[k] = p[5 * k + 1];
+        l.mz[k] = p[5 * k + 2];
+        l.k2[k] = p[5 * k + 3] * 1.4426950408889634f;
+        l.lam[k] = p[5 * k + 4];
     }
     return l;
 }
 
-__device__ __forceinline__ float lobe_radiance(const Lobes& l, float wx, float wy, float wz) {
+template <int NL>
+__device__ __forceinline__ float lobe_radiance(const Lobes<NL>& l, float wx, float wy, float wz) {
     float r = 0.0f;
 #pragma unroll
-    for (int k = 0; k < kMaxLobes; ++k) {
-        if (k < l.n) {
-            const float c = __builtin_fmaf(l.mx[k], wx, __builtin_fmaf(l.my[k], wy, l.mz[k] * wz));
-            r = __builtin_fmaf(l.lam[k], __builtin_amdgcn_exp2f(__builtin_fmaf(l.k2[k], c, -l.k2[k])), r);
-        }
+    for (int k = 0; k < NL; ++k) {
+        const float c = __builtin_fmaf(l.mx[k], wx, __builtin_fmaf(l.my[k], wy, l.mz[k] * wz));
+        r = __builtin_fmaf(l.lam[k], __builtin_amdgcn_exp2f(__builtin_fmaf(l.k2[k], c, -l.k2[k])), r);
     }
     return r;
 }
 
 // Direct-illumination term (Appendix A estimator with radiance L):
 // F(wo.h) G2/G1 L(wl), 0 below the horizon.
-__device__ __forceinline__ float radiance_term(const CellConst& c, float f0, const Lobes& lobes,
+template <int NL>
+__device__ __forceinline__ float radiance_term(const CellConst& c, float f0, const Lobes<NL>& lobes,
                                                float u1, float u2) {
     const CapSample cs = cap_sample(c.s, u1, u2);
     const Normal n = unstretch(cs.hsx, cs.hsy, cs.hsz, c.ax, c.ay);
