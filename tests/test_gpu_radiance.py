@@ -34,7 +34,9 @@ def _cells(n_side, seed):
     return {"wx": wx, "wy": wy, "wz": wz, "ax": gg["ax"], "ay": gg["ay"]}
 
 
-@pytest.mark.parametrize("n,nl", [(1 << 12, 4), (4097, 1), (1, 4), (1 << 14, 8)])
+# every lobe count has its own kernel instantiation (0 lobes: see the edges test)
+@pytest.mark.parametrize("n,nl", [(1 << 12, 4), (4097, 1), (1, 4), (1 << 14, 8), (2049, 2),
+                                  (2049, 3), (2049, 5), (2049, 6), (2049, 7)])
 def test_radiance_matches_oracle(n, nl):
     g = _cells(8, seed=21)
     t = to_dev(g)
