@@ -41,9 +41,9 @@ DISK2018 = 1
 def build() -> str:
     """Compile ``oracle.cpp`` into ``liboracle.so`` (always recompiles)."""
     cmd = [
-        "g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+        "g++", "-O2", "-std=gnu++17", "-fPIC", "-shared", "-pthread",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-        _SRC, "-o", _LIB + ".tmp",
+        _SRC, "-o", _LIB + ".tmp", "-lquadmath",
     ]
     subprocess.run(cmd, check=True)
     os.replace(_LIB + ".tmp", _LIB)
@@ -103,6 +103,15 @@ def _load():
                                   ctypes.c_uint64, _d, ctypes.c_double, _d, _d, _d,
                                   ctypes.c_int32]
     lib.orc_albedo_fd.restype = ctypes.c_int32
+    lib.orc_albedo_kinks.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _i64, _u32,
+                                     ctypes.c_uint64, ctypes.c_double, _i64, _i64, _i64,
+                                     ctypes.c_int32]
+    lib.orc_albedo_kinks.restype = ctypes.c_int32
+    lib.orc_albedo_horizon_band.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _i64, _u32,
+                                            ctypes.c_uint64, _d, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, _d, _d, _d, _i64,
+                                            ctypes.c_int32]
+    lib.orc_albedo_horizon_band.restype = ctypes.c_int32
     lib.orc_radiance.argtypes = [ctypes.c_int64, _d, _d, _d, _d, _d, _d, _i64, _u32,
                                  ctypes.c_uint64, _d, ctypes.c_int32, _d, ctypes.c_int32]
     lib.orc_radiance.restype = ctypes.c_int32
@@ -309,6 +318,51 @@ def albedo_fd(wo, ax, ay, nsamples, seed, f0=1.0, step=1e-4, units=None, nthread
     if rc != 0:
         raise ValueError("orc_albedo_fd failed")
     return tuple(outs)
+
+
+def albedo_kinks(wo, ax, ay, nsamples, seed, step=1e-4, units=None, nthreads=0):
+    """Per cell, for alpha_x, alpha_y and theta_o: the number of samples whose
+    estimator term is zero at some and non-zero at others of the parameter
+    minus step, at it and plus step (the reflection crosses the horizon
+    within the step, a kink of the term)."""
+    wo, n, ax, ay, ns, un, _ = _cells(wo, ax, ay, nsamples, units, 1.0)
+    outs = [np.zeros(n, dtype=np.int64) for _ in range(3)]
+    rc = _load().orc_albedo_kinks(n, *[_p(c) for c in wo], _p(ax), _p(ay),
+                                  ns.ctypes.data_as(_i64),
+                                  None if un is None else un.ctypes.data_as(_u32), seed,
+                                  float(step), *[c.ctypes.data_as(_i64) for c in outs],
+                                  _nt(nthreads))
+    if rc != 0:
+        raise ValueError("orc_albedo_kinks failed")
+    return tuple(outs)
+
+
+# First-order rounding bound of the reflected direction's z in the FP32
+# estimator kernels, in units of 2^-24: (HORIZON_C0 + HORIZON_C1 kappa).  The
+# kernels' normal is within (8 + 48 kappa) 2^-24 of the exact one (the cap
+# sampler's count); wl = 2 (wo.h) h - wo multiplies that by 4 and adds the
+# roundings of the dot product, the reflection and wo's normalisation.
+HORIZON_C0 = 44.0
+HORIZON_C1 = 192.0
+
+
+def albedo_horizon_band(wo, ax, ay, nsamples, seed, f0=1.0, c0=HORIZON_C0, c1=HORIZON_C1,
+                        kappa_max=float("inf"), units=None, nthreads=0):
+    """Per cell: (bound on |d/d alpha_x|, |d/d alpha_y|, |d/d theta_o| of the
+    change a side flip of near-horizon samples can make, count of those
+    samples).  See orc_albedo_horizon_band in oracle.cpp."""
+    wo, n, ax, ay, ns, un, f0 = _cells(wo, ax, ay, nsamples, units, f0)
+    outs = [np.zeros(n) for _ in range(3)]
+    cnt = np.zeros(n, dtype=np.int64)
+    rc = _load().orc_albedo_horizon_band(n, *[_p(c) for c in wo], _p(ax), _p(ay),
+                                         ns.ctypes.data_as(_i64),
+                                         None if un is None else un.ctypes.data_as(_u32),
+                                         seed, _p(f0), float(c0), float(c1), float(kappa_max),
+                                         *[_p(c) for c in outs], cnt.ctypes.data_as(_i64),
+                                         _nt(nthreads))
+    if rc != 0:
+        raise ValueError("orc_albedo_horizon_band failed")
+    return (*outs, cnt)
 
 
 def _lobes(lobes):

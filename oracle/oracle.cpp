@@ -48,6 +48,16 @@
 //   * grad_theta_o is the derivative along the meridian of wo at fixed
 //     azimuth: dwo/dtheta = (cos t cos p, cos t sin p, -sin t); at the pole
 //     the azimuth is taken as 0.
+//
+// Precision: double, except where double is not enough for the tolerance the
+// oracle checks.  A sampled normal near the rim of the cap, seen from the
+// side opposite to wi, is the half vector of two nearly opposite unit
+// vectors: forming it literally loses 2^-53 times the conditioning
+// kappa = max(1, ax, ay) / |M^-T (c + wi_std)| (up to 2^24 for 24-bit
+// uniforms), and the pdf of Eq. (1) at that normal is as sensitive.  The
+// sampler therefore evaluates every tuple in double, and again, with the same
+// code, in quadruple precision (__float128) when the double result has
+// kappa > 1e4; the outputs are the double roundings of that evaluation.
 
 #include <cmath>
 #include <cstdint>
@@ -55,6 +65,7 @@
 #include <thread>
 #include <vector>
 #include <algorithm>
+#include <quadmath.h>
 
 namespace {
 
@@ -153,6 +164,21 @@ inline Dual3 sqrt(const Dual3& a) {
 inline double value(double x) { return x; }
 inline double value(const Dual3& x) { return x.v; }
 inline double sqrt_(double x) { return std::sqrt(x); }
+
+// Quadruple precision for the ill-conditioned samples of the sampler.
+using Quad = __float128;
+inline double value(Quad x) { return (double)x; }
+inline Quad sqrt_(Quad x) { return sqrtq(x); }
+// The scalar type of a sampler's constants: double, except under Quad.
+template <class T> struct ScalarOf { using type = double; };
+template <> struct ScalarOf<Quad> { using type = Quad; };
+inline double cos_(double x) { return std::cos(x); }
+inline double sin_(double x) { return std::sin(x); }
+inline Quad cos_(Quad x) { return cosq(x); }
+inline Quad sin_(Quad x) { return sinq(x); }
+template <class S> S pi_of();
+template <> inline double pi_of<double>() { return kPi; }
+template <> inline Quad pi_of<Quad>() { return M_PIq; }
 inline Dual3 sqrt_(const Dual3& x) { return sqrt(x); }
 
 template <class T>
@@ -184,42 +210,58 @@ T max0(const T& x) { return value(x) > 0.0 ? x : T(0.0); }
 // direction wi, which is unit and above the horizon).
 // ---------------------------------------------------------------------------
 
-// Spherical-cap sampler, Sec. 3.3: draw c uniformly on the cap of directions
-// with z in (-z_i, 1] (azimuth 2 pi u1, height from u2 with u2 = 0 at the
-// apex), and return the half vector c + wi without normalising it.
+// Spherical-cap sampler, Sec. 3.2-3.3.  The visible normals of the
+// hemisphere seen from wi are the half vectors between wi and directions c
+// drawn uniformly on the part of the unit sphere with c_z > -wi_z (the
+// directions whose half vector with wi lies in the upper hemisphere).  By
+// Archimedes' hat-box theorem the zone of the unit sphere above height t has
+// area 2 pi (1 - t), so a uniform point of that cap has a uniform height:
+// P(c_z >= t) = (1 - t) / (1 + wi_z) on (-wi_z, 1]; its azimuth is uniform.
+// u2 selects the height (u2 = 0 at the apex), u1 the azimuth.  Returns
+// wi + c without normalising it.
 template <class T>
 Vec3<T> hemisphere_cap(double u1, double u2, const Vec3<T>& wi) {
-    double phi = 2.0 * kPi * u1;
-    T z = (1.0 - u2) * (T(1.0) + wi.z) - wi.z;
-    T sin_theta = sqrt_(clamp01(T(1.0) - z * z));
-    Vec3<T> c{sin_theta * std::cos(phi), sin_theta * std::sin(phi), z};
-    return Vec3<T>{c.x + wi.x, c.y + wi.y, c.z + wi.z};
+    using S = typename ScalarOf<T>::type;
+    const T height = T(1.0) - S(u2) * (T(1.0) + wi.z);
+    const T radius = sqrt_(clamp01(T(1.0) - height * height));
+    const S azimuth = S(2.0) * pi_of<S>() * S(u1);
+    const Vec3<T> c{radius * cos_(azimuth), radius * sin_(azimuth), height};
+    return Vec3<T>{wi.x + c.x, wi.y + c.y, wi.z + c.z};
 }
 
-// Heitz's cross-section sampler (Sec. 2, as refactored in the paper):
-// orthonormal basis (w1, w2) around wi, polar sample of the unit disk, warp of
-// its second coordinate towards the projected hemisphere's cross section, and
-// reprojection onto the hemisphere.
+// Heitz's cross-section sampler (JCGT 7(4), 2018; the paper's Sec. 2
+// baseline).  Seen from wi, the visible hemisphere projects onto the plane
+// orthogonal to wi as half of the unit disk joined to half of an ellipse
+// whose short axis is wi_z; its visible normals are the points of that
+// projected area, drawn uniformly, lifted back onto the hemisphere.  A
+// uniform point of the unit disk (radius sqrt(u2), azimuth 2 pi u1: the same
+// roles as the cap's) is mapped onto the projected area by moving its second
+// coordinate, along lines of constant first coordinate, from the full
+// disk's chord onto the chord of the half disk + half ellipse: with
+// s = (1 + wi_z) / 2 (the fraction of the projected area on the disk side),
+// d2 -> (1 - s) sqrt(1 - d1^2) + s d2.
 template <class T>
 Vec3<T> hemisphere_disk2018(double u1, double u2, const Vec3<T>& wi) {
-    T tmp = wi.x * wi.x + wi.y * wi.y;
-    Vec3<T> w1;
-    if (value(tmp) > 0.0) {
-        T inv = T(1.0) / sqrt_(tmp);
-        w1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};
-    } else {
-        w1 = Vec3<T>{T(1.0), T(0.0), T(0.0)};
+    // frame (e1, e2, wi): e1 horizontal and orthogonal to wi
+    const T horiz = wi.x * wi.x + wi.y * wi.y;
+    Vec3<T> e1{T(1.0), T(0.0), T(0.0)};
+    if (value(horiz) > 0.0) {
+        const T inv = T(1.0) / sqrt_(horiz);
+        e1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};
     }
-    Vec3<T> w2 = cross(wi, w1);
-    double phi = 2.0 * kPi * u1;
-    double r = std::sqrt(u2);
-    T t1 = T(r * std::cos(phi));
-    T t2 = T(r * std::sin(phi));
-    T s = (T(1.0) + wi.z) / 2.0;
-    t2 = (T(1.0) - s) * sqrt_(T(1.0) - t1 * t1) + s * t2;
-    T ti = sqrt_(max0(T(1.0) - t1 * t1 - t2 * t2));
-    return Vec3<T>{t1 * w1.x + t2 * w2.x + ti * wi.x, t1 * w1.y + t2 * w2.y + ti * wi.y,
-                   t1 * w1.z + t2 * w2.z + ti * wi.z};
+    const Vec3<T> e2 = cross(wi, e1);
+    // uniform point of the unit disk
+    using S = typename ScalarOf<T>::type;
+    const S rad = sqrt_(S(u2)), ang = S(2.0) * pi_of<S>() * S(u1);
+    const T d1 = T(rad * cos_(ang));
+    T d2 = T(rad * sin_(ang));
+    // onto the projected visible area
+    const T frac_disk = (T(1.0) + wi.z) / 2.0;
+    d2 = frac_disk * d2 + (T(1.0) - frac_disk) * sqrt_(T(1.0) - d1 * d1);
+    // lift onto the hemisphere: the normal's component along wi
+    const T lift = sqrt_(max0(T(1.0) - d1 * d1 - d2 * d2));
+    return Vec3<T>{d1 * e1.x + d2 * e2.x + lift * wi.x, d1 * e1.y + d2 * e2.y + lift * wi.y,
+                   d1 * e1.z + d2 * e2.z + lift * wi.z};
 }
 
 // General VNDF sampler (Sec. 2, "Importance Sampling"): warp wi by M^-1 =
@@ -240,7 +282,10 @@ Vec3<T> sample_vndf(double u1, double u2, const Vec3<T>& wi, const T& ax, const 
 
 // Hemisphere NDF, Eq. (3): 1/pi above the horizon.
 template <class T>
-T ndf_std(const Vec3<T>& wm) { return value(wm.z) > 0.0 ? T(1.0 / kPi) : T(0.0); }
+T ndf_std(const Vec3<T>& wm) {
+    using S = typename ScalarOf<T>::type;
+    return value(wm.z) > 0.0 ? T(S(1.0) / pi_of<S>()) : T(0.0);
+}
 
 // Cross-sectional area of the hemisphere seen from wi, Eq. (4).
 template <class T>
@@ -255,15 +300,29 @@ T vndf_std(const Vec3<T>& wm, const Vec3<T>& wi) {
 // GGX VNDF as a linearly transformed hemisphere VNDF, Eq. (1): the
 // hemisphere VNDF of M^T wm / |M^T wm| seen from M^-1 wi / |M^-1 wi|, times
 // the Jacobian |det M^T| / |M^T wm|^3, with M = diag(1/ax, 1/ay, 1).
-double vndf_pdf(const Vec3<double>& wm, const Vec3<double>& wi, double ax, double ay) {
-    if (!(wi.z > 0.0) || !(ax > 0.0) || !(ay > 0.0)) return 0.0;
-    Vec3<double> mtwm{wm.x / ax, wm.y / ay, wm.z};
-    double len = std::sqrt(dot(mtwm, mtwm));
-    Vec3<double> wm_std{mtwm.x / len, mtwm.y / len, mtwm.z / len};
-    Vec3<double> wi_std = normalize(Vec3<double>{wi.x * ax, wi.y * ay, wi.z});
-    double det = 1.0 / (ax * ay);
+template <class T>
+T vndf_pdf(const Vec3<T>& wm, const Vec3<T>& wi, T ax, T ay) {
+    if (!(value(wi.z) > 0.0) || !(value(ax) > 0.0) || !(value(ay) > 0.0)) return T(0.0);
+    Vec3<T> mtwm{wm.x / ax, wm.y / ay, wm.z};
+    T len = sqrt_(dot(mtwm, mtwm));
+    Vec3<T> wm_std{mtwm.x / len, mtwm.y / len, mtwm.z / len};
+    Vec3<T> wi_std = normalize(Vec3<T>{wi.x * ax, wi.y * ay, wi.z});
+    T det = T(1.0) / (ax * ay);
     return vndf_std(wm_std, wi_std) * det / (len * len * len);
 }
+
+// Conditioning of a cap sample (see the header): max(1, ax, ay) / L with
+// L = |M^-T hs| and |hs| = 2 wi_std . h_std, from the sampled normal h.
+double cap_conditioning(const Vec3<double>& h, const Vec3<double>& wi, double ax, double ay) {
+    Vec3<double> mth{h.x / ax, h.y / ay, h.z};
+    double len = std::sqrt(dot(mth, mth));
+    Vec3<double> wi_std = normalize(Vec3<double>{wi.x * ax, wi.y * ay, wi.z});
+    double hs = 2.0 * dot(mth, wi_std) / len;
+    if (!(hs > 0.0)) return HUGE_VAL;
+    return std::max(1.0, std::max(ax, ay)) * len / hs;
+}
+
+const double kQuadKappa = 1e4;
 
 // GGX NDF, Appendix A: the hemisphere NDF of M^T wm / |M^T wm| times the
 // Jacobian |det M^T| / |M^T wm|^4.
@@ -636,8 +695,15 @@ int32_t orc_vndf_sample(int64_t n, const double* wix, const double* wiy, const d
             return;
         }
         Vec3<double> h = sample_vndf(r1, r2, wi, a, b, method);
+        double p = pdf ? vndf_pdf(h, wi, a, b) : 0.0;
+        if (cap_conditioning(h, wi, a, b) > kQuadKappa) {
+            const Vec3<Quad> wq{(Quad)wi.x, (Quad)wi.y, (Quad)wi.z};
+            const Vec3<Quad> hq = sample_vndf(r1, r2, wq, (Quad)a, (Quad)b, method);
+            h = Vec3<double>{(double)hq.x, (double)hq.y, (double)hq.z};
+            if (pdf) p = (double)vndf_pdf(hq, wq, (Quad)a, (Quad)b);
+        }
         hx[i] = h.x; hy[i] = h.y; hz[i] = h.z;
-        if (pdf) pdf[i] = vndf_pdf(h, wi, a, b);
+        if (pdf) pdf[i] = p;
     });
     return 0;
 }
@@ -765,6 +831,110 @@ int32_t orc_albedo_fd(int64_t ncells, const double* wox, const double* woy, cons
                    cell_albedo(wo, a, b - step, n, seed, unit, f0[c], 0)) / (2.0 * step);
         g_theta[c] = (cell_albedo(at(theta + step), a, b, n, seed, unit, f0[c], 0) -
                       cell_albedo(at(theta - step), a, b, n, seed, unit, f0[c], 0)) / (2.0 * step);
+    });
+    return 0;
+}
+
+// Samples whose estimator term changes between zero and non-zero within a
+// central-difference step (the reflection crosses the horizon there): per
+// cell and parameter (alpha_x, alpha_y, theta_o) the number of samples k
+// whose term at the parameter minus step, at it and at it plus step is zero
+// at some of the three and non-zero at others.  There the term has a kink,
+// so a central difference over the step does not approximate its slope.
+int32_t orc_albedo_kinks(int64_t ncells, const double* wox, const double* woy, const double* woz,
+                         const double* ax, const double* ay, const int64_t* nsamples,
+                         const uint32_t* units, uint64_t seed, double step, int64_t* k_ax,
+                         int64_t* k_ay, int64_t* k_theta, int32_t nthreads) {
+    if (ncells < 0 || !(step > 0.0)) return -1;
+    parallel_for(ncells, nthreads, [&](int64_t c) {
+        uint32_t unit = units ? units[c] : (uint32_t)c;
+        int64_t n = nsamples[c];
+        k_ax[c] = 0; k_ay[c] = 0; k_theta[c] = 0;
+        if (n <= 0 || !(woz[c] > 0.0) || !(ax[c] > 0.0) || !(ay[c] > 0.0)) return;
+        Vec3<double> wo = unit_view(wox[c], woy[c], woz[c]);
+        double rho = std::sqrt(wo.x * wo.x + wo.y * wo.y);
+        double theta = std::atan2(rho, wo.z);
+        double phi = rho > 0.0 ? std::atan2(wo.y, wo.x) : 0.0;
+        auto at = [&](double th) {
+            return Vec3<double>{std::sin(th) * std::cos(phi), std::sin(th) * std::sin(phi),
+                                std::cos(th)};
+        };
+        const Vec3<double> wm = at(theta - step), wp = at(theta + step);
+        double a = ax[c], b = ay[c];
+        auto mixed = [](double x, double y, double z) {
+            int live = (x != 0.0) + (y != 0.0) + (z != 0.0);
+            return live != 0 && live != 3;
+        };
+        for (int64_t k = 0; k < n; ++k) {
+            double u1, u2;
+            stream_uniforms(seed, kTagAlbedo, unit, (uint64_t)k, &u1, &u2);
+            double w0 = albedo_term(wo, a, b, u1, u2, 1.0, 0);
+            k_ax[c] += mixed(albedo_term(wo, a - step, b, u1, u2, 1.0, 0), w0,
+                             albedo_term(wo, a + step, b, u1, u2, 1.0, 0));
+            k_ay[c] += mixed(albedo_term(wo, a, b - step, u1, u2, 1.0, 0), w0,
+                             albedo_term(wo, a, b + step, u1, u2, 1.0, 0));
+            k_theta[c] += mixed(albedo_term(wm, a, b, u1, u2, 1.0, 0), w0,
+                                albedo_term(wp, a, b, u1, u2, 1.0, 0));
+        }
+    });
+    return 0;
+}
+
+// Horizon band of an FP32 evaluation of the estimator.  A GPU sample whose
+// reflected direction lies within its own rounding error of the horizon may
+// land on the other side than the exact sample; its weight is continuous
+// there but the weight's slope jumps from the live side's to 0.  Per cell,
+// over the samples whose exact wb_z lies within (c0 + c1 kappa) 2^-24 of 0
+// (kappa: the sample's conditioning, as for the sampler), this returns their
+// count and (1/N) sum of |d/dp| of the live side's weight F G2 / G1(wa) for
+// p = alpha_x, alpha_y, theta_o, with G1(wb) continued below the horizon by
+// its hemisphere form 2 z / (1 + z) -- the most a change of side of those
+// samples can move the gradient.  Samples with kappa > kappa_max are left
+// out (the kernels evaluate those in double precision).
+int32_t orc_albedo_horizon_band(int64_t ncells, const double* wox, const double* woy,
+                                const double* woz, const double* ax, const double* ay,
+                                const int64_t* nsamples, const uint32_t* units, uint64_t seed,
+                                const double* f0, double c0, double c1, double kappa_max,
+                                double* b_ax, double* b_ay, double* b_theta, int64_t* count,
+                                int32_t nthreads) {
+    if (ncells < 0) return -1;
+    parallel_for(ncells, nthreads, [&](int64_t c) {
+        uint32_t unit = units ? units[c] : (uint32_t)c;
+        int64_t n = nsamples[c];
+        b_ax[c] = 0.0; b_ay[c] = 0.0; b_theta[c] = 0.0; count[c] = 0;
+        if (n <= 0 || !(woz[c] > 0.0) || !(ax[c] > 0.0) || !(ay[c] > 0.0)) return;
+        Vec3<double> wo = unit_view(wox[c], woy[c], woz[c]);
+        Vec3<double> t = meridian_tangent(wo);
+        Vec3<Dual3> wo_d{Dual3(wo.x, 0.0, 0.0, t.x), Dual3(wo.y, 0.0, 0.0, t.y),
+                         Dual3(wo.z, 0.0, 0.0, t.z)};
+        Dual3 a(ax[c], 1.0, 0.0, 0.0), b(ay[c], 0.0, 1.0, 0.0);
+        NeumaierSum<double> s0, s1, s2;
+        for (int64_t k = 0; k < n; ++k) {
+            double u1, u2;
+            stream_uniforms(seed, kTagAlbedo, unit, (uint64_t)k, &u1, &u2);
+            Vec3<double> wm = sample_vndf(u1, u2, wo, ax[c], ay[c], 0);
+            double cm = dot(wm, wo);
+            double wbz = 2.0 * cm * wm.z - wo.z;
+            const double kap = cap_conditioning(wm, wo, ax[c], ay[c]);
+            if (kap > kappa_max) continue;
+            double band = (c0 + c1 * kap) * 0x1p-24;
+            if (!(std::fabs(wbz) <= band)) continue;
+            ++count[c];
+            Vec3<Dual3> wmd = sample_vndf(u1, u2, wo_d, a, b, 0);
+            Dual3 cd = dot(wmd, wo_d);
+            Vec3<Dual3> wb{2.0 * cd * wmd.x - wo_d.x, 2.0 * cd * wmd.y - wo_d.y,
+                           2.0 * cd * wmd.z - wo_d.z};
+            Vec3<Dual3> wb_std = normalize(Vec3<Dual3>{wb.x * a, wb.y * b, wb.z});
+            Dual3 gl = wb_std.z / sigma_std(wb_std);
+            Dual3 go = smith_g1(wmd, wo_d, a, b);
+            Dual3 g2 = go * gl / (go + gl - go * gl);
+            Dual3 w = fresnel_schlick(cd, f0[c]) * g2 / go;
+            s0.add(std::fabs(w.d[0])); s1.add(std::fabs(w.d[1])); s2.add(std::fabs(w.d[2]));
+        }
+        double inv = 1.0 / (double)n;
+        b_ax[c] = s0.result() * inv;
+        b_ay[c] = s1.result() * inv;
+        b_theta[c] = s2.result() * inv;
     });
     return 0;
 }

@@ -22,6 +22,7 @@ import pytest
 from scipy import integrate
 
 from _hemi import hemi_grid
+import workloads
 
 
 def _normal_incidence(alpha, f0):
@@ -147,6 +148,47 @@ def test_dual_vs_central_differences(orc):
     fd = orc.albedo_fd(wo, ax, ay, N, seed=3, step=1e-7)
     for g, f in zip((gx, gy, gt), fd):
         assert np.all(np.abs(g - f) <= 1e-7 + 1e-6 * np.abs(g)), (g, f)
+
+
+FD_STEP = 1e-4      # the gradient configuration's central-difference step
+FD_MIN_ALPHA = 0.2  # both roughness values at least 2000 steps
+
+
+def fd_cells(orc, n):
+    """The gradient workload's 32 x 32 grid (seed 3) at n samples per cell,
+    and per parameter the cells where FD(1e-4) approximates the derivative of
+    the estimator: no sample's term changes between zero and non-zero within
+    the step (orc.albedo_kinks: the reflection would cross the horizon, a
+    kink of the term), and both roughness values at least FD_MIN_ALPHA, so
+    that the central difference's truncation error (h^2 / 6) d^3A / dp^3,
+    which grows as (h / alpha)^2 |dA/dp|, stays below 1e-5 |dA/dp|."""
+    gg = workloads.grad_grid(32, seed=3)
+    wx, wy, wz = workloads.view_from_angles(gg["theta"], gg["phi"])
+    g = {"wx": wx, "wy": wy, "wz": wz, "ax": gg["ax"], "ay": gg["ay"]}
+    wo = (wx, wy, wz)
+    kinks = orc.albedo_kinks(wo, g["ax"], g["ay"], n, 3, step=FD_STEP)
+    smooth = np.minimum(g["ax"], g["ay"]) >= FD_MIN_ALPHA
+    return g, [(k == 0) & smooth for k in kinks], kinks, smooth
+
+
+def test_dual_vs_central_differences_at_the_configured_step(orc):
+    """Central differences with the configuration's step 1e-4 (same random
+    numbers) against the dual-number gradient, within 1e-6 + 1e-5 |g|, on the
+    cells of the 32 x 32 gradient grid (2^12 samples per cell) where the step
+    resolves the derivative (see fd_cells); the cells left out are counted
+    with their reason."""
+    n = 1 << 12
+    g, ok, kinks, smooth = fd_cells(orc, n)
+    wo = (g["wx"], g["wy"], g["wz"])
+    _, gx, gy, gt = orc.albedo_grad(wo, g["ax"], g["ay"], n, 3)
+    fd = orc.albedo_fd(wo, g["ax"], g["ay"], n, 3, step=FD_STEP)
+    for name, d, f, m, k in zip(("alpha_x", "alpha_y", "theta_o"), (gx, gy, gt), fd, ok, kinks):
+        r = np.abs(d - f) / (1e-6 + 1e-5 * np.abs(d))
+        print(f"d/d {name}: {m.sum()} cells checked (worst {r[m].max():.3f} of the bound); "
+              f"left out: {(k > 0).sum()} with horizon kinks within the step, "
+              f"{(~smooth & (k == 0)).sum()} more with roughness below {FD_MIN_ALPHA}")
+        assert m.sum() >= 60
+        assert np.all(r[m] <= 1.0)
 
 
 def test_gradient_at_normal_incidence(orc):

@@ -18,21 +18,28 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.cpp")
 PINS = ["tests/test_oracle_rng.py", "tests/test_oracle_sampler.py", "tests/test_oracle_pdf.py",
         "tests/test_oracle_albedo.py", "tests/test_oracle_radiance.py",
-        "tests/test_oracle_dielectric.py"]
+        "tests/test_oracle_dielectric.py", "tests/test_oracle_horizon_band.py"]
 
 # (name, text in oracle.cpp, replacement)
 MUTANTS = [
     ("philox key bump", "k[0] += kPhiloxW0;", "k[0] += kPhiloxW1;"),
     ("philox word order", "uint32_t n1 = lo1;", "uint32_t n1 = hi1;"),
     ("uniform bits", "(double)(w >> 8) * (1.0 / 16777216.0)", "(double)(w >> 9) * (1.0 / 16777216.0)"),
-    ("cap height sign", "T z = (1.0 - u2) * (T(1.0) + wi.z) - wi.z;",
-     "T z = (1.0 - u2) * (T(1.0) + wi.z) + wi.z;"),
-    ("u roles swapped", "double phi = 2.0 * kPi * u1;\n    T z = (1.0 - u2)",
-     "double phi = 2.0 * kPi * u2;\n    T z = (1.0 - u1)"),
-    ("half vector drops wi", "return Vec3<T>{c.x + wi.x, c.y + wi.y, c.z + wi.z};",
-     "return Vec3<T>{c.x + wi.x, c.y + wi.y, c.z};"),
-    ("stretch transposed", "normalize(Vec3<T>{wi.x * ax, wi.y * ay, wi.z});",
-     "normalize(Vec3<T>{wi.x * ay, wi.y * ax, wi.z});"),
+    ("cap height sign", "const T height = T(1.0) - S(u2) * (T(1.0) + wi.z);",
+     "const T height = T(1.0) - S(u2) * (T(1.0) - wi.z);"),
+    ("u roles swapped", "const T height = T(1.0) - S(u2) * (T(1.0) + wi.z);",
+     "const T height = T(1.0) - S(u1) * (T(1.0) + wi.z);"),
+    ("cap azimuth from the height's number", "const S azimuth = S(2.0) * pi_of<S>() * S(u1);",
+     "const S azimuth = S(2.0) * pi_of<S>() * S(u2);"),
+    ("horizon band without the G1 division", "Dual3 w = fresnel_schlick(cd, f0[c]) * g2 / go;",
+     "Dual3 w = fresnel_schlick(cd, f0[c]) * g2;"),
+    ("no quadruple precision at the cap's rim", "if (cap_conditioning(h, wi, a, b) > kQuadKappa) {",
+     "if (cap_conditioning(h, wi, a, b) > 1e300) {"),
+    ("half vector drops wi", "return Vec3<T>{wi.x + c.x, wi.y + c.y, wi.z + c.z};",
+     "return Vec3<T>{wi.x + c.x, wi.y + c.y, c.z};"),
+    ("stretch transposed",
+     "Vec3<T> wi_std = normalize(Vec3<T>{wi.x * ax, wi.y * ay, wi.z});\n    Vec3<T> wm_std = method",
+     "Vec3<T> wi_std = normalize(Vec3<T>{wi.x * ay, wi.y * ax, wi.z});\n    Vec3<T> wm_std = method"),
     ("unstretch inverted", "return normalize(Vec3<T>{wm_std.x * ax, wm_std.y * ay, wm_std.z});",
      "return normalize(Vec3<T>{wm_std.x / ax, wm_std.y / ay, wm_std.z});"),
     ("pdf Jacobian power", "return vndf_std(wm_std, wi_std) * det / (len * len * len);",
@@ -52,8 +59,10 @@ MUTANTS = [
     ("dual quotient rule", "(a.d[0] - q * b.d[0]) / b.v", "(a.d[0] + q * b.d[0]) / b.v"),
     ("theta tangent sign", "return Vec3<double>{wo.z * wo.x / rho, wo.z * wo.y / rho, -rho};",
      "return Vec3<double>{wo.z * wo.x / rho, wo.z * wo.y / rho, rho};"),
-    ("disk warp weight", "T s = (T(1.0) + wi.z) / 2.0;", "T s = (T(1.0) - wi.z) / 2.0;"),
-    ("disk basis", "w1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};", "w1 = Vec3<T>{wi.y * inv, wi.x * inv, T(0.0)};"),
+    ("disk warp weight", "const T frac_disk = (T(1.0) + wi.z) / 2.0;",
+     "const T frac_disk = (T(1.0) - wi.z) / 2.0;"),
+    ("disk basis", "e1 = Vec3<T>{-wi.y * inv, wi.x * inv, T(0.0)};",
+     "e1 = Vec3<T>{wi.y * inv, wi.x * inv, T(0.0)};"),
     ("lobe exponent", "l += p[4] * std::exp(p[3] * (c - 1.0));", "l += p[4] * std::exp(p[3] * (1.0 - c));"),
     ("inverse azimuth swapped", "double t = std::atan2(c.y, c.x) / (2.0 * kPi);",
      "double t = std::atan2(c.x, c.y) / (2.0 * kPi);"),
@@ -91,8 +100,8 @@ def _run_mutant(name, old, new, tmp):
     with open(os.path.join(path, "oracle.cpp"), "w") as f:
         f.write(src.replace(old, new))
     lib = os.path.join(path, "liboracle.so")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
-                    os.path.join(path, "oracle.cpp"), "-o", lib], check=True)
+    subprocess.run(["g++", "-O2", "-std=gnu++17", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
+                    os.path.join(path, "oracle.cpp"), "-o", lib, "-lquadmath"], check=True)
     env = dict(os.environ, CAPVNDF_ORACLE_LIB=lib, CAPVNDF_ORACLE_THREADS="1",
                OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",

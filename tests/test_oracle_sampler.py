@@ -227,3 +227,61 @@ def test_oracle_inverse_map_round_trip(orc):
                                    np.array([1.0, -0.5, 0.0, 1.0])),
                                   np.array([0.5, 0.5, 0.5, 0.0]), np.full(n, 0.5))
     assert np.all(bad1 == -1.0) and np.all(bad2 == -1.0)
+
+
+def _degenerate_tuples():
+    """Rim (u2 = 1 - 2^-24) and apex of the cap, quadrant azimuths, normal
+    incidence, near-grazing views, extreme roughness: the GPU tests' set."""
+    u2s = [0.0, 2.0 ** -24, 0.5, 1.0 - 2.0 ** -24]
+    u1s = [0.0, 0.25, 0.5, 0.75, 1.0 - 2.0 ** -24]
+    views = [(0.0, 0.0, 1.0), (np.sqrt(1 - 1e-6), 0.0, 1e-3), (0.6, 0.0, 0.8),
+             (0.0, -np.sqrt(1 - 1e-8), 1e-4)]
+    alphas = [(1.0, 1.0), (1e-3, 1e-3), (1e-5, 0.5), (0.5, 1e-5), (1.0, 1e-3)]
+    rows = [(v, a, p, q) for v in views for a in alphas for p in u1s for q in u2s]
+    f = np.float32
+    w = tuple(np.array([r[0][i] for r in rows], f).astype(np.float64) for i in range(3))
+    ax = np.array([r[1][0] for r in rows], f).astype(np.float64)
+    ay = np.array([r[1][1] for r in rows], f).astype(np.float64)
+    u1 = np.array([r[2] for r in rows], f).astype(np.float64)
+    u2 = np.array([r[3] for r in rows], f).astype(np.float64)
+    return w, ax, ay, u1, u2
+
+
+def test_ill_conditioned_samples(orc):
+    """Samples at the rim of the cap opposite to the view, where the half
+    vector is the sum of two nearly opposite unit vectors (conditioning up to
+    about 2^24): the oracle's pdf, evaluated through Eq. (1), equals the fused
+    form L^3 / (pi ax ay (1 + zs) |hs|^2) of the same density (an identity of
+    Appendix A's quantities, evaluated here with 50 significant digits at
+    the oracle's normal) within 1e-8, and the inverse map (Sec. 3.2, also at
+    50 digits) takes the oracle's normal back to its u2 within 1e-9 and to
+    u1 within 1e-8 turns where the cap point is off the axis.  In plain
+    double precision the literal half vector loses up to 6 % of this pdf."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    w, ax, ay, u1, u2 = _degenerate_tuples()
+    h, p = orc.vndf_sample(w, ax, ay, u1=u1, u2=u2)
+    worst_p = worst_u2 = worst_u1 = 0.0
+    for i in range(len(u1)):
+        a, b = mp.mpf(ax[i]), mp.mpf(ay[i])
+        wx, wy, wz = (mp.mpf(x[i]) for x in w)
+        l = mp.sqrt((a * wx) ** 2 + (b * wy) ** 2 + wz ** 2)
+        ws = (a * wx / l, b * wy / l, wz / l)
+        hx, hy, hz = (mp.mpf(h[i, j]) for j in range(3))
+        mt = (hx / a, hy / b, hz)
+        n = mp.sqrt(sum(x * x for x in mt))
+        hstd = tuple(x / n for x in mt)
+        d = sum(x * y for x, y in zip(hstd, ws))
+        hs_len = 2 * d                      # |hs| = 2 ws . h_std (|c| = |ws| = 1)
+        L = hs_len / n                       # |M^-T hs| with hs = |hs| h_std
+        fused = L ** 3 / (mp.pi * a * b * (1 + ws[2]) * hs_len ** 2)
+        worst_p = max(worst_p, abs(float(mp.mpf(p[i]) / fused - 1)))
+        c = tuple(2 * d * x - y for x, y in zip(hstd, ws))  # reflect ws about h_std
+        r2 = 1 - (c[2] + ws[2]) / (1 + ws[2])
+        worst_u2 = max(worst_u2, abs(float(r2) - u2[i]))
+        if mp.sqrt(c[0] ** 2 + c[1] ** 2) > 1e-6:
+            t = float(mp.atan2(c[1], c[0]) / (2 * mp.pi)) % 1.0
+            dt = abs(t - u1[i])
+            worst_u1 = max(worst_u1, min(dt, 1.0 - dt))
+    print(f"ill-conditioned: pdf {worst_p:.2e}, u2 {worst_u2:.2e}, u1 {worst_u1:.2e}")
+    assert worst_p <= 1e-8 and worst_u2 <= 1e-9 and worst_u1 <= 1e-8
