@@ -20,9 +20,9 @@
  *  - Element-wise calls take any n >= 0 that fits in memory: a call longer
  *    than 2^31 elements is enqueued as consecutive launches of 2^31 elements
  *    (results identical to one launch; a HIP error in a later launch leaves
- *    the earlier ones enqueued).  The estimators accept fewer than 2^24
- *    chunks of 16384 samples (about 2.7e11 samples) per call; a cell's
- *    chunks are ceil(nsamples / 16384).
+ *    the earlier ones enqueued).  The table estimators take per-cell
+ *    sample counts (see albedo_workspace_size) and fewer than 2^24 cells
+ *    per call.
  *  - The library never allocates on these calls, except the batch-plan calls
  *    (which own their chunk tables, partial buffers and graph).
  *  - Return value: CAPVNDF_OK (0) or a negative CAPVNDF_ERR_* code.  All
@@ -66,11 +66,13 @@ extern "C" {
 #define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
 #define CAPVNDF_CAP_F64 2  /* spherical cap evaluated in double precision   */
 
-/* Version of this ABI (major * 10000 + minor * 100 + patch): 2.1.0.  Major 2
+/* Version of this ABI (major * 10000 + minor * 100 + patch): 3.0.0.  Major 3
+ * gave the table estimators per-cell device sample counts and
+ * albedo_workspace_size its (ncells, host counts, with_grad) form; major 2
  * added the `dynamic` field to capvndf_tiling (a layout change) and the
- * CAPVNDF_CAP_F64 method; minor 1 added albedo_view_from_angles and
- * albedo_apply_jacobian. */
-#define CAPVNDF_VERSION 20100
+ * CAPVNDF_CAP_F64 method; minor 1 of major 2 added albedo_view_from_angles
+ * and albedo_apply_jacobian. */
+#define CAPVNDF_VERSION 30000
 int32_t capvndf_version(void);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -205,12 +207,32 @@ int32_t dielectric_pdf(int64_t n, const float* wix, const float* wiy, const floa
                        const float* ay, float eta, float* pdf, void* stream);
 
 /*
- * albedo_workspace_size -- bytes of device workspace needed for ncells cells
- * of nsamples samples each by albedo_estimate (mode 0),
- * albedo_estimate_backward (mode 1) or albedo_value_and_grad (mode 2; enough
- * with or without gradients).  Returns 0 for invalid sizes or modes.
+ * Sample counts of the table estimators.  Appendix A's estimator of a cell
+ * (one outgoing direction) averages N samples; every cell has its own N,
+ * given as a DEVICE array `nsamples` of int64 (8-byte aligned), N in
+ * [0, 2^40).  A cell of N samples is cut into ceil(ceil(N / 2) / 8192)
+ * chunks of 16384 samples.  A call gives each cell a number of slots (blocks)
+ * chosen on the host from the cell count and the workspace: slot s of a cell
+ * sums the cell's chunks s, s + slots, ... into one compensated partial, and
+ * the partials are merged in slot order, so results are bitwise reproducible
+ * for the same inputs and workspace size.  A count outside [0, 2^40) gives
+ * NaN outputs for that cell; a count of 0 gives 0.  At most 2^24 - 1 cells
+ * per call.
+ *
+ * albedo_workspace_size -- bytes of device workspace for ncells cells:
+ *   nsamples_host [ncells] HOST copy of the per-cell counts, or NULL.  With
+ *                 the counts, the size covers slots up to the largest cell's
+ *                 chunk count only (fewer, fuller blocks); without, the
+ *                 most slots a call of ncells cells uses.
+ *   with_grad     0: enough for albedo_estimate, albedo_value_and_grad
+ *                 without gradients and radiance_estimate; 1: enough for
+ *                 every table estimator (two or four partial sums per slot).
+ * Any workspace of at least ncells * 8 * (partial sums of the call) bytes
+ * works; a larger one (up to this size) lets the call use more slots.
+ * Returns 0 for ncells <= 0, ncells >= 2^24, with_grad not 0 or 1, or a host
+ * count outside [0, 2^40).
  */
-size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t mode);
+size_t albedo_workspace_size(int64_t ncells, const int64_t* nsamples_host, int32_t with_grad);
 
 /*
  * albedo_estimate -- directional albedo per cell: the Monte Carlo estimator
@@ -221,23 +243,23 @@ size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t mode);
  * below the horizon weigh 0 but count.  With Schlick's Fresnel
  * F = F0 + (1 - F0)(1 - wo.h)^5 the albedo is linear in F0, so one stream
  * gives both sums:
- *   s_f1[c] = (1/N) sum G2/G1,  s_f5[c] = (1/N) sum G2/G1 (1 - wo.h)^5,
+ *   s_f1[c] = (1/N_c) sum G2/G1,  s_f5[c] = (1/N_c) sum G2/G1 (1 - wo.h)^5,
  *   A(F0)   = F0 s_f1 + (1 - F0) s_f5.
- * Sums are compensated (TwoSum) and reduced in a fixed order, so results are
- * bitwise reproducible.
+ * Sums are compensated (TwoSum) and reduced in a fixed order.
  *
  *   ncells               number of cells (>= 0)
  *   wox,woy,woz [ncells] view directions (normalised internally; wo_z > 0)
  *   ax, ay      [ncells] roughness
- *   nsamples             samples per cell N (>= 0, < 2^40)
+ *   nsamples    [ncells] device int64: samples N_c of each cell (see above)
  *   seed                 Philox key; cell c uses unit c of tag 3
  *   s_f1, s_f5  [ncells] out
- *   workspace            device scratch of albedo_workspace_size(ncells,
- *                        nsamples, 0) bytes, 16-byte aligned (NULL if 0)
+ *   workspace            device scratch, 16-byte aligned, of
+ *                        albedo_workspace_size(ncells, counts, 0) bytes (at
+ *                        least ncells * 16)
  * Errors: NULL_PTR, BAD_SIZE, MISALIGNED, WORKSPACE (too small), HIP.
  */
 int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy, const float* woz,
-                        const float* ax, const float* ay, int64_t nsamples, uint64_t seed,
+                        const float* ax, const float* ay, const int64_t* nsamples, uint64_t seed,
                         float* s_f1, float* s_f5, void* workspace, size_t workspace_bytes,
                         void* stream);
 
@@ -257,12 +279,13 @@ int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy, cons
  *                    the meridian of wo at fixed azimuth
  *                    (dwo/dtheta = (cos t cos p, cos t sin p, -sin t); at the
  *                    pole the azimuth is taken as 0)
- *   workspace        albedo_workspace_size(ncells, nsamples, 1) bytes
+ *   workspace        albedo_workspace_size(ncells, counts, 1) bytes (at
+ *                    least ncells * 24)
  * Errors: as albedo_estimate.
  */
 int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* woy,
                                  const float* woz, const float* ax, const float* ay,
-                                 int64_t nsamples, uint64_t seed, const float* f0,
+                                 const int64_t* nsamples, uint64_t seed, const float* f0,
                                  const float* grad_albedo, float* grad_ax, float* grad_ay,
                                  float* grad_theta_o, void* workspace, size_t workspace_bytes,
                                  void* stream);
@@ -280,13 +303,14 @@ int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* 
  *   f0          [ncells] Fresnel F0 per cell (NULL = 1)
  *   albedo      [ncells] out: A(F0)
  *   grad_ax, grad_ay, grad_theta_o [ncells] out, all NULL for values only
- *   workspace   albedo_workspace_size(ncells, nsamples, 2) bytes
+ *   workspace   albedo_workspace_size(ncells, counts, 1) bytes (at least
+ *               ncells * 32 with gradients, ncells * 8 without)
  * Errors: as albedo_estimate; NULL_PTR if only some gradient outputs are given.
  */
 int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy,
                               const float* woz, const float* ax, const float* ay,
-                              int64_t nsamples, uint64_t seed, const float* f0, float* albedo,
-                              float* grad_ax, float* grad_ay, float* grad_theta_o,
+                              const int64_t* nsamples, uint64_t seed, const float* f0,
+                              float* albedo, float* grad_ax, float* grad_ay, float* grad_theta_o,
                               void* workspace, size_t workspace_bytes, void* stream);
 
 /*
@@ -305,13 +329,15 @@ int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy
  *               error grows as kappa * 2^-24)
  *   nlobes      0 .. 8 (0 gives zero radiance)
  *   radiance    [ncells] out
- *   workspace   albedo_workspace_size(ncells, nsamples, 0) bytes suffice
+ *   workspace   albedo_workspace_size(ncells, counts, 0) bytes (at least
+ *               ncells * 8)
  * Errors: as albedo_estimate; BAD_SIZE for nlobes outside [0, 8].
  */
 int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy, const float* woz,
-                          const float* ax, const float* ay, const float* f0, int64_t nsamples,
-                          uint64_t seed, const float* lobes, int32_t nlobes, float* radiance,
-                          void* workspace, size_t workspace_bytes, void* stream);
+                          const float* ax, const float* ay, const float* f0,
+                          const int64_t* nsamples, uint64_t seed, const float* lobes,
+                          int32_t nlobes, float* radiance, void* workspace,
+                          size_t workspace_bytes, void* stream);
 
 /*
  * albedo_view_from_angles -- view directions from spherical angles,
@@ -475,6 +501,24 @@ int32_t capvndf_philox_blocks(int64_t n, const uint32_t* ctr, uint32_t key0, uin
  */
 int32_t vndf_microbench(int32_t method, int64_t lanes, int32_t iters, uint64_t seed,
                         uint32_t* out, void* stream);
+
+/*
+ * estimator_microbench -- register-resident benchmark of the estimators'
+ * per-sample arithmetic: each of `lanes` lanes draws one cell (view uniform
+ * over the hemisphere, alpha_x, alpha_y = 10^(-2U)) and runs the per-sample
+ * code of one table estimator on `pairs` Philox pairs of its own stream
+ * (tag 3, unit = lane index) into plain per-lane sums, written as one word
+ * to out[lane] (device, [lanes]).  No loads in the loop, no compensated sums
+ * and no cross-lane reductions: the issue rate of that instruction mix with
+ * nothing else in the way, against which the table kernels are measured.
+ * kind 0: albedo_estimate's two sums; 1: albedo_value_and_grad's value and
+ * adjoint; 2: radiance_estimate's term under the 4 lobes in `lobes` (device
+ * FP32 [20], as radiance_estimate's; ignored for other kinds).
+ * Errors: BAD_SIZE (lanes outside [0, 2^31], pairs < 0), BAD_ARG (kind),
+ * NULL_PTR, MISALIGNED, HIP.
+ */
+int32_t estimator_microbench(int32_t kind, int64_t lanes, int32_t pairs, uint64_t seed,
+                             const float* lobes, uint32_t* out, void* stream);
 
 /*
  * capvndf_stream_probe -- plain streaming kernels with the sampler's arrays,

@@ -20,6 +20,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch  # loads the HIP runtime that libcapvndf.so links against
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -68,14 +69,14 @@ _SIGNATURES = {
     "dielectric_sample": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _U64, _U64, _P,
                            _P, _P, _P, _P, _P], _I32),
     "dielectric_pdf": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _P, _P], _I32),
-    "albedo_workspace_size": ([_I64, _I64, _I32], ctypes.c_size_t),
-    "albedo_estimate": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, ctypes.c_size_t, _P],
+    "albedo_workspace_size": ([_I64, _P, _I32], ctypes.c_size_t),
+    "albedo_estimate": ([_I64, _P, _P, _P, _P, _P, _P, _U64, _P, _P, _P, ctypes.c_size_t, _P],
                         _I32),
-    "albedo_estimate_backward": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, _P, _P, _P,
+    "albedo_estimate_backward": ([_I64, _P, _P, _P, _P, _P, _P, _U64, _P, _P, _P, _P, _P, _P,
                                   ctypes.c_size_t, _P], _I32),
-    "albedo_value_and_grad": ([_I64, _P, _P, _P, _P, _P, _I64, _U64, _P, _P, _P, _P, _P, _P,
+    "albedo_value_and_grad": ([_I64, _P, _P, _P, _P, _P, _P, _U64, _P, _P, _P, _P, _P, _P,
                                ctypes.c_size_t, _P], _I32),
-    "radiance_estimate": ([_I64, _P, _P, _P, _P, _P, _P, _I64, _U64, _P, _I32, _P, _P,
+    "radiance_estimate": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _I32, _P, _P,
                            ctypes.c_size_t, _P], _I32),
     "albedo_view_from_angles": ([_I64, _P, _P, _P, _P, _P, _P], _I32),
     "albedo_apply_jacobian": ([_I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
@@ -91,6 +92,7 @@ _SIGNATURES = {
     "capvndf_uniforms": ([_U64, _U32, _U32, _U64, _I64, _P, _P, _P], _I32),
     "capvndf_philox_blocks": ([_I64, _P, _U32, _U32, _P, _P], _I32),
     "vndf_microbench": ([_I32, _I64, _I32, _U64, _P, _P], _I32),
+    "estimator_microbench": ([_I32, _I64, _I32, _U64, _P, _P, _P], _I32),
     "capvndf_stream_probe": ([_I32, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I32),
 }
 
@@ -161,7 +163,7 @@ def version() -> int:
     return int(load_library().capvndf_version())
 
 
-def vndf_sample(wix, wiy, wiz, ax, ay, u1=None, u2=None, seed=0, index_base=0, method="cap",
+def vndf_sample(wix, wiy, wiz, ax, ay, u1=None, u2=None, seed=0, index_base=0, method="cap_f64",
                 with_pdf=True, out=None, stream=None):
     """GGX VNDF samples h (and pdf) for SoA float32 GPU tensors; see
     include/capvndf.h.  Returns (hx, hy, hz, pdf_or_None)."""
@@ -259,27 +261,65 @@ def dielectric_pdf(wix, wiy, wiz, wox, woy, woz, ax, ay, eta, out=None, stream=N
     return pdf
 
 
-def albedo_workspace_size(ncells: int, nsamples: int, mode: int) -> int:
-    """Workspace bytes: mode 0 albedo_estimate, 1 backward, 2 value_and_grad."""
-    return int(load_library().albedo_workspace_size(ncells, nsamples, int(mode)))
+def albedo_workspace_size(ncells: int, nsamples_host=None, with_grad: int = 0) -> int:
+    """Workspace bytes of the table estimators for ncells cells; nsamples_host
+    (host int64 counts per cell, or None) lets the call use fewer slots."""
+    if nsamples_host is None:
+        ptr = None
+    else:
+        nsamples_host = np.ascontiguousarray(np.asarray(nsamples_host, dtype=np.int64))
+        if nsamples_host.size != ncells:
+            raise ValueError("nsamples_host must have one entry per cell")
+        ptr = nsamples_host.ctypes.data_as(ctypes.c_void_p)
+    return int(load_library().albedo_workspace_size(ncells, ptr, int(with_grad)))
 
 
 def _workspace(nbytes, device):
     return torch.empty(max(1, (nbytes + 3) // 4), dtype=torch.float32, device=device)
 
 
+def _counts(nsamples, n, device):
+    """Per-cell sample counts as (device int64 tensor, host int64 array or
+    None).  An int gives every cell that count; a host sequence or CPU tensor
+    is copied to the device; a GPU tensor is used as it is (no host copy, so
+    the workspace is sized without the counts)."""
+    if isinstance(nsamples, torch.Tensor) and nsamples.is_cuda:
+        _dev(nsamples, "nsamples", torch.int64)
+        _same_len(n, nsamples=nsamples)
+        return nsamples, None
+    if isinstance(nsamples, (int, np.integer)):
+        host = np.full(n, int(nsamples), dtype=np.int64)
+        return torch.full((n,), int(nsamples), dtype=torch.int64, device=device), host
+    if isinstance(nsamples, torch.Tensor):
+        nsamples = nsamples.numpy()
+    host = np.ascontiguousarray(np.asarray(nsamples, dtype=np.int64).reshape(-1))
+    if host.size != n:
+        raise ValueError(f"nsamples has {host.size} entries, expected {n}")
+    return torch.from_numpy(host).to(device), host
+
+
+def _table_setup(wox, n, nsamples, with_grad, workspace):
+    dev_counts, host = _counts(nsamples, n, wox.device)
+    if workspace is None:
+        nbytes = albedo_workspace_size(n, host, with_grad) if n > 0 else 0
+        workspace = _workspace(nbytes, wox.device)
+    else:
+        _dev(workspace, "workspace")
+    return dev_counts, workspace
+
+
 def albedo_estimate(wox, woy, woz, ax, ay, nsamples, seed, workspace=None, stream=None):
-    """(s_f1, s_f5) per cell: A(F0) = F0 s_f1 + (1 - F0) s_f5."""
+    """(s_f1, s_f5) per cell: A(F0) = F0 s_f1 + (1 - F0) s_f5.  nsamples: an
+    int for every cell, or one count per cell (host sequence or int64 tensor)."""
     lib = load_library()
     n = wox.numel()
     for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay).items():
         _dev(t, k)
     _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay)
-    nbytes = albedo_workspace_size(n, nsamples, 0)
-    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    ns, ws = _table_setup(wox, n, nsamples, 0, workspace)
     s1 = torch.empty_like(wox)
     s5 = torch.empty_like(wox)
-    rc = lib.albedo_estimate(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), nsamples,
+    rc = lib.albedo_estimate(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), _ptr(ns),
                              seed, _ptr(s1), _ptr(s5), _ptr(ws), ws.numel() * 4, _stream(stream))
     _check("albedo_estimate", rc)
     return s1, s5
@@ -294,11 +334,10 @@ def albedo_estimate_backward(wox, woy, woz, ax, ay, nsamples, seed, f0=None, gra
                      grad_albedo=grad_albedo).items():
         _dev(t, k)
     _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0, grad_albedo=grad_albedo)
-    nbytes = albedo_workspace_size(n, nsamples, 1)
-    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    ns, ws = _table_setup(wox, n, nsamples, 1, workspace)
     gx, gy, gt = (torch.empty_like(wox) for _ in range(3))
     rc = lib.albedo_estimate_backward(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
-                                      nsamples, seed, _ptr(f0), _ptr(grad_albedo), _ptr(gx),
+                                      _ptr(ns), seed, _ptr(f0), _ptr(grad_albedo), _ptr(gx),
                                       _ptr(gy), _ptr(gt), _ptr(ws), ws.numel() * 4,
                                       _stream(stream))
     _check("albedo_estimate_backward", rc)
@@ -314,12 +353,11 @@ def albedo_value_and_grad(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_g
     for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0).items():
         _dev(t, k)
     _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
-    nbytes = albedo_workspace_size(n, nsamples, 2)
-    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    ns, ws = _table_setup(wox, n, nsamples, 1 if with_grad else 0, workspace)
     a = torch.empty_like(wox)
     g = [torch.empty_like(wox) for _ in range(3)] if with_grad else [None, None, None]
     rc = lib.albedo_value_and_grad(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
-                                   nsamples, seed, _ptr(f0), _ptr(a), *[_ptr(x) for x in g],
+                                   _ptr(ns), seed, _ptr(f0), _ptr(a), *[_ptr(x) for x in g],
                                    _ptr(ws), ws.numel() * 4, _stream(stream))
     _check("albedo_value_and_grad", rc)
     return (a, *g)
@@ -336,11 +374,10 @@ def radiance_estimate(wox, woy, woz, ax, ay, nsamples, seed, lobes, f0=None, wor
     _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
     if lobes.dim() != 2 or lobes.shape[1] != 5:
         raise ValueError("lobes must have shape (nlobes, 5)")
-    nbytes = albedo_workspace_size(n, nsamples, 0)
-    ws = _workspace(nbytes, wox.device) if workspace is None else _dev(workspace, "workspace")
+    ns, ws = _table_setup(wox, n, nsamples, 0, workspace)
     out = torch.empty_like(wox)
     rc = lib.radiance_estimate(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay), _ptr(f0),
-                               nsamples, seed, _ptr(lobes), lobes.shape[0], _ptr(out), _ptr(ws),
+                               _ptr(ns), seed, _ptr(lobes), lobes.shape[0], _ptr(out), _ptr(ws),
                                ws.numel() * 4, _stream(stream))
     _check("radiance_estimate", rc)
     return out
@@ -499,6 +536,20 @@ def vndf_microbench(method, lanes, iters, seed=1, out=None, stream=None):
     o = torch.empty(lanes, dtype=torch.int32, device="cuda") if out is None else out
     _check("vndf_microbench", load_library().vndf_microbench(
         _METHODS.get(method, method), lanes, iters, seed, _ptr(o), _stream(stream)))
+    return o
+
+
+def estimator_microbench(kind, lanes, pairs, seed=1, lobes=None, out=None, stream=None):
+    """Register-resident benchmark of an estimator's per-sample arithmetic
+    (kind 0 forward, 1 value + adjoint, 2 radiance under 4 lobes given as a
+    (4, 5) float32 GPU tensor); returns the per-lane int32 fold."""
+    o = torch.empty(lanes, dtype=torch.int32, device="cuda") if out is None else out
+    if lobes is not None:
+        _dev(lobes, "lobes")
+        if lobes.numel() != 20:
+            raise ValueError("lobes must hold 4 lobes of 5 values")
+    _check("estimator_microbench", load_library().estimator_microbench(
+        int(kind), lanes, pairs, seed, _ptr(lobes), _ptr(o), _stream(stream)))
     return o
 
 

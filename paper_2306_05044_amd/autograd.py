@@ -20,7 +20,8 @@ class AlbedoFunction(torch.autograd.Function):
     """A(alpha_x, alpha_y, theta_o; phi_o, F0) per cell.
 
     Inputs: ax, ay, theta_o, phi_o, f0 -- float32 GPU tensors of one shape --
-    then nsamples (int) and seed (int).  Gradients flow to ax, ay and theta_o
+    then nsamples (an int for every cell, or an int64 tensor of that shape
+    with each cell's count) and seed (int).  Gradients flow to ax, ay and theta_o
     (theta_o is the polar angle of the view direction, phi_o its azimuth) by
     the pathwise adjoint, and to f0 exactly (A is linear in F0); phi_o gets
     none.
@@ -31,14 +32,16 @@ class AlbedoFunction(torch.autograd.Function):
         from . import albedo_estimate, albedo_value_and_grad, albedo_view_from_angles
         flat = [t.contiguous().reshape(-1) for t in (ax, ay, theta_o, phi_o, f0)]
         axf, ayf, thf, phf, f0f = flat
+        ns = (nsamples.contiguous().reshape(-1) if isinstance(nsamples, torch.Tensor)
+              else int(nsamples))
         wox, woy, woz = albedo_view_from_angles(thf, phf)
         need = any(ctx.needs_input_grad[:3])
         a, gx, gy, gt = albedo_value_and_grad(
-            wox, woy, woz, axf, ayf, int(nsamples), int(seed), f0=f0f, with_grad=need)
+            wox, woy, woz, axf, ayf, ns, int(seed), f0=f0f, with_grad=need)
         saved = [gx, gy, gt] if need else [None] * 3
         if ctx.needs_input_grad[4]:
             # the estimate is linear in F0: dA/dF0 = S1 - S5 on the same stream
-            saved += list(albedo_estimate(wox, woy, woz, axf, ayf, int(nsamples), int(seed)))
+            saved += list(albedo_estimate(wox, woy, woz, axf, ayf, ns, int(seed)))
         else:
             saved += [None, None]
         ctx.save_for_backward(*saved)

@@ -124,6 +124,39 @@ __device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uin
     }
 }
 
+// Replaces the FP32 terms of the samples albedo_adj flagged (reflection
+// within FP32 rounding of the horizon, or ill-conditioned) by their double
+// precision evaluation: acc += t64 - t32 for each such sample of this
+// lane's pairs.  With one flagged pair (the usual case) only that pair is
+// evaluated again; with more, the lane walks its pairs once more.
+template <int STRIDE>
+__device__ __attribute__((noinline)) void fix_flagged(
+    const CellConst& c, float f0, uint64_t pbeg, uint64_t pend, uint64_t nsamples, uint32_t unit,
+    uint32_t k0, uint32_t k1, uint32_t lane, uint32_t nflag, uint32_t pflag, Comp* acc) {
+    auto fix_pair = [&](uint64_t p) {
+        const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
+        const float u[4] = {unit24(w.w0), unit24(w.w1), unit24(w.w2), unit24(w.w3)};
+        for (int h = 0; h < 2; ++h) {
+            if (2 * p + h >= nsamples) break;
+            const AdjTerm a = albedo_adj(c, f0, u[2 * h], u[2 * h + 1]);
+            if (!a.amb) continue;
+            const AdjTerm d = albedo_adj_f64(c, f0, u[2 * h], u[2 * h + 1]);
+            comp_add(acc[0], d.w - a.w);
+            comp_add(acc[1], d.dax - a.dax);
+            comp_add(acc[2], d.day - a.day);
+            comp_add(acc[3], d.dth - a.dth);
+            comp_add(acc[4], d.dwsx - a.dwsx);
+            comp_add(acc[5], d.dwsy - a.dwsy);
+            comp_add(acc[6], d.dzs - a.dzs);
+        }
+    };
+    if (nflag == 1) {
+        fix_pair(pbeg + pflag);
+    } else {
+        for (uint64_t p = pbeg + lane; p < pend; p += STRIDE) fix_pair(p);
+    }
+}
+
 // Adjoint loop: accumulates w, the direct derivatives and the adjoint of ws,
 // then chains ws into (alpha_x, alpha_y, theta_o).  out = {w, gax, gay, gth}.
 template <int STRIDE>
@@ -134,6 +167,8 @@ __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t
     Comp acc[7];
 #pragma unroll
     for (int a = 0; a < 7; ++a) acc[a] = Comp{0.0f, 0.0f};
+    uint32_t nflag = 0;   // pairs with a flagged sample
+    uint32_t pflag = 0;   // the last of them, relative to pbeg (a chunk has < 2^32 pairs)
     for (uint64_t p0 = pbeg + lane; p0 < pend; p0 += (uint64_t)STRIDE * kGroup) {
         float part[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll CAPVNDF_ADJ_UNROLL
@@ -144,16 +179,22 @@ __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t
                 const AdjTerm t0 = albedo_adj(c, f0, unit24(w.w0), unit24(w.w1));
                 part[0] += t0.w; part[1] += t0.dax; part[2] += t0.day; part[3] += t0.dth;
                 part[4] += t0.dwsx; part[5] += t0.dwsy; part[6] += t0.dzs;
+                bool flag = t0.amb;
                 if (2 * p + 1 < nsamples) {
                     const AdjTerm t1 = albedo_adj(c, f0, unit24(w.w2), unit24(w.w3));
                     part[0] += t1.w; part[1] += t1.dax; part[2] += t1.day; part[3] += t1.dth;
                     part[4] += t1.dwsx; part[5] += t1.dwsy; part[6] += t1.dzs;
+                    flag = flag || t1.amb;
                 }
+                nflag += flag ? 1u : 0u;
+                pflag = flag ? (uint32_t)(p - pbeg) : pflag;
             }
         }
 #pragma unroll
         for (int a = 0; a < 7; ++a) comp_add(acc[a], part[a]);
     }
+    if (nflag != 0)
+        fix_flagged<STRIDE>(c, f0, pbeg, pend, nsamples, unit, k0, k1, lane, nflag, pflag, acc);
     float gax = acc[1].s + acc[1].c;
     float gay = acc[2].s + acc[2].c;
     float gth = acc[3].s + acc[3].c;
@@ -165,35 +206,75 @@ __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t
 }
 
 // ---------------------------------------------------------------------------
-// Uniform-N kernels (one cell per group of `cpc` consecutive blocks).
+// Table estimators: per-cell sample counts, cells cut into slots.
+//
+// Cell c has N_c samples (its own count, read from device memory), i.e.
+// ceil(ceil(N_c / 2) / kLutChunkPairs) chunks.  A launch gives every cell
+// `slots` consecutive blocks; slot s of a cell handles the cell's chunks
+// s, s + slots, s + 2 slots, ... into one compensated partial, and the
+// finishing pass merges the cell's first min(slots, chunks) partials in slot
+// order.  A slot beyond the cell's chunk count returns at once.  The slot
+// count is a host choice (enough blocks to fill the chip, capped by the
+// workspace), so no device-side table or scan is needed and a workspace
+// depends only on the cell count.
 // ---------------------------------------------------------------------------
+constexpr int64_t kMaxSamples = (int64_t)1 << 40;
+
+__host__ __device__ inline int64_t cell_chunks(int64_t n) {
+    if (n <= 0 || n >= kMaxSamples) return 0;
+    const uint64_t npairs = ((uint64_t)n + 1) / 2;
+    return (int64_t)((npairs + kLutChunkPairs - 1) / kLutChunkPairs);
+}
+
+// The part of a launch that block b works on.
+struct SlotWork {
+    int64_t cell;    // cell index within the call
+    int64_t nchunks; // chunks of the cell
+    uint64_t n;      // its sample count
+    int32_t slot;
+};
+
+__device__ __forceinline__ SlotWork slot_work(const int64_t* __restrict__ nsamp, int32_t slots) {
+    SlotWork w;
+    const int64_t b = blockIdx.x;
+    w.cell = b / slots;
+    w.slot = (int32_t)(b - w.cell * slots);
+    const int64_t n = nsamp[w.cell];
+    w.nchunks = cell_chunks(n);
+    w.n = w.nchunks > 0 ? (uint64_t)n : 0;
+    return w;
+}
+
 // MODE 0: two sums (G2/G1 and G2/G1 (1 - wo.h)^5) for albedo_estimate;
 // MODE 1: one sum of F G2/G1 with the cell's F0.
 template <int MODE>
 __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
-    uint64_t nsamples, int32_t cpc, uint32_t unit_base, uint32_t k0, uint32_t k1,
-    float* __restrict__ partial) {
+    const int64_t* __restrict__ nsamp, int32_t slots, uint32_t unit_base, uint32_t k0,
+    uint32_t k1, float* __restrict__ partial) {
     constexpr int NACC = MODE == 0 ? 2 : 1;
-    const int64_t b = blockIdx.x;
-    const int64_t cell = b / cpc;
-    const int64_t chunk = b - cell * cpc;
+    const SlotWork sw = slot_work(nsamp, slots);
+    if (sw.slot >= sw.nchunks) return;  // the same for the whole block
+    const int64_t cell = sw.cell;
     const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
     Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-    const uint64_t npairs = (nsamples + 1) / 2;
-    const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
-    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+    const uint64_t npairs = (sw.n + 1) / 2;
     if (c.ok)
-        pairs_fwd<kLutBlock>(c, pbeg, pend, nsamples, unit_base + (uint32_t)cell, k0, k1, acc);
+        for (int64_t k = sw.slot; k < sw.nchunks; k += slots) {
+            const uint64_t pbeg = (uint64_t)k * kLutChunkPairs;
+            const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+            pairs_fwd<kLutBlock>(c, pbeg, pend, sw.n, unit_base + (uint32_t)cell, k0, k1, acc);
+        }
+    float* dst = partial + (int64_t)blockIdx.x * 2 * NACC;
     if (MODE == 0) {
-        block_reduce_store<2, kLutBlock>(acc, partial + b * 2 * NACC);
+        block_reduce_store<2, kLutBlock>(acc, dst);
     } else {
         // A(F0) = F0 S1 + (1 - F0) S5, folded per lane
         const float f0 = f0p ? f0p[cell] : 1.0f;
         const float a1 = acc[0].s + acc[0].c, a5 = acc[1].s + acc[1].c;
         Comp w[1] = {Comp{__builtin_fmaf(f0, a1, (1.0f - f0) * a5), 0.0f}};
-        block_reduce_store<1, kLutBlock>(w, partial + b * 2 * NACC);
+        block_reduce_store<1, kLutBlock>(w, dst);
     }
 }
 
@@ -204,24 +285,34 @@ template <bool WITH_VALUE>
 __global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
-    uint64_t nsamples, int32_t cpc, uint32_t unit_base, uint32_t k0, uint32_t k1,
-    float* __restrict__ partial) {
-    const int64_t b = blockIdx.x;
-    const int64_t cell = b / cpc;
-    const int64_t chunk = b - cell * cpc;
+    const int64_t* __restrict__ nsamp, int32_t slots, uint32_t unit_base, uint32_t k0,
+    uint32_t k1, float* __restrict__ partial) {
+    const SlotWork sw = slot_work(nsamp, slots);
+    if (sw.slot >= sw.nchunks) return;
+    const int64_t cell = sw.cell;
     const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
     const float f0 = f0p ? f0p[cell] : 1.0f;
     Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-    const uint64_t npairs = (nsamples + 1) / 2;
-    const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
-    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
-    if (c.ok)
-        pairs_adj<kLutBlock>(c, f0, pbeg, pend, nsamples, unit_base + (uint32_t)cell, k0, k1, out);
+    const uint64_t npairs = (sw.n + 1) / 2;
+    if (c.ok) {
+        // one sweep per chunk of the slot; the pathwise sums of successive
+        // chunks are added in chunk order (each already compensated)
+        for (int64_t k = sw.slot; k < sw.nchunks; k += slots) {
+            const uint64_t pbeg = (uint64_t)k * kLutChunkPairs;
+            const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+            Comp part[4];
+            pairs_adj<kLutBlock>(c, f0, pbeg, pend, sw.n, unit_base + (uint32_t)cell, k0, k1,
+                                 part);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) out[a] = comp_merge(out[a], part[a]);
+        }
+    }
+    float* dst = partial + (int64_t)blockIdx.x * (WITH_VALUE ? 8 : 6);
     if (WITH_VALUE) {
-        block_reduce_store<4, kLutBlock>(out, partial + b * 8);
+        block_reduce_store<4, kLutBlock>(out, dst);
     } else {
         Comp g[3] = {out[1], out[2], out[3]};
-        block_reduce_store<3, kLutBlock>(g, partial + b * 6);
+        block_reduce_store<3, kLutBlock>(g, dst);
     }
 }
 
@@ -230,36 +321,38 @@ template <int NL>
 __global__ __launch_bounds__(kLutBlock) void k_radiance(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
-    const float* __restrict__ lobep, uint64_t nsamples, int32_t cpc, uint32_t k0, uint32_t k1,
-    float* __restrict__ partial) {
-    const int64_t b = blockIdx.x;
-    const int64_t cell = b / cpc;
-    const int64_t chunk = b - cell * cpc;
+    const float* __restrict__ lobep, const int64_t* __restrict__ nsamp, int32_t slots,
+    uint32_t k0, uint32_t k1, float* __restrict__ partial) {
+    const SlotWork sw = slot_work(nsamp, slots);
+    if (sw.slot >= sw.nchunks) return;
+    const int64_t cell = sw.cell;
     const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
     const float f0 = f0p ? f0p[cell] : 1.0f;
     const Lobes<NL> lobes = load_lobes<NL>(lobep);
     Comp acc[1] = {Comp{0.0f, 0.0f}};
-    const uint64_t npairs = (nsamples + 1) / 2;
-    const uint64_t pbeg = (uint64_t)chunk * kLutChunkPairs;
-    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+    const uint64_t npairs = (sw.n + 1) / 2;
     if (c.ok) {
         const uint32_t unit = (uint32_t)cell;
-        for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)kLutBlock * kGroup) {
-            float part = 0.0f;
+        for (int64_t k = sw.slot; k < sw.nchunks; k += slots) {
+            const uint64_t pbeg = (uint64_t)k * kLutChunkPairs;
+            const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+            for (uint64_t p0 = pbeg + threadIdx.x; p0 < pend; p0 += (uint64_t)kLutBlock * kGroup) {
+                float part = 0.0f;
 #pragma unroll 2
-            for (int j = 0; j < kGroup; ++j) {
-                const uint64_t p = p0 + (uint64_t)j * kLutBlock;
-                if (p < pend) {
-                    const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
-                    part += radiance_term(c, f0, lobes, unit24(w.w0), unit24(w.w1));
-                    if (2 * p + 1 < nsamples)
-                        part += radiance_term(c, f0, lobes, unit24(w.w2), unit24(w.w3));
+                for (int j = 0; j < kGroup; ++j) {
+                    const uint64_t p = p0 + (uint64_t)j * kLutBlock;
+                    if (p < pend) {
+                        const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
+                        part += radiance_term(c, f0, lobes, unit24(w.w0), unit24(w.w1));
+                        if (2 * p + 1 < sw.n)
+                            part += radiance_term(c, f0, lobes, unit24(w.w2), unit24(w.w3));
+                    }
                 }
+                comp_add(acc[0], part);
             }
-            comp_add(acc[0], part);
         }
     }
-    block_reduce_store<1, kLutBlock>(acc, partial + b * 2);
+    block_reduce_store<1, kLutBlock>(acc, partial + (int64_t)blockIdx.x * 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,8 +451,11 @@ __global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch(CAPVNDF_BATCH_
         const int32_t ce = __builtin_amdgcn_readfirstlane(owner_chunks[blockIdx.x + 1]);
         for (int32_t ch = cb; ch < ce; ++ch) batch_chunk_block<BLOCK, GRAD>(ch, CAPVNDF_CHUNK_ARGS);
     } else {
+        // At most nchunks + 1 tickets per owner: the loop ends even if a
+        // miscompiled ticket read kept returning one chunk (that would leave
+        // other slots unwritten, which the parity tests catch).
         __shared__ int32_t next;
-        for (;;) {
+        for (int32_t t = 0; t <= nchunks; ++t) {
             if (threadIdx.x == 0) next = atomicAdd(counter, 1);
             __syncthreads();
             const int32_t ch = __builtin_amdgcn_readfirstlane(next);
@@ -388,8 +484,9 @@ __global__ __launch_bounds__(BLOCK) CAPVNDF_ADJ_ATTR void k_batch_wave(CAPVNDF_B
         // under `if (lane == 0)` the compiler joined it to the lane-0 store
         // that ends the previous chunk and split the loop in two: lane 0 went
         // back to take a ticket while lanes 1-63 looped on with a zero ticket
-        // and never left.
-        for (;;) {
+        // and never left.  The ticket count is capped at nchunks + 1 as in
+        // k_batch, so such a fault would give a wrong result, not a hang.
+        for (int32_t t = 0; t <= nchunks; ++t) {
             const int32_t mine = atomicAdd(counter, lane == 0 ? 1 : 0);
             const int32_t ch = __builtin_amdgcn_readfirstlane(mine);
             if (ch >= nchunks) break;
@@ -407,26 +504,28 @@ __global__ void k_reset_counter(int32_t* counter) {
 }
 
 // ---------------------------------------------------------------------------
-// Finishing pass: unit u merges its chunk partials in chunk order, divides by
-// its sample count and applies an optional per-unit scale.
-// Chunks of unit u: [u*cpc, (u+1)*cpc) if unit_chunks is NULL, else
-// [unit_chunks[u], unit_chunks[u+1]).
+// Finishing pass: unit u merges its partials in order, divides by its sample
+// count and applies an optional per-unit scale.  Partials of unit u: the
+// first min(slots, chunks) of [u * slots, (u + 1) * slots) if unit_chunks is
+// NULL (table estimators), else [unit_chunks[u], unit_chunks[u + 1]) (batch
+// plans).  A count outside [0, 2^40) gives NaN.
 // ---------------------------------------------------------------------------
 template <int NACC>
 __global__ __launch_bounds__(kFinishBlock) void k_finish(
-    int64_t nunits, const float* __restrict__ partial, int32_t cpc,
-    const int32_t* __restrict__ unit_chunks, const int64_t* __restrict__ nsamp_dev,
-    uint64_t nsamp_uniform, const float* __restrict__ scale, float* __restrict__ o0,
-    float* __restrict__ o1, float* __restrict__ o2, float* __restrict__ o3) {
+    int64_t nunits, const float* __restrict__ partial, int32_t slots,
+    const int32_t* __restrict__ unit_chunks, const int64_t* __restrict__ nsamp,
+    const float* __restrict__ scale, float* __restrict__ o0, float* __restrict__ o1,
+    float* __restrict__ o2, float* __restrict__ o3) {
     const int64_t u = (int64_t)blockIdx.x * kFinishBlock + threadIdx.x;
     if (u >= nunits) return;
+    const int64_t n = nsamp[u];
     int64_t cb, ce;
     if (unit_chunks) {
         cb = unit_chunks[u];
         ce = unit_chunks[u + 1];
     } else {
-        cb = u * cpc;
-        ce = cb + cpc;
+        cb = u * slots;
+        ce = cb + std::min<int64_t>(slots, cell_chunks(n));
     }
     Comp r[NACC];
 #pragma unroll
@@ -438,51 +537,56 @@ __global__ __launch_bounds__(kFinishBlock) void k_finish(
             r[a] = comp_merge(r[a], Comp{p[0], p[1]});
         }
     }
-    const uint64_t n = nsamp_dev ? (uint64_t)nsamp_dev[u] : nsamp_uniform;
-    const float inv = n > 0 ? (float)(1.0 / (double)n) : 0.0f;
+    const bool bad = n < 0 || n >= kMaxSamples;
+    const float inv = n > 0 && !bad ? (float)(1.0 / (double)n) : 0.0f;
     const float sc = (scale ? scale[u] : 1.0f) * inv;
     float* outs[4] = {o0, o1, o2, o3};
 #pragma unroll
-    for (int a = 0; a < NACC; ++a) outs[a][u] = (r[a].s + r[a].c) * sc;
+    for (int a = 0; a < NACC; ++a) outs[a][u] = bad ? __builtin_nanf("") : (r[a].s + r[a].c) * sc;
 }
 
 inline unsigned finish_grid(int64_t n) { return (unsigned)((n + kFinishBlock - 1) / kFinishBlock); }
 
-inline int64_t lut_chunks_per_cell(int64_t nsamples) {
-    const uint64_t npairs = ((uint64_t)nsamples + 1) / 2;
-    const uint64_t c = (npairs + kLutChunkPairs - 1) / kLutChunkPairs;
-    return c == 0 ? 1 : (int64_t)c;
+// Slots per cell.  A call aims for kFillBlocks blocks (about four rounds of
+// the blocks the chip holds at once) with at least kMinSlots per cell, and
+// stays below 2^24 blocks (a dispatch counts its work-items in 32 bits).
+constexpr int64_t kFillBlocks = 8192;
+constexpr int64_t kMinSlots = 64;
+constexpr int64_t kMaxBlocks = ((int64_t)1 << 24) - 1;
+
+int64_t target_slots(int64_t ncells) {
+    const int64_t s = std::max<int64_t>(kMinSlots, (kFillBlocks + ncells - 1) / ncells);
+    return std::max<int64_t>(1, std::min<int64_t>(s, kMaxBlocks / ncells));
 }
 
-// Size and pointer checks of the per-cell estimators.  lut_grid: the call
-// launches one kLutBlock block per chunk of each cell (the table estimators,
-// not the batch plans, whose persistent grid is small).
-int32_t check_cells(const char* fn, int64_t ncells, int64_t nsamples, const float* wox,
-                    const float* woy, const float* woz, const float* ax, const float* ay,
-                    bool lut_grid = true) {
+size_t slot_bytes(int nacc) { return (size_t)nacc * 2 * sizeof(float); }
+
+// Argument checks of the table estimators and the slot count the workspace
+// allows: min(target_slots(ncells), workspace_bytes / (ncells * slot bytes)).
+int32_t prepare_cells(const char* fn, int64_t ncells, const float* wox, const float* woy,
+                      const float* woz, const float* ax, const float* ay, const int64_t* nsamples,
+                      int nacc, const void* workspace, size_t workspace_bytes, int32_t* slots) {
+    *slots = 0;
     if (ncells < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells < 0", fn);
-    if (nsamples < 0 || nsamples >= ((int64_t)1 << 40))
-        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: nsamples must be in [0, 2^40)", fn);
-    // one block of kLutBlock work-items per chunk; a dispatch counts its
-    // work-items in 32 bits
-    if (lut_grid && ncells > 0 &&
-        (double)ncells * (double)lut_chunks_per_cell(nsamples) * kLutBlock > 4294967295.0)
-        return fail(CAPVNDF_ERR_BAD_SIZE,
-                    "%s: ncells * chunks per cell (%lld * %lld) must be below 2^24 (chunks of "
-                    "%llu samples); split the cells over several calls", fn, (long long)ncells,
-                    (long long)lut_chunks_per_cell(nsamples), (unsigned long long)(2 * kLutChunkPairs));
-    if (ncells > ((int64_t)1 << 32))
-        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells exceeds the 32-bit stream unit", fn);
+    if (ncells > kMaxBlocks)
+        return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells must be below 2^24; split the cells over "
+                    "several calls", fn);
+    if (ncells == 0) return CAPVNDF_OK;
     const void* req[] = {wox, woy, woz, ax, ay};
     const char* names[] = {"wox", "woy", "woz", "ax", "ay"};
-    if (ncells > 0)
-        for (int i = 0; i < 5; ++i)
-            if (int32_t rc = check_array(req[i], names[i])) return rc;
+    for (int i = 0; i < 5; ++i)
+        if (int32_t rc = check_array(req[i], names[i])) return rc;
+    if (nsamples == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "%s: nsamples is NULL", fn);
+    if (!aligned_to(nsamples, 8))
+        return fail(CAPVNDF_ERR_MISALIGNED, "%s: nsamples must be 8-byte aligned", fn);
+    const size_t per_cell = (size_t)ncells * slot_bytes(nacc);
+    if (workspace == nullptr || workspace_bytes < per_cell)
+        return fail(CAPVNDF_ERR_WORKSPACE, "%s: workspace of at least %zu bytes needed, %zu given",
+                    fn, per_cell, workspace == nullptr ? (size_t)0 : workspace_bytes);
+    if (!aligned_to(workspace, 16))
+        return fail(CAPVNDF_ERR_MISALIGNED, "%s: workspace must be 16-byte aligned", fn);
+    *slots = (int32_t)std::min<int64_t>(target_slots(ncells), (int64_t)(workspace_bytes / per_cell));
     return CAPVNDF_OK;
-}
-
-size_t lut_workspace(int64_t ncells, int64_t nsamples, int nacc) {
-    return (size_t)ncells * (size_t)lut_chunks_per_cell(nsamples) * (size_t)nacc * 2 * sizeof(float);
 }
 
 }  // namespace
@@ -490,47 +594,55 @@ size_t lut_workspace(int64_t ncells, int64_t nsamples, int nacc) {
 
 using namespace capvndf;
 
-extern "C" size_t albedo_workspace_size(int64_t ncells, int64_t nsamples, int32_t mode) {
-    if (ncells < 0 || nsamples < 0 || nsamples >= ((int64_t)1 << 40)) return 0;
-    if (mode < 0 || mode > 2) return 0;
-    return lut_workspace(ncells, nsamples, mode == 0 ? 2 : (mode == 1 ? 3 : 4));
+extern "C" size_t albedo_workspace_size(int64_t ncells, const int64_t* nsamples_host,
+                                        int32_t with_grad) {
+    if (ncells <= 0 || ncells > kMaxBlocks || (with_grad != 0 && with_grad != 1)) return 0;
+    int64_t slots = target_slots(ncells);
+    if (nsamples_host != nullptr) {
+        int64_t most = 0;
+        for (int64_t c = 0; c < ncells; ++c) {
+            const int64_t n = nsamples_host[c];
+            if (n < 0 || n >= kMaxSamples) return 0;
+            most = std::max(most, cell_chunks(n));
+        }
+        slots = std::min(slots, std::max<int64_t>(1, most));
+    }
+    return (size_t)ncells * (size_t)slots * slot_bytes(with_grad ? 4 : 2);
 }
 
 extern "C" int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy,
                                    const float* woz, const float* ax, const float* ay,
-                                   int64_t nsamples, uint64_t seed, float* s_f1, float* s_f5,
-                                   void* workspace, size_t workspace_bytes, void* stream) {
-    if (int32_t rc = check_cells("albedo_estimate", ncells, nsamples, wox, woy, woz, ax, ay))
+                                   const int64_t* nsamples, uint64_t seed, float* s_f1,
+                                   float* s_f5, void* workspace, size_t workspace_bytes,
+                                   void* stream) {
+    int32_t slots = 0;
+    if (int32_t rc = prepare_cells("albedo_estimate", ncells, wox, woy, woz, ax, ay, nsamples, 2,
+                                   workspace, workspace_bytes, &slots))
         return rc;
     if (ncells == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(s_f1, "s_f1")) return rc;
     if (int32_t rc = check_array(s_f5, "s_f5")) return rc;
-    const size_t need = lut_workspace(ncells, nsamples, 2);
-    if (workspace_bytes < need || workspace == nullptr)
-        return fail(CAPVNDF_ERR_WORKSPACE, "albedo_estimate: workspace of %zu bytes needed, %zu given",
-                    need, workspace == nullptr ? (size_t)0 : workspace_bytes);
-    if (!aligned_to(workspace, 16))
-        return fail(CAPVNDF_ERR_MISALIGNED, "albedo_estimate: workspace must be 16-byte aligned");
-    const int64_t cpc = lut_chunks_per_cell(nsamples);
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
-    hipLaunchKernelGGL(k_albedo_fwd<0>, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st, wox,
-                       woy, woz, ax, ay, nullptr, (uint64_t)nsamples, (int32_t)cpc, 0u,
-                       key_lo(seed), key_hi(seed), part);
+    hipLaunchKernelGGL(k_albedo_fwd<0>, dim3((unsigned)(ncells * slots)), dim3(kLutBlock), 0, st,
+                       wox, woy, woz, ax, ay, nullptr, nsamples, slots, 0u, key_lo(seed),
+                       key_hi(seed), part);
     if (int32_t rc = check_launch("albedo_estimate launch")) return rc;
     hipLaunchKernelGGL(k_finish<2>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
-                       part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr, s_f1,
-                       s_f5, nullptr, nullptr);
+                       part, slots, nullptr, nsamples, nullptr, s_f1, s_f5, nullptr, nullptr);
     return check_launch("albedo_estimate finish launch");
 }
 
 extern "C" int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* woy,
                                             const float* woz, const float* ax, const float* ay,
-                                            int64_t nsamples, uint64_t seed, const float* f0,
-                                            const float* grad_albedo, float* grad_ax,
-                                            float* grad_ay, float* grad_theta_o, void* workspace,
-                                            size_t workspace_bytes, void* stream) {
-    if (int32_t rc = check_cells("albedo_estimate_backward", ncells, nsamples, wox, woy, woz, ax, ay))
+                                            const int64_t* nsamples, uint64_t seed,
+                                            const float* f0, const float* grad_albedo,
+                                            float* grad_ax, float* grad_ay, float* grad_theta_o,
+                                            void* workspace, size_t workspace_bytes,
+                                            void* stream) {
+    int32_t slots = 0;
+    if (int32_t rc = prepare_cells("albedo_estimate_backward", ncells, wox, woy, woz, ax, ay,
+                                   nsamples, 3, workspace, workspace_bytes, &slots))
         return rc;
     if (ncells == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(grad_ax, "grad_ax")) return rc;
@@ -540,109 +652,119 @@ extern "C" int32_t albedo_estimate_backward(int64_t ncells, const float* wox, co
         if (int32_t rc = check_array(f0, "f0")) return rc;
     if (grad_albedo != nullptr)
         if (int32_t rc = check_array(grad_albedo, "grad_albedo")) return rc;
-    const size_t need = lut_workspace(ncells, nsamples, 3);
-    if (workspace_bytes < need || workspace == nullptr)
-        return fail(CAPVNDF_ERR_WORKSPACE,
-                    "albedo_estimate_backward: workspace of %zu bytes needed, %zu given", need,
-                    workspace == nullptr ? (size_t)0 : workspace_bytes);
-    if (!aligned_to(workspace, 16))
-        return fail(CAPVNDF_ERR_MISALIGNED, "albedo_estimate_backward: workspace must be 16-byte aligned");
-    const int64_t cpc = lut_chunks_per_cell(nsamples);
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
-    hipLaunchKernelGGL(k_albedo_adj<false>, dim3((unsigned)(ncells * cpc)), dim3(kLutBlock), 0, st,
-                       wox, woy, woz, ax, ay, f0, (uint64_t)nsamples, (int32_t)cpc, 0u,
-                       key_lo(seed), key_hi(seed), part);
+    hipLaunchKernelGGL(k_albedo_adj<false>, dim3((unsigned)(ncells * slots)), dim3(kLutBlock), 0,
+                       st, wox, woy, woz, ax, ay, f0, nsamples, slots, 0u, key_lo(seed),
+                       key_hi(seed), part);
     if (int32_t rc = check_launch("albedo_estimate_backward launch")) return rc;
     hipLaunchKernelGGL(k_finish<3>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
-                       part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, grad_albedo,
-                       grad_ax, grad_ay, grad_theta_o, nullptr);
+                       part, slots, nullptr, nsamples, grad_albedo, grad_ax, grad_ay, grad_theta_o,
+                       nullptr);
     return check_launch("albedo_estimate_backward finish launch");
 }
 
-extern "C" int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy,
-                                         const float* woz, const float* ax, const float* ay,
-                                         int64_t nsamples, uint64_t seed, const float* f0,
-                                         float* albedo, float* grad_ax, float* grad_ay,
-                                         float* grad_theta_o, void* workspace,
-                                         size_t workspace_bytes, void* stream) {
-    if (int32_t rc = check_cells("albedo_value_and_grad", ncells, nsamples, wox, woy, woz, ax, ay))
-        return rc;
-    if (ncells == 0) return CAPVNDF_OK;
+namespace capvndf {
+namespace {
+
+// albedo_value_and_grad on a given partial buffer with a given slot count
+// (shared by the workspace entry point and its variant on the library's own
+// buffer).
+int32_t enqueue_value_and_grad(int64_t ncells, const float* wox, const float* woy,
+                               const float* woz, const float* ax, const float* ay,
+                               const int64_t* nsamples, uint64_t seed, const float* f0,
+                               float* albedo, float* grad_ax, float* grad_ay, float* grad_theta_o,
+                               bool grad, float* part, int32_t slots, hipStream_t st) {
+    const dim3 grid((unsigned)(ncells * slots)), block(kLutBlock);
+    if (grad) {
+        hipLaunchKernelGGL(k_albedo_adj<true>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
+                           nsamples, slots, 0u, key_lo(seed), key_hi(seed), part);
+        if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
+        hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                           part, slots, nullptr, nsamples, nullptr, albedo, grad_ax, grad_ay,
+                           grad_theta_o);
+    } else {
+        hipLaunchKernelGGL(k_albedo_fwd<1>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
+                           nsamples, slots, 0u, key_lo(seed), key_hi(seed), part);
+        if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
+        hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
+                           part, slots, nullptr, nsamples, nullptr, albedo, nullptr, nullptr,
+                           nullptr);
+    }
+    return check_launch("albedo_value_and_grad finish launch");
+}
+
+// Output checks of albedo_value_and_grad; *grad tells whether the three
+// gradient outputs are given.
+int32_t check_value_and_grad_outputs(const char* fn, const float* f0, const float* albedo,
+                                     const float* grad_ax, const float* grad_ay,
+                                     const float* grad_theta_o, bool* grad) {
     if (int32_t rc = check_array(albedo, "albedo")) return rc;
     const int ngrad = (grad_ax != nullptr) + (grad_ay != nullptr) + (grad_theta_o != nullptr);
     if (ngrad != 0 && ngrad != 3)
-        return fail(CAPVNDF_ERR_NULL_PTR,
-                    "albedo_value_and_grad: give all three gradient outputs or none");
-    const bool grad = ngrad == 3;
-    if (grad) {
+        return fail(CAPVNDF_ERR_NULL_PTR, "%s: give all three gradient outputs or none", fn);
+    *grad = ngrad == 3;
+    if (*grad) {
         if (int32_t rc = check_array(grad_ax, "grad_ax")) return rc;
         if (int32_t rc = check_array(grad_ay, "grad_ay")) return rc;
         if (int32_t rc = check_array(grad_theta_o, "grad_theta_o")) return rc;
     }
     if (f0 != nullptr)
         if (int32_t rc = check_array(f0, "f0")) return rc;
-    const size_t need = lut_workspace(ncells, nsamples, grad ? 4 : 1);
-    if (workspace_bytes < need || workspace == nullptr)
-        return fail(CAPVNDF_ERR_WORKSPACE,
-                    "albedo_value_and_grad: workspace of %zu bytes needed, %zu given", need,
-                    workspace == nullptr ? (size_t)0 : workspace_bytes);
-    if (!aligned_to(workspace, 16))
-        return fail(CAPVNDF_ERR_MISALIGNED, "albedo_value_and_grad: workspace must be 16-byte aligned");
-    const int64_t cpc = lut_chunks_per_cell(nsamples);
-    const hipStream_t st = as_stream(stream);
-    float* part = static_cast<float*>(workspace);
-    const dim3 grid((unsigned)(ncells * cpc)), block(kLutBlock);
-    if (grad) {
-        hipLaunchKernelGGL(k_albedo_adj<true>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
-                           (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed), key_hi(seed), part);
-        if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
-        hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
-                           part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr,
-                           albedo, grad_ax, grad_ay, grad_theta_o);
-    } else {
-        hipLaunchKernelGGL(k_albedo_fwd<1>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
-                           (uint64_t)nsamples, (int32_t)cpc, 0u, key_lo(seed), key_hi(seed), part);
-        if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
-        hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
-                           part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr,
-                           albedo, nullptr, nullptr, nullptr);
-    }
-    return check_launch("albedo_value_and_grad finish launch");
+    return CAPVNDF_OK;
+}
+
+}  // namespace
+}  // namespace capvndf
+
+extern "C" int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy,
+                                         const float* woz, const float* ax, const float* ay,
+                                         const int64_t* nsamples, uint64_t seed, const float* f0,
+                                         float* albedo, float* grad_ax, float* grad_ay,
+                                         float* grad_theta_o, void* workspace,
+                                         size_t workspace_bytes, void* stream) {
+    const char* fn = "albedo_value_and_grad";
+    bool grad = false;
+    if (ncells > 0)
+        if (int32_t rc = check_value_and_grad_outputs(fn, f0, albedo, grad_ax, grad_ay,
+                                                      grad_theta_o, &grad))
+            return rc;
+    int32_t slots = 0;
+    if (int32_t rc = prepare_cells(fn, ncells, wox, woy, woz, ax, ay, nsamples, grad ? 4 : 1,
+                                   workspace, workspace_bytes, &slots))
+        return rc;
+    if (ncells == 0) return CAPVNDF_OK;
+    return enqueue_value_and_grad(ncells, wox, woy, woz, ax, ay, nsamples, seed, f0, albedo,
+                                  grad_ax, grad_ay, grad_theta_o, grad,
+                                  static_cast<float*>(workspace), slots, as_stream(stream));
 }
 
 extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const float* woy,
                                      const float* woz, const float* ax, const float* ay,
-                                     const float* f0, int64_t nsamples, uint64_t seed,
+                                     const float* f0, const int64_t* nsamples, uint64_t seed,
                                      const float* lobes, int32_t nlobes, float* radiance,
                                      void* workspace, size_t workspace_bytes, void* stream) {
-    if (int32_t rc = check_cells("radiance_estimate", ncells, nsamples, wox, woy, woz, ax, ay))
-        return rc;
     if (nlobes < 0 || nlobes > kMaxLobes)
         return fail(CAPVNDF_ERR_BAD_SIZE, "radiance_estimate: nlobes must be in [0, %d]", kMaxLobes);
+    int32_t slots = 0;
+    if (int32_t rc = prepare_cells("radiance_estimate", ncells, wox, woy, woz, ax, ay, nsamples, 1,
+                                   workspace, workspace_bytes, &slots))
+        return rc;
     if (ncells == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(radiance, "radiance")) return rc;
     if (nlobes > 0)
         if (int32_t rc = check_array(lobes, "lobes")) return rc;
     if (f0 != nullptr)
         if (int32_t rc = check_array(f0, "f0")) return rc;
-    const size_t need = lut_workspace(ncells, nsamples, 1);
-    if (workspace_bytes < need || workspace == nullptr)
-        return fail(CAPVNDF_ERR_WORKSPACE, "radiance_estimate: workspace of %zu bytes needed, %zu given",
-                    need, workspace == nullptr ? (size_t)0 : workspace_bytes);
-    if (!aligned_to(workspace, 16))
-        return fail(CAPVNDF_ERR_MISALIGNED, "radiance_estimate: workspace must be 16-byte aligned");
-    const int64_t cpc = lut_chunks_per_cell(nsamples);
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
-    const dim3 grid((unsigned)(ncells * cpc)), block(kLutBlock);
-    const uint64_t ns = (uint64_t)nsamples;
+    const dim3 grid((unsigned)(ncells * slots)), block(kLutBlock);
     const uint32_t k0 = key_lo(seed), k1 = key_hi(seed);
     static_assert(kMaxLobes == 8, "the switch below covers 0 .. 8 lobes");
 #define CAPVNDF_LAUNCH_RADIANCE(NL)                                                                \
     case NL:                                                                                       \
         hipLaunchKernelGGL(k_radiance<NL>, grid, block, 0, st, wox, woy, woz, ax, ay, f0, lobes,  \
-                           ns, (int32_t)cpc, k0, k1, part);                                        \
+                           nsamples, slots, k0, k1, part);                                         \
         break;
     switch (nlobes) {
         CAPVNDF_LAUNCH_RADIANCE(0)
@@ -660,9 +782,105 @@ extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const flo
 #undef CAPVNDF_LAUNCH_RADIANCE
     if (int32_t rc = check_launch("radiance_estimate launch")) return rc;
     hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
-                       part, (int32_t)cpc, nullptr, nullptr, (uint64_t)nsamples, nullptr, radiance,
-                       nullptr, nullptr, nullptr);
+                       part, slots, nullptr, nsamples, nullptr, radiance, nullptr, nullptr,
+                       nullptr);
     return check_launch("radiance_estimate finish launch");
+}
+
+// ===========================================================================
+// Register-resident estimator microbenchmark: each lane runs the per-sample
+// arithmetic of one estimator kernel over `pairs` Philox pairs of its own
+// stream (tag 3, unit = lane) into plain per-lane sums -- no loads in the
+// loop, no compensated sums, no cross-lane reductions -- at the estimator
+// kernel's own occupancy.  KIND 0: the forward's two sums; 1: value and
+// adjoint; 2: direct illumination under 4 lobes.  Its issue rate is what the
+// estimator's instruction mix reaches on this chip with nothing else in the
+// way, the ceiling the table kernels are measured against.
+// ===========================================================================
+namespace capvndf {
+namespace {
+
+template <int KIND>
+__device__ __forceinline__ float microbench_lane(int64_t t, int32_t pairs, uint32_t k0,
+                                                 uint32_t k1, const Lobes<4>& lobes) {
+    // the lane's cell: view uniform over the hemisphere, alpha = 10^(-2 U)
+    const Words w = philox_pair(0, (uint32_t)t, 6u, k0, k1);
+    const float mu = 1.0f - unit24(w.w0);
+    float sp, cp;
+    sincos_turns(unit24(w.w1), &sp, &cp);
+    const float sz = fsqrt(fmaxf(__builtin_fmaf(-mu, mu, 1.0f), 0.0f));
+    const float ax = __builtin_amdgcn_exp2f(-6.643856189774724f * unit24(w.w2));
+    const float ay = __builtin_amdgcn_exp2f(-6.643856189774724f * unit24(w.w3));
+    const CellConst c = cell_setup(sz * cp, sz * sp, mu, ax, ay);
+    float acc[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int32_t p = 0; p < pairs; ++p) {
+        const Words q = philox_pair((uint64_t)p, (uint32_t)t, kTagAlbedo, k0, k1);
+        const float u[4] = {unit24(q.w0), unit24(q.w1), unit24(q.w2), unit24(q.w3)};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            if (KIND == 0) {
+                const FwdTerm r = albedo_fwd(c, u[2 * j], u[2 * j + 1]);
+                acc[0] += r.g;
+                acc[1] = __builtin_fmaf(r.g, r.m5, acc[1]);
+            } else if (KIND == 1) {
+                const AdjTerm r = albedo_adj(c, 0.04f, u[2 * j], u[2 * j + 1]);
+                acc[0] += r.w; acc[1] += r.dax; acc[2] += r.day; acc[3] += r.dth;
+                acc[4] += r.dwsx; acc[5] += r.dwsy; acc[6] += r.dzs;
+            } else {
+                acc[0] += radiance_term(c, 0.04f, lobes, u[2 * j], u[2 * j + 1]);
+            }
+        }
+    }
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLutBlock) void k_estimator_microbench(
+    int64_t lanes, int32_t pairs, uint32_t k0, uint32_t k1, const float* __restrict__ lobep,
+    uint32_t* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * kLutBlock + threadIdx.x;
+    if (t >= lanes) return;
+    const Lobes<4> lobes = KIND == 2 ? load_lobes<4>(lobep) : Lobes<4>{};
+    out[t] = __float_as_uint(microbench_lane<KIND>(t, pairs, k0, k1, lobes));
+}
+
+template <>
+__global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_estimator_microbench<1>(
+    int64_t lanes, int32_t pairs, uint32_t k0, uint32_t k1, const float* __restrict__ lobep,
+    uint32_t* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * kLutBlock + threadIdx.x;
+    if (t >= lanes) return;
+    (void)lobep;
+    out[t] = __float_as_uint(microbench_lane<1>(t, pairs, k0, k1, Lobes<4>{}));
+}
+
+}  // namespace
+}  // namespace capvndf
+
+extern "C" int32_t estimator_microbench(int32_t kind, int64_t lanes, int32_t pairs, uint64_t seed,
+                                        const float* lobes, uint32_t* out, void* stream) {
+    if (lanes < 0 || lanes > ((int64_t)1 << 31) || pairs < 0)
+        return fail(CAPVNDF_ERR_BAD_SIZE,
+                    "estimator_microbench: lanes must be in [0, 2^31], pairs >= 0");
+    if (kind < 0 || kind > 2)
+        return fail(CAPVNDF_ERR_BAD_ARG, "estimator_microbench: kind must be 0, 1 or 2");
+    if (lanes == 0) return CAPVNDF_OK;
+    if (int32_t rc = check_array(out, "out")) return rc;
+    if (kind == 2)
+        if (int32_t rc = check_array(lobes, "lobes")) return rc;
+    const dim3 grid((unsigned)((lanes + kLutBlock - 1) / kLutBlock)), block(kLutBlock);
+    const hipStream_t st = as_stream(stream);
+    const uint32_t k0 = key_lo(seed), k1 = key_hi(seed);
+    if (kind == 0)
+        hipLaunchKernelGGL(k_estimator_microbench<0>, grid, block, 0, st, lanes, pairs, k0, k1,
+                           lobes, out);
+    else if (kind == 1)
+        hipLaunchKernelGGL(k_estimator_microbench<1>, grid, block, 0, st, lanes, pairs, k0, k1,
+                           lobes, out);
+    else
+        hipLaunchKernelGGL(k_estimator_microbench<2>, grid, block, 0, st, lanes, pairs, k0, k1,
+                           lobes, out);
+    return check_launch("estimator_microbench launch");
 }
 
 // ===========================================================================
@@ -789,6 +1007,8 @@ struct capvndf_batch_plan {
     int32_t* d_counter = nullptr;  // dynamic scheduling
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded after every run; destroy waits for it before freeing
+    hipEvent_t done = nullptr;
 };
 
 namespace capvndf {
@@ -904,17 +1124,22 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
     if (int32_t rc = check_launch("batch kernel launch")) return rc;
     if (g)
         hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
-                           p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, (uint64_t)0,
-                           nullptr, p->albedo, p->gax, p->gay, p->gth);
+                           p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, nullptr,
+                           p->albedo, p->gax, p->gay, p->gth);
     else
         hipLaunchKernelGGL(k_finish<1>, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
-                           p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, (uint64_t)0,
-                           nullptr, p->albedo, nullptr, nullptr, nullptr);
+                           p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, nullptr,
+                           p->albedo, nullptr, nullptr, nullptr);
     return check_launch("batch finish launch");
 }
 
 void destroy_plan(capvndf_batch_plan* p) {
     if (!p) return;
+    // a run still in flight reads and writes the memory freed below
+    if (p->done) {
+        (void)hipEventSynchronize(p->done);
+        (void)hipEventDestroy(p->done);
+    }
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->dmem) (void)hipFree(p->dmem);
@@ -932,9 +1157,12 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
         return fail(CAPVNDF_ERR_BAD_SIZE, "albedo_batch_plan_create: njobs must be in [1, 2^31 - 2]");
     if (nsamples_host == nullptr)
         return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_plan_create: nsamples_host is NULL");
-    if (int32_t rc =
-            check_cells("albedo_batch_plan_create", njobs, 0, wox, woy, woz, ax, ay, false))
-        return rc;
+    {
+        const void* req[] = {wox, woy, woz, ax, ay};
+        const char* names[] = {"wox", "woy", "woz", "ax", "ay"};
+        for (int i = 0; i < 5; ++i)
+            if (int32_t rc = check_array(req[i], names[i])) return rc;
+    }
     if (int32_t rc = check_array(albedo, "albedo")) return rc;
     if (f0 != nullptr)
         if (int32_t rc = check_array(f0, "f0")) return rc;
@@ -1028,7 +1256,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
 
     // Device memory: tables, partials, per-request scratch.
     const int nacc = with_grad ? 4 : 1;
-    const int64_t max_cpc = lut_chunks_per_cell(max_n);
+    const int64_t max_cpc = std::max<int64_t>(1, cell_chunks(max_n));
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         const size_t o = off;
@@ -1100,6 +1328,7 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
         rc = rl ? rl : re;
     }
     if (!rc) rc = check_hip(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (!rc) rc = check_hip(hipEventCreateWithFlags(&p->done, hipEventDisableTiming), "hipEventCreateWithFlags");
     if (cap) (void)hipStreamDestroy(cap);
     if (rc) {
         destroy_plan(p);
@@ -1139,7 +1368,9 @@ int32_t check_plan_device(const capvndf_batch_plan* p, const char* who) {
 extern "C" int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream) {
     if (plan == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "albedo_batch_run: plan is NULL");
     if (int32_t rc = check_plan_device(plan, "albedo_batch_run")) return rc;
-    return check_hip(hipGraphLaunch(plan->exec, as_stream(stream)), "hipGraphLaunch");
+    if (int32_t rc = check_hip(hipGraphLaunch(plan->exec, as_stream(stream)), "hipGraphLaunch"))
+        return rc;
+    return check_hip(hipEventRecord(plan->done, as_stream(stream)), "hipEventRecord");
 }
 
 extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* stream) {
@@ -1148,7 +1379,7 @@ extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* str
     // one kLutBlock block per chunk of a job: each launch must fit a 32-bit
     // work-item count; checked for every job before anything is enqueued
     for (int64_t j = 0; j < p->njobs; ++j)
-        if (lut_chunks_per_cell(p->nsamp_host[j]) * kLutBlock > (int64_t)0xffffffff)
+        if (cell_chunks(p->nsamp_host[j]) > kMaxBlocks)
             return fail(CAPVNDF_ERR_BAD_SIZE,
                         "albedo_batch_run_per_request: job %lld has %lld samples, more than one "
                         "launch of this path covers (2^24 - 1 chunks of %llu samples)",
@@ -1157,26 +1388,31 @@ extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* str
     const hipStream_t st = as_stream(stream);
     const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
     for (int64_t j = 0; j < p->njobs; ++j) {
-        const int64_t n = p->nsamp_host[j];
-        const int64_t cpc = lut_chunks_per_cell(n);
+        // the table kernels on one cell, one slot per chunk of the job
+        const int32_t cpc = (int32_t)cell_chunks(p->nsamp_host[j]);
+        const int32_t slots = std::max<int32_t>(cpc, 1);
         const float* f0 = p->f0 ? p->f0 + j : nullptr;
+        const int64_t* nj = p->d_nsamp + j;
         if (p->with_grad) {
-            hipLaunchKernelGGL(k_albedo_adj<true>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
-                               p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
-                               (uint64_t)n, (int32_t)cpc, (uint32_t)j, k0, k1, p->d_req_ws);
+            if (cpc > 0)
+                hipLaunchKernelGGL(k_albedo_adj<true>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
+                                   p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
+                                   nj, slots, (uint32_t)j, k0, k1, p->d_req_ws);
             hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
-                               p->d_req_ws, (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr,
-                               p->albedo + j, p->gax + j, p->gay + j, p->gth + j);
+                               p->d_req_ws, slots, nullptr, nj, nullptr, p->albedo + j,
+                               p->gax + j, p->gay + j, p->gth + j);
         } else {
-            hipLaunchKernelGGL(k_albedo_fwd<1>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
-                               p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
-                               (uint64_t)n, (int32_t)cpc, (uint32_t)j, k0, k1, p->d_req_ws);
+            if (cpc > 0)
+                hipLaunchKernelGGL(k_albedo_fwd<1>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
+                                   p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
+                                   nj, slots, (uint32_t)j, k0, k1, p->d_req_ws);
             hipLaunchKernelGGL(k_finish<1>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
-                               p->d_req_ws, (int32_t)cpc, nullptr, nullptr, (uint64_t)n, nullptr,
-                               p->albedo + j, nullptr, nullptr, nullptr);
+                               p->d_req_ws, slots, nullptr, nj, nullptr, p->albedo + j, nullptr,
+                               nullptr, nullptr);
         }
     }
-    return check_launch("albedo_batch_run_per_request launch");
+    if (int32_t rc = check_launch("albedo_batch_run_per_request launch")) return rc;
+    return check_hip(hipEventRecord(p->done, st), "hipEventRecord");
 }
 
 extern "C" int32_t albedo_batch_plan_info(const capvndf_batch_plan* plan, capvndf_tiling* tiling,

@@ -25,6 +25,8 @@ struct CellConst {
     float go;          // G1(wo)
     float tgo;         // 2 - G1(wo)
     float tx, ty, tz;  // meridian tangent dwo/dtheta_o
+    float rx, ry, rz;  // the view direction as given (for the double-precision path)
+    float amax;        // max(1, ax, ay)
     bool ok;           // inside the domain
 };
 
@@ -34,6 +36,10 @@ __device__ __forceinline__ CellConst cell_setup(float wx, float wy, float wz, fl
     if (!c.ok) {
         wx = 0.0f; wy = 0.0f; wz = 1.0f; ax = 1.0f; ay = 1.0f;
     }
+    c.rx = wx;
+    c.ry = wy;
+    c.rz = wz;
+    c.amax = fmaxf(1.0f, fmaxf(ax, ay));
     const float in = rsq(__builtin_fmaf(wx, wx, __builtin_fmaf(wy, wy, wz * wz)));
     c.ox = wx * in;
     c.oy = wy * in;
@@ -83,16 +89,17 @@ __device__ __forceinline__ FwdTerm albedo_fwd(const CellConst& c, float u1, floa
 
 // Synthetic incident radiance for the direct-illumination estimator: up to
 // kMaxLobes spherical-Gaussian lobes L(w) = sum lambda exp(kappa (mu.w - 1)),
-// held per lane (uniform values) with kappa pre-scaled by log2(e) for the
-// hardware base-2 exponential.  The lobe count is a compile-time parameter:
-// with a run-time count the compiler evaluated all kMaxLobes lobes and
-// selected the live ones.
+// held per lane (uniform values).  For the hardware base-2 exponential each
+// lobe keeps b = kappa log2(e) mu and c = kappa log2(e), so that its exponent
+// b.w - c is three fused multiply-adds.  The lobe count is a compile-time
+// parameter: with a run-time count the compiler evaluated all kMaxLobes lobes
+// and selected the live ones.
 constexpr int kMaxLobes = 8;
 
 template <int NL>
 struct Lobes {
     static constexpr int kN = NL > 0 ? NL : 1;
-    float mx[kN], my[kN], mz[kN], k2[kN], lam[kN];
+    float bx[kN], by[kN], bz[kN], nc[kN], lam[kN];  // b, -c, lambda
 };
 
 template <int NL>
@@ -100,10 +107,11 @@ __device__ __forceinline__ Lobes<NL> load_lobes(const float* __restrict__ p) {
     Lobes<NL> l;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        l.mx[k] = p[5 * k];
-        l.my[k] = p[5 * k + 1];
-        l.mz[k] = p[5 * k + 2];
-        l.k2[k] = p[5 * k + 3] * 1.4426950408889634f;
+        const float k2 = p[5 * k + 3] * 1.4426950408889634f;
+        l.bx[k] = p[5 * k] * k2;
+        l.by[k] = p[5 * k + 1] * k2;
+        l.bz[k] = p[5 * k + 2] * k2;
+        l.nc[k] = -k2;
         l.lam[k] = p[5 * k + 4];
     }
     return l;
@@ -114,8 +122,9 @@ __device__ __forceinline__ float lobe_radiance(const Lobes<NL>& l, float wx, flo
     float r = 0.0f;
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-        const float c = __builtin_fmaf(l.mx[k], wx, __builtin_fmaf(l.my[k], wy, l.mz[k] * wz));
-        r = __builtin_fmaf(l.lam[k], __builtin_amdgcn_exp2f(__builtin_fmaf(l.k2[k], c, -l.k2[k])), r);
+        const float e = __builtin_fmaf(l.bx[k], wx, __builtin_fmaf(l.by[k], wy,
+                                                                   __builtin_fmaf(l.bz[k], wz, l.nc[k])));
+        r = __builtin_fmaf(l.lam[k], __builtin_amdgcn_exp2f(e), r);
     }
     return r;
 }
@@ -150,7 +159,123 @@ __device__ __forceinline__ float radiance_term(const CellConst& c, float f0, con
 // applied once per thread by ws_chain().
 struct AdjTerm {
     float w, dax, day, dth, dwsx, dwsy, dzs;
+    bool amb;  // FP32 cannot place the reflection relative to the horizon
 };
+
+// Reflections within the FP32 path's rounding of the horizon.  The FP32
+// normal is within (8 + 48 kappa) 2^-24 of the exact one (first-order count,
+// kappa = max(1, ax, ay) / L with L = |M^-T hs|), and wl = 2 (wo.h) h - wo
+// multiplies that by 4 and adds the roundings of the dot product, the
+// reflection and wo's normalisation: wl_z within (44 + 192 kappa) 2^-24 of 0
+// may lie on either side of the horizon, where the weight's slope jumps from
+// its live value to 0.  albedo_adj flags such samples (a few in 10^5), and
+// the sample loops evaluate them again in double precision after their pass
+// over the chunk, replacing the FP32 terms.
+constexpr float kBandC0 = 44.0f * 0x1p-24f;
+constexpr float kBandC1 = 192.0f * 0x1p-24f;
+// Beyond this conditioning the FP32 sample's terms carry relative errors
+// above about 1 % ((35 + 200 kappa) 2^-24); such samples take the double path
+// too, wherever their reflection lies.
+constexpr float kIllConditioned = 1024.0f;
+
+// albedo_adj's value and derivatives in double precision from the cell's
+// inputs as given (the same steps; the FP32 view direction, roughness and
+// uniforms are exact in double), rounded to FP32 at the end.
+__device__ __attribute__((noinline)) AdjTerm albedo_adj_f64(const CellConst& c, float f0f,
+                                                            float u1f, float u2f) {
+    // cell constants
+    const double rx = c.rx, ry = c.ry, rz = c.rz, ax = c.ax, ay = c.ay;
+    const double in = rsq_f64(__builtin_fma(rx, rx, __builtin_fma(ry, ry, rz * rz)));
+    const double ox = rx * in, oy = ry * in, oz = rz * in;
+    const double px = ax * ox, py = ay * oy;
+    const double q = __builtin_fma(px, px, py * py);
+    const double l2 = __builtin_fma(oz, oz, q);
+    const double il = rsq_f64(l2);
+    const double lpz = l2 * il + oz;
+    const double wsx = px * il, wsy = py * il, zs = oz * il;
+    const double opz = lpz * il, omz = q * il * rcp_f64(lpz);
+    const double iopz = rcp_f64(opz);
+    const double go = 2.0 * zs * iopz, tgo = 2.0 - go;
+    const double rho2 = __builtin_fma(ox, ox, oy * oy);
+    double tx = oz, ty = 0.0, tz = 0.0;
+    if (rho2 > 0.0) {
+        const double ir = rsq_f64(rho2);
+        tx = oz * ox * ir;
+        ty = oz * oy * ir;
+        tz = -rho2 * ir;
+    }
+    // forward sweep
+    const double u2 = u2f, a = 1.0 - u2;
+    const double hsz = a * opz;
+    const double s2 = u2 * opz * (hsz + omz);
+    const bool apex = !(s2 > 0.0);
+    const double ist = apex ? 0.0 : rsq_f64(s2);
+    const double st = s2 * ist;
+    double sp, cp;
+    sincos_turns_f64(u1f, &sp, &cp);
+    const double hsx = __builtin_fma(st, cp, wsx);
+    const double hsy = __builtin_fma(st, sp, wsy);
+    const double vx = ax * hsx, vy = ay * hsy, vz = hsz;
+    const double iL = rsq_f64(__builtin_fma(vx, vx, __builtin_fma(vy, vy, vz * vz)));
+    const double hx = vx * iL, hy = vy * iL, hz = vz * iL;
+    const double x = __builtin_fma(ox, hx, __builtin_fma(oy, hy, oz * hz));
+    const double x2 = x + x;
+    const double wlx = __builtin_fma(x2, hx, -ox);
+    const double wly = __builtin_fma(x2, hy, -oy);
+    const double wlz = __builtin_fma(x2, hz, -oz);
+    const double plx = ax * wlx, ply = ay * wly;
+    const double pp = __builtin_fma(plx, plx, ply * ply);
+    const double m2 = __builtin_fma(wlz, wlz, pp);
+    const double im = rsq_f64(m2);
+    const double ml = m2 * im;
+    const bool live = wlz > 0.0;
+    const double wz0 = live ? wlz : 0.0;
+    const double iD = rcp_f64(__builtin_fma(go, ml, tgo * wz0));
+    const double g = 2.0 * wz0 * iD;
+    const double mx = 1.0 - x, mm = mx * mx, m4 = mm * mm;
+    const double f0 = f0f, f1 = 1.0 - f0;
+    const double F = __builtin_fma(f1, m4 * mx, f0);
+    // reverse sweep (as albedo_adj)
+    double dx = -5.0 * f1 * m4 * g;
+    const double ft2 = F * 2.0 * iD * iD;
+    const double e = ft2 * go * im;
+    const double dwlz = live ? e * pp : 0.0;
+    const double ew = -e * wz0;
+    const double dplx = ew * plx, dply = ew * ply;
+    const double dgo = -ft2 * wz0 * (ml - wz0);
+    double dax = dplx * wlx, day = dply * wly;
+    const double dwlx = dplx * ax, dwly = dply * ay;
+    dx += 2.0 * __builtin_fma(dwlx, hx, __builtin_fma(dwly, hy, dwlz * hz));
+    double dhx = x2 * dwlx, dhy = x2 * dwly, dhz = x2 * dwlz;
+    dhx = __builtin_fma(dx, ox, dhx);
+    dhy = __builtin_fma(dx, oy, dhy);
+    dhz = __builtin_fma(dx, oz, dhz);
+    const double dox = __builtin_fma(dx, hx, -dwlx);
+    const double doy = __builtin_fma(dx, hy, -dwly);
+    const double doz = __builtin_fma(dx, hz, -dwlz);
+    const double hd = __builtin_fma(hx, dhx, __builtin_fma(hy, dhy, hz * dhz));
+    const double dvx = iL * __builtin_fma(-hx, hd, dhx);
+    const double dvy = iL * __builtin_fma(-hy, hd, dhy);
+    const double dvz = iL * __builtin_fma(-hz, hd, dhz);
+    dax = __builtin_fma(dvx, hsx, dax);
+    day = __builtin_fma(dvy, hsy, day);
+    const double dhsx = dvx * ax, dhsy = dvy * ay;
+    const double dst = __builtin_fma(dhsx, cp, dhsy * sp);
+    const double ds2u = apex ? 0.0 : 0.5 * dst * ist * u2;
+    const double dopz = __builtin_fma(dvz, a, ds2u * (2.0 * hsz + omz));
+    const double domz = ds2u * opz;
+    const double dzs = __builtin_fma(dgo * 2.0 * iopz, iopz, dopz - domz);
+    AdjTerm r;
+    r.w = (float)(F * g);
+    r.dax = (float)dax;
+    r.day = (float)day;
+    r.dth = (float)__builtin_fma(tx, dox, __builtin_fma(ty, doy, tz * doz));
+    r.dwsx = (float)dhsx;
+    r.dwsy = (float)dhsy;
+    r.dzs = (float)dzs;
+    r.amb = false;
+    return r;
+}
 
 __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, float u1, float u2) {
     const Stretched& s = c.s;
@@ -175,6 +300,8 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     const float wlx = __builtin_fmaf(x2, hx, -c.ox);
     const float wly = __builtin_fmaf(x2, hy, -c.oy);
     const float wlz = __builtin_fmaf(x2, hz, -c.oz);
+    const float kap = c.amax * iL;
+    const bool amb = !(fabsf(wlz) > __builtin_fmaf(kBandC1, kap, kBandC0)) || kap > kIllConditioned;
     const float plx = c.ax * wlx, ply = c.ay * wly;
     const float pp = __builtin_fmaf(plx, plx, ply * ply);
     const float m2 = __builtin_fmaf(wlz, wlz, pp);
@@ -242,6 +369,7 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     r.dwsx = dhsx;
     r.dwsy = dhsy;
     r.dzs = dzs;
+    r.amb = amb;
     return r;
 }
 

@@ -1,36 +1,70 @@
-"""Helpers shared by the GPU parity tests: device transfer and the tolerance
-rules the comparisons use.
+"""Helpers shared by the GPU parity tests: device transfer, the oracle's
+stored values for the estimator workloads, and the tolerance rules the
+comparisons use.
 
-Tolerance of sampled normals and pdfs (FP32 GPU vs FP64 oracle on the same
-FP32 inputs and the same uniforms).  The half vector hs = c + ws of the cap
-construction is the sum of two unit vectors, so its components carry absolute
-rounding errors of O(2^-24) however small hs is.  The normal is
-h = M^-T hs / L with L = |M^-T hs| (M^-T = diag(ax, ay, 1)), so those errors
-reach h as O(2^-24 max(1, ax, ay) / L) and reach the pdf (which goes as
-L^3 / |hs|^2) as a relative error of the same order.  The condition number
-kappa = max(1, ax, ay) / L (= 1 / L for roughness up to 1) is computed from the
-oracle's normal: with h_std = M^T h / |M^T h|, |hs| = 2 ws . h_std and
-L = |hs| / |M^T h|.  Rule: every sample has err <= max(2e-6, C 2^-24 kappa)
-(C = 64 for h, 128 for the pdf), and every sample with kappa <= 3.5 has
-err <= 2e-6.  The second threshold comes from all 2^26 samples of the
-streaming workload: the largest pdf error per band of kappa grows as about
-9 2^-24 kappa (1.06e-6 below kappa 2, 1.72e-6 below 4, 2.04e-6 below 5), so
-2e-6 is crossed near kappa 3.7.  The flat 2e-6 on every sample is the
-double-precision method's bound.
+Normals and pdfs (GPU vs FP64 oracle on the same FP32 inputs and uniforms):
 
-Heitz's disk sampler (the timing baseline) builds the hemisphere normal from
-its height above the disk, ti = sqrt(1 - t1^2 - t2^2) = ws . h_std, whose
-argument cancels at the rim: ti carries a relative error of O(2^-24 / ti^2),
-which its pdf inherits.  Its pdf is checked with kappa = 1 / L + 1 / ti^2 and
-without the 2e-6 clause (that target is the cap method's; the baseline's
-literal FP32 arithmetic reaches about 3e-6 on well-conditioned samples).
+* The double-precision method (CAPVNDF_CAP_F64, the default and the
+  benchmark's) is held to the flat bound of the target: every h within 2e-6
+  (|h - h_ref|) and every pdf within 2e-6 relative.
+
+* The FP32-arithmetic method (CAPVNDF_CAP) forms the half vector
+  hs = c + ws from two unit vectors whose components carry absolute rounding
+  errors, so its error grows with the conditioning
+  kappa = max(1, ax, ay) / L, L = |M^-T hs| (M^-T = diag(ax, ay, 1)).  A
+  first-order worst-case count of its roundings (u = 2^-24 per correctly
+  rounded operation, 2u for the hardware rsq / rcp / sqrt, 2.1u absolute for
+  the turn-based sin / cos, measured exhaustively over the 2^-24 lattice)
+  bounds the absolute error of hs by 40u, so |h - h_ref| <= (8 + 40 kappa) u
+  (direction through the unstretch, plus the normalisation's roundings), and
+  the pdf L^3 / (pi ax ay (1 + zs) |hs|^2), which moves by 3 times the
+  relative error of L and 2 times that of |hs| (each at most 40 kappa u),
+  by (35 + 200 kappa) u.  The tests allow 20 % over these first-order counts
+  for the neglected higher-order terms: (8 + 48 kappa) u and
+  (40 + 240 kappa) u.  kappa is computed from the oracle's normal: with
+  h_std = M^T h / |M^T h|, |hs| = 2 ws . h_std and L = |hs| / |M^T h|.  The
+  fraction of samples above 2e-6 is reported.
+
+* Heitz's disk sampler (the timing baseline) builds the hemisphere normal from
+  its height above the disk, ti = sqrt(1 - t1^2 - t2^2) = ws . h_std, whose
+  argument cancels at the rim: ti carries a relative error of O(2^-24 / ti^2),
+  which its pdf inherits.  Its pdf is checked against 128 u (1 / L + 1 / ti^2).
 """
+
+import importlib.util
+import os
 
 import numpy as np
 import torch
 
 EPS32 = 2.0 ** -24
-KAPPA_WELL = 3.5  # conditioning up to which the FP32 sampler stays within 2e-6
+# first-order worst-case bounds of the FP32-arithmetic cap sampler, in units
+# of 2^-24: |h - h_ref| <= H_A + H_B kappa, pdf relative <= P_A + P_B kappa
+H_A, H_B = 8.0, 48.0
+P_A, P_B = 40.0, 240.0
+
+_GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_golden_cache = {}
+
+
+def golden(part):
+    """The oracle's stored values for every unit of one estimator workload
+    ("lut", "grad" or "batch"), written by tests/golden/make_estimator_golden.py.
+    The digest of the inputs it was computed on must match the inputs the
+    workload generator gives now."""
+    if "mk" not in _golden_cache:
+        spec = importlib.util.spec_from_file_location(
+            "make_estimator_golden", os.path.join(_GOLDEN_DIR, "make_estimator_golden.py"))
+        mk = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mk)
+        with np.load(mk.OUT, allow_pickle=False) as f:
+            _golden_cache["data"] = {k: f[k] for k in f.files}
+        _golden_cache["mk"] = mk
+    mk, data = _golden_cache["mk"], _golden_cache["data"]
+    inputs = {"lut": mk.lut_inputs, "grad": mk.grad_inputs, "batch": mk.batch_inputs}[part]()
+    assert str(data[f"{part}_digest"]) == mk.digest(inputs), \
+        f"{part}: the stored oracle values were computed on other inputs; rerun the script"
+    return data
 
 
 def to_dev(arrs, dev="cuda"):
@@ -71,18 +105,31 @@ def kappa_disk_pdf(h_ref, wx, wy, wz, ax, ay):
     return k + 1.0 / (ti * ti)
 
 
-def check_conditioned(err, kap, c, name, strict_well=True):
-    lim = np.maximum(2e-6, c * EPS32 * kap)
+def check_conditioned(err, kap, a, b, name):
+    """Every sample within (a + b kappa) 2^-24; reports the largest
+    err / (2^-24 kappa) and the fraction of samples above 2e-6."""
+    lim = (a + b * kap) * EPS32
     bad = err > lim
     assert not bad.any(), f"{name}: {bad.sum()} samples over the limit, worst " \
         f"{err[bad].max():.3e} at kappa {kap[bad][np.argmax(err[bad])]:.3e}"
-    well = kap <= KAPPA_WELL
-    if strict_well:
-        assert np.all(err[well] <= 2e-6), f"{name}: well-conditioned max {err[well].max():.3e}"
     ratio = err / (EPS32 * kap)
     print(f"{name}: max err {err.max():.3e}, max err/(eps kappa) {ratio.max():.2f}, "
-          f"fraction > 2e-6 {(err > 2e-6).mean():.2e}, max kappa {kap.max():.3e}")
+          f"max err/limit {(err / lim).max():.3f}, fraction > 2e-6 {(err > 2e-6).mean():.2e}, "
+          f"max kappa {kap.max():.3e}")
     return float((err > 2e-6).mean())
+
+
+def check_flat(H, P, h_ref, p_ref, name, lim=2e-6):
+    """Every h within lim of the oracle's and every pdf within lim relative;
+    zero pdfs exactly where the oracle's are zero."""
+    herr = np.linalg.norm(H - h_ref, axis=1)
+    ok = p_ref > 0
+    perr = np.abs(P[ok] / p_ref[ok] - 1.0)
+    print(f"{name}: max |h - h_ref| {herr.max():.2e}, max pdf rel {perr.max():.2e} "
+          f"over {len(herr)} samples")
+    assert herr.max() <= lim, (name, herr.max())
+    assert perr.max() <= lim, (name, perr.max())
+    assert np.array_equal(P > 0, ok)
 
 
 # A call of more than 2^31 elements (the element-wise entry points split it

@@ -53,3 +53,49 @@ def test_alu_roofline_arithmetic():
     assert r["achieved"] == pytest.approx(ips * 4096 * 2 ** 20 / 12.8e-3 / 1e12, rel=1e-3)
     assert r["peak"] == pytest.approx(256 * 128 * 2.4e9 / 1e12, rel=1e-4)
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
+
+
+FIXTURE = os.path.join(ROOT, "tests", "fixtures", "rocprof")
+
+
+def test_profile_summaries_from_rocprof_csv(tmp_path):
+    """--summarize-profiles on a trimmed copy of real rocprofv3 CSV output:
+    the trace average, the counter calibration and the lane-instructions per
+    sample are the arithmetic the summaries claim."""
+    import csv
+    import numpy as np
+    done = bench.summarize_profiles(FIXTURE, prof=str(tmp_path), batch_samples=2073825747)
+    assert done == ["stream_sampler_2p26", "stream_sampler_2p26_counters", "albedo_valu_counters"]
+    # trace: the headline kernel's mean duration
+    rows = list(csv.DictReader(open(os.path.join(FIXTURE, "trace", "run_kernel_trace.csv"))))
+    dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows
+           if "k_sample_v4<2," in r["Kernel_Name"]]
+    rec = json.load(open(tmp_path / "stream_sampler_2p26.json"))
+    assert rec["kernel"] == "k_sample_v4<2, false, true, 1>"
+    assert rec["trace_avg_us"] == pytest.approx(np.mean(dur) / 1e3, abs=0.01)
+    assert rec["frac_trace"] == pytest.approx(36 * 2 ** 26 / (np.mean(dur) * 1e-9) / 8e12,
+                                              abs=1e-4)
+    plain = json.load(open(os.path.join(FIXTURE, "bench_plain.json")))
+    assert rec["event_ms_same_box"] == plain["ms_per_step"]
+    assert "$REPO/bench.py --only stream fp32 disk probe" in rec["command_trace"]
+    # traffic: calibration by the probe whose traffic is known
+    def mean_counter(sub, kernel, name):
+        rs = list(csv.DictReader(open(os.path.join(FIXTURE, sub, "run_counter_collection.csv"))))
+        return np.mean([float(r["Counter_Value"]) for r in rs
+                        if kernel in r["Kernel_Name"] and r["Counter_Name"] == name])
+    t = json.load(open(tmp_path / "stream_sampler_2p26_counters.json"))
+    fs = 20 * 2 ** 26 / 1024 / mean_counter("fetch", "k_stream_probe<0>", "FETCH_SIZE")
+    ws = 16 * 2 ** 26 / 1024 / mean_counter("write", "k_stream_probe<0>", "WRITE_SIZE")
+    assert t["fetch_scale"] == pytest.approx(fs) and t["write_scale"] == pytest.approx(ws)
+    head = (mean_counter("fetch", "k_sample_v4<2,", "FETCH_SIZE") * fs +
+            mean_counter("write", "k_sample_v4<2,", "WRITE_SIZE") * ws) * 1024
+    assert t["hbm_bytes_per_launch"] == pytest.approx(head)
+    assert abs(head / (36 * 2 ** 26) - 1) < 1e-3
+    # VALU: SQ_INSTS_VALU x 64 / samples of one dispatch
+    v = json.load(open(tmp_path / "albedo_valu_counters.json"))
+    ips = v["valu_lane_instr_per_sample"]
+    assert ips["forward_two_sums"] == pytest.approx(
+        mean_counter("valu_a", "k_albedo_fwd<0>", "SQ_INSTS_VALU") * 64 / (4096 * 2 ** 20))
+    assert ips["batch:k_batch<256, true, true>"] == pytest.approx(
+        mean_counter("valu_b", "k_batch<256, true, true>", "SQ_INSTS_VALU") * 64 / 2073825747)
+    assert 60 < ips["forward_two_sums"] < 90 and 120 < ips["value_and_grad"] < 180

@@ -88,44 +88,60 @@ def test_sample_argument_errors(lib):
 def test_albedo_argument_errors(lib):
     P = ctypes.c_void_p
     fake = P(0x1000)
-    assert lib.albedo_workspace_size(-1, 10, 0) == 0
-    assert lib.albedo_workspace_size(4096, 1 << 20, 0) == 4096 * 64 * 2 * 2 * 4
-    assert lib.albedo_workspace_size(4096, 1 << 20, 1) == 4096 * 64 * 3 * 2 * 4
-    assert lib.albedo_workspace_size(3, 1, 0) == 3 * 1 * 2 * 2 * 4
-    assert lib.albedo_workspace_size(4096, 1 << 20, 2) == 4096 * 64 * 4 * 2 * 4
-    assert lib.albedo_workspace_size(16, 1 << 20, 3) == 0
+    i64 = ctypes.c_int64
+
+    def counts(*v):
+        return (i64 * len(v))(*v)
+
+    # workspace: ncells * slots * partial sums * 8 bytes; slots per cell aim
+    # at 8192 blocks with at least 64, below 2^24 blocks, and (given host
+    # counts) no more than the largest cell's chunks of 16384 samples
+    assert lib.albedo_workspace_size(-1, None, 0) == 0
+    assert lib.albedo_workspace_size(0, None, 0) == 0
+    assert lib.albedo_workspace_size(1 << 24, None, 0) == 0
+    assert lib.albedo_workspace_size(16, None, 2) == 0
+    assert lib.albedo_workspace_size(4096, None, 0) == 4096 * 64 * 2 * 8
+    assert lib.albedo_workspace_size(4096, None, 1) == 4096 * 64 * 4 * 8
+    assert lib.albedo_workspace_size(4096, counts(*[1 << 20] * 4096), 0) == 4096 * 64 * 2 * 8
+    assert lib.albedo_workspace_size(4096, counts(*[4096] * 4096), 1) == 4096 * 1 * 4 * 8
+    assert lib.albedo_workspace_size(1, None, 0) == 8192 * 2 * 8
+    assert lib.albedo_workspace_size(1, counts(1 << 20), 0) == 64 * 2 * 8
+    assert lib.albedo_workspace_size(1, counts(1 << 30), 1) == 8192 * 4 * 8
+    assert lib.albedo_workspace_size(3, counts(0, 1, 0), 0) == 3 * 1 * 2 * 8
+    assert lib.albedo_workspace_size(2, counts(0, 0), 0) == 2 * 1 * 2 * 8
+    assert lib.albedo_workspace_size(1 << 20, None, 0) == (1 << 20) * 15 * 2 * 8
+    assert lib.albedo_workspace_size(2, counts(5, -1), 0) == 0
+    assert lib.albedo_workspace_size(2, counts(5, 1 << 40), 0) == 0
     five = [fake] * 5
-    assert lib.albedo_estimate(-1, *five, 10, 0, fake, fake, fake, 1 << 20, None) == -2
-    assert lib.albedo_estimate(4, *five, -3, 0, fake, fake, fake, 1 << 20, None) == -2
-    assert lib.albedo_estimate(4, *five, 1 << 40, 0, fake, fake, fake, 1 << 20, None) == -2
-    assert lib.albedo_estimate(4, *five, 100, 0, fake, fake, fake, 8, None) == -5
-    assert "workspace" in _err(lib)
-    # fewer than 2^24 chunks of 16384 samples (one 256-lane block each, and a
-    # dispatch counts work-items in 32 bits): 2^12 cells of 2^26 samples are
-    # exactly 2^24 chunks, one too many; one sample less per cell still is
-    assert lib.albedo_workspace_size(1 << 12, 1 << 26, 0) == (1 << 24) * 2 * 2 * 4
-    assert lib.albedo_estimate(1 << 12, *five, 1 << 26, 0, fake, fake, fake, 1 << 62,
-                               None) == -2
+    assert lib.albedo_estimate(-1, *five, fake, 0, fake, fake, fake, 1 << 20, None) == -2
+    assert lib.albedo_estimate(1 << 24, *five, fake, 0, fake, fake, fake, 1 << 62, None) == -2
     assert "below 2^24" in _err(lib)
-    assert lib.radiance_estimate(1 << 12, *five, None, 1 << 26, 0, None, 0, fake, fake,
-                                 1 << 62, None) == -2
-    # (2^12 - 1) cells pass the size check and fail on the NULL output instead
-    assert lib.albedo_estimate((1 << 12) - 1, *five, 1 << 26, 0, None, fake, fake, 1 << 62,
-                               None) == -1
-    assert lib.albedo_estimate(4, *five, 100, 0, fake, fake, None, 0, None) == -5
-    assert lib.albedo_estimate(0, *[None] * 5, 100, 0, None, None, None, 0, None) == 0
-    assert lib.albedo_estimate_backward(4, *five, 100, 0, None, None, fake, fake, fake, fake, 8,
-                                        None) == -5
-    # value_and_grad: partial gradient outputs, small workspace
-    assert lib.albedo_value_and_grad(4, *five, 100, 0, None, fake, fake, None, None, fake,
+    assert lib.radiance_estimate(1 << 24, *five, None, fake, 0, None, 0, fake, fake, 1 << 62,
+                                 None) == -2
+    assert lib.albedo_estimate(4, *five, None, 0, fake, fake, fake, 1 << 20, None) == -1
+    assert "nsamples" in _err(lib)
+    assert lib.albedo_estimate(4, *five, P(0x1004), 0, fake, fake, fake, 1 << 20, None) == -3
+    assert lib.albedo_estimate(4, *five, fake, 0, fake, fake, fake, 4 * 16 - 1, None) == -5
+    assert "workspace" in _err(lib)
+    assert lib.albedo_estimate(4, *five, fake, 0, fake, fake, None, 1 << 20, None) == -5
+    assert lib.albedo_estimate(4, *five, fake, 0, fake, fake, P(0x1008), 1 << 20, None) == -3
+    assert lib.albedo_estimate(4, *five, fake, 0, None, fake, fake, 1 << 20, None) == -1
+    assert lib.albedo_estimate(0, *[None] * 5, None, 0, None, None, None, 0, None) == 0
+    assert lib.albedo_estimate_backward(4, *five, fake, 0, None, None, fake, fake, fake, fake,
+                                        4 * 24 - 1, None) == -5
+    # value_and_grad: partial gradient outputs, small workspace, no value output
+    assert lib.albedo_value_and_grad(4, *five, fake, 0, None, fake, fake, None, None, fake,
                                      1 << 20, None) == -1
-    assert lib.albedo_value_and_grad(4, *five, 100, 0, None, fake, fake, fake, fake, fake, 8,
-                                     None) == -5
-    assert lib.albedo_value_and_grad(4, *five, 100, 0, None, None, None, None, None, fake, 1 << 20,
-                                     None) == -1
-    assert lib.radiance_estimate(4, *five, None, 100, 0, fake, 9, fake, fake, 1 << 20, None) == -2
-    assert lib.radiance_estimate(4, *five, None, 100, 0, None, 2, fake, fake, 1 << 20, None) == -1
-    assert lib.radiance_estimate(4, *five, None, 100, 0, fake, 2, fake, fake, 4, None) == -5
+    assert lib.albedo_value_and_grad(4, *five, fake, 0, None, fake, fake, fake, fake, fake,
+                                     4 * 32 - 1, None) == -5
+    assert lib.albedo_value_and_grad(4, *five, fake, 0, None, None, None, None, None, fake,
+                                     4 * 8 - 1, None) == -1
+    assert lib.albedo_value_and_grad(4, *five, fake, 0, None, fake, None, None, None, fake,
+                                     4 * 8 - 1, None) == -5
+    assert lib.radiance_estimate(4, *five, None, fake, 0, fake, 9, fake, fake, 1 << 20, None) == -2
+    assert lib.radiance_estimate(4, *five, None, fake, 0, None, 2, fake, fake, 1 << 20, None) == -1
+    assert lib.radiance_estimate(4, *five, None, fake, 0, fake, 2, fake, fake, 4 * 8 - 1,
+                                 None) == -5
     out = P()
     ns = (ctypes.c_int64 * 2)(10, 20)
     assert lib.albedo_batch_plan_create(0, *five, None, ns, 0, 1, fake, fake, fake, fake, None,

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads
-from _gpu import host, to_dev
+from _gpu import golden, host, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -64,21 +64,106 @@ def test_lut_edges():
     assert s1.numel() == 0
 
 
-def test_lut_full_size_sampled():
-    """64 x 64 cells x 2^20 samples (the LUT workload); 64 cells vs oracle."""
+def _uneven_counts(ncells):
+    """Per-cell counts: empty, single, odd, chunk boundaries (16384 samples
+    per chunk), and one cell with more chunks (257) than a call of this many
+    cells gives it slots (128), so that slots loop over several chunks."""
+    base = [0, 1, 2, 3, 4097, 16383, 16384, 16385, 32769, 70001, (1 << 22) + 12345]
+    rng = np.random.default_rng(31)
+    rest = rng.integers(0, 1 << 15, ncells - len(base))
+    return np.concatenate([base, rest]).astype(np.int64)
+
+
+def test_uneven_counts():
+    """Every table estimator with its own sample count per cell (host counts
+    and a device count tensor), against the oracle on the same counts."""
+    g = workloads.lut_grid(8, 8)
+    t = to_dev(g)
+    ns = _uneven_counts(64)
+    wo = (g["wx"], g["wy"], g["wz"])
+    a1 = oracle.albedo(wo, g["ax"], g["ay"], ns, 12, f0=1.0)
+    a5 = oracle.albedo(wo, g["ax"], g["ay"], ns, 12, f0=0.0)
+    f0 = np.where(np.arange(64) % 2 == 0, 0.04, 1.0).astype(np.float32)
+    A, rx, ry, rt = oracle.albedo_grad(wo, g["ax"], g["ay"], ns, 12, f0=f0)
+    gf = torch.from_numpy(f0).cuda()
+    for counts in (ns, torch.from_numpy(ns).cuda()):
+        s1, s5 = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], counts, 12)
+        assert np.abs(host(s1) - a1).max() <= ATOL_A
+        assert np.abs(host(s5) - a5).max() <= ATOL_A
+        assert host(s1)[0] == 0 and host(s5)[0] == 0  # an empty cell
+        a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                                                 counts, 12, f0=gf)
+        assert np.abs(host(a) - A).max() <= ATOL_A
+        _check_grad(host(gx), rx, "uneven d/d alpha_x")
+        _check_grad(host(gy), ry, "uneven d/d alpha_y")
+        _check_grad(host(gt), rt, "uneven d/d theta_o")
+        bx, by, bt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                                                 counts, 12, f0=gf)
+        for u, v in ((gx, bx), (gy, by), (gt, bt)):
+            assert torch.allclose(u, v, rtol=1e-5, atol=1e-6)
+    # host counts size the workspace for at most the largest cell's chunks,
+    # device counts for the most slots: with one chunk per slot in both, the
+    # bits agree; the big cell (257 chunks) is summed over different slots
+    h1, _ = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], ns, 12)
+    d1, _ = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
+                               torch.from_numpy(ns).cuda(), 12)
+    small = ns < 128 * 16384
+    assert torch.equal(h1[torch.from_numpy(small).cuda()], d1[torch.from_numpy(small).cuda()])
+
+
+def test_one_slot_per_cell():
+    """The smallest workspace (one partial per cell): every slot sums all of
+    its cell's chunks; results stay within the parity bounds."""
+    g = workloads.lut_grid(4, 4)
+    t = to_dev(g)
+    ns = np.array([0, 1, 70001, 1 << 18] * 4, dtype=np.int64)
+    ws = torch.empty(16 * 4 * 2, device="cuda")  # 16 cells x 4 sums x (s, c)
+    a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], ns, 14,
+                                             workspace=ws)
+    A, rx, ry, rt = oracle.albedo_grad((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], ns, 14)
+    assert np.abs(host(a) - A).max() <= ATOL_A
+    _check_grad(host(gx), rx, "one slot d/d alpha_x")
+    _check_grad(host(gy), ry, "one slot d/d alpha_y")
+    _check_grad(host(gt), rt, "one slot d/d theta_o")
+
+
+def test_invalid_count_gives_nan():
+    """A device count outside [0, 2^40) cannot be checked on the host: that
+    cell's outputs are NaN and the other cells are unaffected."""
+    g = workloads.lut_grid(2, 2)
+    t = to_dev(g)
+    ns = torch.tensor([1000, -5, 1 << 40, 3000], dtype=torch.int64, device="cuda")
+    s1, s5 = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], ns, 1)
+    r1 = oracle.albedo((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], [1000, 0, 0, 3000], 1)
+    v = host(s1)
+    assert np.isnan(v[1]) and np.isnan(v[2]) and np.isnan(host(s5)[1])
+    assert abs(v[0] - r1[0]) <= ATOL_A and abs(v[3] - r1[3]) <= ATOL_A
+
+
+def test_lut_full_size_every_cell():
+    """64 x 64 cells x 2^20 samples (the table workload): S1 and S5 of every
+    cell against the oracle's values, and the one-pass value and Jacobian at
+    F0 = 0.04 (what the autograd Function and the benchmark's forward +
+    backward run) of every cell against the oracle's dual-number gradient."""
+    gold = golden("lut")
     g = workloads.lut_grid(64, 64)
     t = to_dev(g)
-    n = 1 << 20
+    n = int(gold["lut_n"])
     s1, s5 = cv.albedo_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2)
+    f0 = torch.full((4096,), float(gold["lut_f0"]), device="cuda")
+    a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2,
+                                             f0=f0)
     torch.cuda.synchronize()
     S1, S5 = host(s1), host(s5)
     assert np.all(S1 >= 0) and np.all(S1 <= 1.0 + 1e-6) and np.all(S5 >= 0) and np.all(S5 <= S1)
-    cells = np.unique(np.concatenate([np.linspace(0, 4095, 60).astype(np.int64),
-                                      [63, 64 * 31 + 7, 64 * 40 + 50, 4032]]))
-    sub = {k: v[cells] for k, v in g.items()}
-    a1, a5 = _oracle_sums(sub, n, 2, units=cells)
-    assert np.abs(S1[cells] - a1).max() <= ATOL_A
-    assert np.abs(S5[cells] - a5).max() <= ATOL_A
+    e1 = np.abs(S1 - gold["lut_s1"]).max()
+    e5 = np.abs(S5 - gold["lut_s5"]).max()
+    ea = np.abs(host(a) - gold["lut_value"]).max()
+    print(f"table, every cell: max |err| S1 {e1:.2e}, S5 {e5:.2e}, A(0.04) {ea:.2e}")
+    assert e1 <= ATOL_A and e5 <= ATOL_A and ea <= ATOL_A
+    _check_grad(host(gx), gold["lut_gax"], "table d/d alpha_x", gold["lut_band_ax"])
+    _check_grad(host(gy), gold["lut_gay"], "table d/d alpha_y", gold["lut_band_ay"])
+    _check_grad(host(gt), gold["lut_gth"], "table d/d theta_o", gold["lut_band_th"])
     # normal incidence row (mu = 1) at alpha = 1: 1 - ln 2 within MC error
     c = 64 * 63 + 63
     assert abs(S1[c] - (1 - np.log(2))) < 4 * 0.366 / np.sqrt(n)
@@ -90,9 +175,16 @@ def _grad_cells(n_side, seed=3):
     return {"wx": wx, "wy": wy, "wz": wz, "ax": gg["ax"], "ay": gg["ay"]}
 
 
-def _check_grad(got, ref, name):
+def _check_grad(got, ref, name, band=None):
+    """Within 1e-4 + 1e-3 |g| of the oracle's dual-number gradient, plus (for
+    the full-size workloads) the oracle's bound on what samples within FP32
+    rounding of the horizon can move (they may land on either side)."""
     diff = np.abs(got - ref)
     lim = 1e-4 + 1e-3 * np.abs(ref)
+    if band is not None:
+        lim = lim + band
+    print(f"{name}: worst {np.max(diff / lim):.3f} of the limit, "
+          f"{np.max(diff / (1e-4 + 1e-3 * np.abs(ref))):.3f} of the plain tolerance")
     assert np.all(diff <= lim), f"{name}: worst {np.max(diff / lim):.2f}x of the limit"
 
 
@@ -112,44 +204,25 @@ def test_backward_subgrid(n):
     _check_grad(host(gt), u * rt, "d/d theta_o")
 
 
-def test_backward_full_size_sampled():
-    """32 x 32 anisotropic cells x 2^18 samples; 32 cells vs the oracle."""
+def test_grad_grid_every_cell():
+    """32 x 32 anisotropic cells x 2^18 samples (the gradient workload): the
+    recompute-style backward and the one-pass value and Jacobian of every
+    cell against the oracle's dual-number gradient."""
+    gold = golden("grad")
     g = _grad_cells(32)
     t = to_dev(g)
-    n = 1 << 18
+    n = int(gold["grad_n"])
     gx, gy, gt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
+    a, vx, vy, vt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
     torch.cuda.synchronize()
-    assert torch.all(torch.isfinite(gx)) and torch.all(torch.isfinite(gy))
-    cells = np.unique(np.concatenate([np.linspace(0, 1023, 28).astype(np.int64),
-                                      [33, 517, 1000, 1022]]))
-    sub = {k: v[cells] for k, v in g.items()}
-    _, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
-                                       n, 3, units=cells)
-    _check_grad(host(gx)[cells], rx, "full d/d alpha_x")
-    _check_grad(host(gy)[cells], ry, "full d/d alpha_y")
-    _check_grad(host(gt)[cells], rt, "full d/d theta_o")
-
-
-def test_value_and_grad_full_size_sampled():
-    """The LUT workload (64 x 64 cells x 2^20 samples) through the one-pass
-    value and Jacobian that the autograd Function and the benchmark's
-    forward + backward run, with F0 = 0.04: 32 cells vs the oracle's value
-    and dual-number gradient."""
-    g = workloads.lut_grid(64, 64)
-    t = to_dev(g)
-    n = 1 << 20
-    f0 = torch.full((4096,), 0.04, device="cuda")
-    a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2,
-                                             f0=f0)
-    torch.cuda.synchronize()
-    cells = np.linspace(0, 4095, 32).astype(np.int64)
-    sub = {k: v[cells] for k, v in g.items()}
-    ra, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"],
-                                        sub["ay"], n, 2, f0=0.04, units=cells)
-    assert np.abs(host(a)[cells] - ra).max() <= ATOL_A
-    _check_grad(host(gx)[cells], rx, "LUT d/d alpha_x")
-    _check_grad(host(gy)[cells], ry, "LUT d/d alpha_y")
-    _check_grad(host(gt)[cells], rt, "LUT d/d theta_o")
+    assert np.abs(host(a) - gold["grad_value"]).max() <= ATOL_A
+    for (x, y), ref, band, name in zip(((gx, vx), (gy, vy), (gt, vt)),
+                                       (gold["grad_gax"], gold["grad_gay"], gold["grad_gth"]),
+                                       (gold["grad_band_ax"], gold["grad_band_ay"],
+                                        gold["grad_band_th"]),
+                                       ("alpha_x", "alpha_y", "theta_o")):
+        _check_grad(host(x), ref, f"grid backward d/d {name}", band)
+        _check_grad(host(y), ref, f"grid value_and_grad d/d {name}", band)
 
 
 @pytest.mark.parametrize("n", [1 << 12, 4097, 1])
@@ -178,24 +251,31 @@ def test_value_and_grad(n):
 
 
 def test_backward_vs_central_differences():
-    """The configuration's check against FP64 central differences with step
-    1e-4: the GPU gradient must sit as close to FD(1e-4) as the exact
-    (dual-number) gradient does, plus the parity tolerance.  (FD(1e-4) itself
-    is off by up to ~1e-3 where samples cross the horizon within the step.)"""
-    g = _grad_cells(32)
-    rng = np.random.default_rng(2)
-    cells = rng.choice(1024, 16, replace=False)
-    sub = {k: v[cells] for k, v in g.items()}
-    t = to_dev(sub)
-    n = 1 << 14
-    # the GPU entry point takes cells 0..15 as units 0..15, so compare on those units
-    gx, gy, gt = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
-    wo = (sub["wx"], sub["wy"], sub["wz"])
-    _, rx, ry, rt = oracle.albedo_grad(wo, sub["ax"], sub["ay"], n, 3)
-    fd = oracle.albedo_fd(wo, sub["ax"], sub["ay"], n, 3, step=1e-4)
-    for got, exact, f in zip((gx, gy, gt), (rx, ry, rt), fd):
-        gap = np.abs(exact - f)
-        assert np.all(np.abs(host(got) - f) <= gap + 1e-4 + 1e-3 * np.abs(exact))
+    """The gradient configuration's check: the GPU gradient on the 32 x 32
+    grid (2^12 samples per cell) against the oracle's FP64 central
+    differences with step 1e-4 on the same random numbers, within
+    1e-4 + 1e-3 |g| (the parity bound) + 1e-6 + 1e-5 |g| (the bound between
+    the exact derivative and FD(1e-4) that the oracle's pin establishes), on
+    the cells where the step resolves the derivative: no horizon kink within
+    the step and both roughness values at least 0.2 (the same selection as
+    the oracle's pin)."""
+    n = 1 << 12
+    gg = workloads.grad_grid(32, seed=3)
+    wx, wy, wz = workloads.view_from_angles(gg["theta"], gg["phi"])
+    g = {"wx": wx, "wy": wy, "wz": wz, "ax": gg["ax"], "ay": gg["ay"]}
+    wo = (wx, wy, wz)
+    kinks = oracle.albedo_kinks(wo, g["ax"], g["ay"], n, 3, step=1e-4)
+    smooth = np.minimum(g["ax"], g["ay"]) >= 0.2
+    t = to_dev(g)
+    got = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 3)
+    fd = oracle.albedo_fd(wo, g["ax"], g["ay"], n, 3, step=1e-4)
+    for name, x, f, k in zip(("alpha_x", "alpha_y", "theta_o"), got, fd, kinks):
+        m = (k == 0) & smooth
+        gpu = host(x)
+        lim = 1e-4 + 1e-3 * np.abs(f) + 1e-6 + 1e-5 * np.abs(f)
+        r = np.abs(gpu - f) / lim
+        print(f"GPU vs FD(1e-4) d/d {name}: {m.sum()} cells, worst {r[m].max():.3f} of the limit")
+        assert m.sum() >= 60 and np.all(r[m] <= 1.0)
 
 
 def test_autograd_function():
@@ -291,3 +371,25 @@ def test_estimator_determinism():
     d = cv.albedo_estimate_backward(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], 50000, 9)
     for x, y in zip(c, d):
         assert torch.equal(x, y)
+
+
+def test_estimator_microbench_runs():
+    """The register-resident estimator benchmark (the mix ceiling the table
+    kernels are measured against): every kind runs, gives finite per-lane
+    sums and the same bits twice; a ragged lane count leaves the words
+    beyond it untouched; bad arguments are refused."""
+    lobes = torch.tensor([[0.0, 0.0, 1.0, 4.0, 2.0], [0.6, 0.0, 0.8, 30.0, 5.0],
+                          [-0.5, 0.5, 0.70710678, 10.0, 1.5], [0.0, 0.0, 1.0, 0.0, 0.3]],
+                         dtype=torch.float32, device="cuda")
+    for kind in (0, 1, 2):
+        a = cv.estimator_microbench(kind, 1000, 16, 3, lobes)
+        b = cv.estimator_microbench(kind, 1000, 16, 3, lobes)
+        assert torch.equal(a, b)
+        assert np.all(np.isfinite(host(a).view(np.float32)))
+        out = torch.full((1024,), 7, dtype=torch.int32, device="cuda")
+        cv.estimator_microbench(kind, 1000, 16, 3, lobes, out=out)
+        assert torch.equal(out[:1000], a) and torch.all(out[1000:] == 7)
+    with pytest.raises(cv.CapvndfError):
+        cv.estimator_microbench(3, 10, 1, 3, lobes)
+    with pytest.raises(cv.CapvndfError):
+        cv.estimator_microbench(2, 10, 1, 3, None)

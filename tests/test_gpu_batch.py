@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import workloads
-from _gpu import host, to_dev
+from _gpu import golden, host, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -117,105 +117,39 @@ def test_dynamic_replays_are_bitwise_stable(tiling):
     plan.close()
 
 
-def test_full_batch_sampled():
-    """4096 uneven jobs (2^10 .. 2^22 samples); 72 jobs checked by the oracle."""
+def test_full_batch_every_job():
+    """4096 uneven jobs (2^10 .. 2^22 samples, the batch workload): value and
+    gradients of every job, from the graph replay and from the per-request
+    launches, against the oracle's dual-number gradient."""
+    gold = golden("batch")
     j = workloads.batch_jobs(4096, seed=4)
+    assert np.array_equal(j["n"], gold["batch_n"])
     t = to_dev({k: v for k, v in j.items() if k != "n"})
     plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True)
-    plan.run()
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(1)
-    small = np.flatnonzero(j["n"] <= (1 << 16))
-    large = np.flatnonzero(j["n"] >= (1 << 21))
-    mid = np.flatnonzero((j["n"] > (1 << 16)) & (j["n"] < (1 << 21)))
-    idx = np.concatenate([rng.choice(small, 48, replace=False), rng.choice(mid, 16, replace=False),
-                          rng.choice(large, 8, replace=False)])
-    sub = {k: v[idx] for k, v in j.items()}
-    A, rx, ry, rt = oracle.albedo_grad((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"],
-                                       sub["n"], 4, units=idx)
-    assert np.abs(host(plan.albedo)[idx] - A).max() <= 1e-4
-    for got, ref in ((plan.grad_ax, rx), (plan.grad_ay, ry), (plan.grad_theta_o, rt)):
-        d = np.abs(host(got)[idx] - ref)
-        assert np.all(d <= 1e-4 + 1e-3 * np.abs(ref))
-    assert torch.all(torch.isfinite(plan.grad_ax))
-
-
-def test_autotune_small(tmp_path, monkeypatch):
-    monkeypatch.setenv("CAPVNDF_TUNE_CACHE", str(tmp_path / "tune.txt"))
-    j = _jobs(32, seed=8, lo=8, hi=14)
-    t = to_dev({k: v for k, v in j.items() if k != "n"})
-    best, ms = cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
-    assert best[0] in (256, 512) and best[1] % 8 == 0 and best[3] in (0, 1) and ms > 0
-    assert best[4] in (0, 1)
-    text = (tmp_path / "tune.txt").read_text().split()
-    assert [int(x) for x in text[1:6]] == list(best)
-    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
-    assert plan.info()["tiling"] == best   # picked up from the cache
-    plan.run()
-    torch.cuda.synchronize()
-    _check(plan, j, 1.0, True)
-    plan.close()
-    # lines of another layout for the same problem are skipped, not misread:
-    # a six-field line (no dynamic field) whose time would parse as a valid
-    # dynamic flag, and a truncated line
-    sig = text[0]
-    other = (512, 16, 2, 1) if tuple(best[:4]) != (512, 16, 2, 1) else (256, 16, 2, 1)
-    with open(tmp_path / "tune.txt", "a") as f:
-        f.write(f"{sig} {other[0]} {other[1]} {other[2]} {other[3]} 1.250000\n")
-        f.write(f"{sig} {other[0]} {other[1]}\n")
-    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4)
-    assert plan.info()["tiling"] == best
-    plan.close()
-
-
-@pytest.mark.parametrize("tiling", [None, (256, 8, 4, 1), (512, 32, 8, 0, 1)])
-@pytest.mark.parametrize("n_samples", [1, 2, 1 << 20])
-def test_single_job(n_samples, tiling):
-    """A batch of one job: one sample, one pair, and a job large enough to be
-    split over many chunks and blocks."""
-    j = workloads.batch_jobs(1, seed=9)
-    j["n"][0] = n_samples
-    t = to_dev({k: v for k, v in j.items() if k != "n"})
-    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True,
-                        tiling=tiling)
-    plan.run()
-    torch.cuda.synchronize()
-    _check(plan, j, 1.0, True)
-    assert plan.info()["total_samples"] == n_samples
-    plan.close()
-
-
-def test_too_many_chunks_is_refused_before_building():
-    """2048 jobs of 2^40 - 1 samples in chunks of 512 pairs are 2^41 chunks:
-    refused with a message before any table is built (no host blow-up)."""
-    n = 2048
-    t = {k: torch.full((n,), v, device="cuda") for k, v in
-         (("wx", 0.0), ("wy", 0.0), ("wz", 1.0), ("ax", 0.5), ("ay", 0.5))}
-    with pytest.raises(cv.CapvndfError) as e:
-        cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
-                     np.full(n, (1 << 40) - 1, dtype=np.int64), 4, tiling=(256, 8, 2, 1, 0))
-    assert "exceed 2^31 - 2" in str(e.value)
-
-
-def test_autotune_refuses_when_no_tiling_fits():
-    n = 2048
-    t = {k: torch.full((n,), v, device="cuda") for k, v in
-         (("wx", 0.0), ("wy", 0.0), ("wz", 1.0), ("ax", 0.5), ("ay", 0.5))}
-    with pytest.raises(cv.CapvndfError) as e:
-        cv.albedo_batch_autotune(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
-                                 np.full(n, (1 << 40) - 1, dtype=np.int64), 4)
-    assert e.value.code == -2 and "exceed 2^31 - 2" in str(e.value)
-
-
-def test_per_request_path_refuses_a_job_beyond_one_launch():
-    """A job of 2^38 samples is 2^24 per-request chunks of 16384 samples,
-    one more than a launch of 256-lane blocks can count: refused before
-    anything is enqueued (the plan itself, with large chunks, is fine)."""
-    t = {k: torch.full((1,), v, device="cuda") for k, v in
-         (("wx", 0.0), ("wy", 0.0), ("wz", 1.0), ("ax", 0.5), ("ay", 0.5))}
-    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"],
-                        np.array([1 << 38], dtype=np.int64), 4, tiling=(512, 4096, 1, 0, 0))
-    with pytest.raises(cv.CapvndfError) as e:
-        plan.run_per_request()
-    assert e.value.code == -2 and "more than one launch" in str(e.value)
+    for mode in ("graph", "per-request"):
+        for o in (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o):
+            o.fill_(float("nan"))
+        plan.run() if mode == "graph" else plan.run_per_request()
+        torch.cuda.synchronize()
+        e = np.abs(host(plan.albedo) - gold["batch_value"]).max()
+        print(f"batch {mode}: max |err| value {e:.2e}")
+        assert e <= 1e-4
+        # tolerance plus the oracle's bound on what samples within FP32
+        # rounding of the horizon can move (they may land on either side)
+        for got, ref, band, name in ((plan.grad_ax, gold["batch_gax"], gold["batch_band_ax"],
+                                      "alpha_x"),
+                                     (plan.grad_ay, gold["batch_gay"], gold["batch_band_ay"],
+                                      "alpha_y"),
+                                     (plan.grad_theta_o, gold["batch_gth"], gold["batch_band_th"],
+                                      "theta_o")):
+            d = np.abs(host(got) - ref)
+            tol = 1e-4 + 1e-3 * np.abs(ref)
+            lim = tol + band
+            worst = int(np.argmax(d / lim))
+            over = np.flatnonzero(d > tol)
+            print(f"batch {mode} d/d {name}: worst {d[worst] / lim[worst]:.3f} of the limit "
+                  f"(job {worst}, {j['n'][worst]} samples); {len(over)} jobs past the plain "
+                  f"tolerance, all with horizon-band samples: "
+                  f"{bool(np.all(gold['batch_band_count'][over] > 0))}")
+            assert np.all(d <= lim), f"{mode} d/d {name}: job {worst} at {d[worst] / lim[worst]:.2f}x"
     plan.close()

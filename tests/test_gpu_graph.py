@@ -35,8 +35,8 @@ def test_hot_path_in_a_captured_graph():
     outs = tuple(torch.empty_like(t["wx"]) for _ in range(4))
     douts = tuple(torch.empty_like(t["wx"]) for _ in range(5))
     pouts = tuple(torch.empty_like(t["wx"]) for _ in range(4))  # pdf, u1, u2, dielectric pdf
-    ws = torch.empty(cv.albedo_workspace_size(64, n, 2) // 4 + 4, device="cuda")
-    wr = torch.empty(cv.albedo_workspace_size(64, n, 0) // 4 + 4, device="cuda")
+    ws = torch.empty(cv.albedo_workspace_size(64, [n] * 64, 1) // 4 + 4, device="cuda")
+    wr = torch.empty(cv.albedo_workspace_size(64, None, 0) // 4 + 4, device="cuda")
     vals = [torch.empty(64, device="cuda") for _ in range(5)]
     lobes = torch.tensor([[0.0, 0.0, 1.0, 4.0, 2.0], [0.6, 0.0, 0.8, 30.0, 5.0]],
                          dtype=torch.float32, device="cuda")
