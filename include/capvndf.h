@@ -66,13 +66,15 @@ extern "C" {
 #define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
 #define CAPVNDF_CAP_F64 2  /* spherical cap evaluated in double precision   */
 
-/* Version of this ABI (major * 10000 + minor * 100 + patch): 3.0.0.  Major 3
+/* Version of this ABI (major * 10000 + minor * 100 + patch): 3.1.0.  Minor 1
+ * of major 3 added a 32-byte horizon record per slot to the workspace of the
+ * gradient entry points (albedo_workspace_size covers it); major 3
  * gave the table estimators per-cell device sample counts and
  * albedo_workspace_size its (ncells, host counts, with_grad) form; major 2
  * added the `dynamic` field to capvndf_tiling (a layout change) and the
  * CAPVNDF_CAP_F64 method; minor 1 of major 2 added albedo_view_from_angles
  * and albedo_apply_jacobian. */
-#define CAPVNDF_VERSION 30000
+#define CAPVNDF_VERSION 30100
 int32_t capvndf_version(void);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -226,9 +228,11 @@ int32_t dielectric_pdf(int64_t n, const float* wix, const float* wiy, const floa
  *                 most slots a call of ncells cells uses.
  *   with_grad     0: enough for albedo_estimate, albedo_value_and_grad
  *                 without gradients and radiance_estimate; 1: enough for
- *                 every table estimator (two or four partial sums per slot).
- * Any workspace of at least ncells * 8 * (partial sums of the call) bytes
- * works; a larger one (up to this size) lets the call use more slots.
+ *                 every table estimator (two or four partial sums per slot,
+ *                 and with gradients a 32-byte horizon record per slot).
+ * Any workspace of at least ncells * (8 * partial sums of the call, + 32 with
+ * gradients) bytes works; a larger one (up to this size) lets the call use
+ * more slots.
  * Returns 0 for ncells <= 0, ncells >= 2^24, with_grad not 0 or 1, or a host
  * count outside [0, 2^40).
  */
@@ -280,7 +284,11 @@ int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy, cons
  *                    (dwo/dtheta = (cos t cos p, cos t sin p, -sin t); at the
  *                    pole the azimuth is taken as 0)
  *   workspace        albedo_workspace_size(ncells, counts, 1) bytes (at
- *                    least ncells * 24)
+ *                    least ncells * 56)
+ * The samples whose FP32 reflection lies within rounding of the horizon,
+ * where the weight's slope jumps, or whose conditioning is too poor for FP32
+ * (a few in 10^5) are evaluated again in double precision by a second kernel
+ * on the same stream, which replaces their FP32 terms.
  * Errors: as albedo_estimate.
  */
 int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* woy,
@@ -304,7 +312,9 @@ int32_t albedo_estimate_backward(int64_t ncells, const float* wox, const float* 
  *   albedo      [ncells] out: A(F0)
  *   grad_ax, grad_ay, grad_theta_o [ncells] out, all NULL for values only
  *   workspace   albedo_workspace_size(ncells, counts, 1) bytes (at least
- *               ncells * 32 with gradients, ncells * 8 without)
+ *               ncells * 64 with gradients, ncells * 8 without)
+ * With gradients, near-horizon samples are evaluated again in double
+ * precision as in albedo_estimate_backward.
  * Errors: as albedo_estimate; NULL_PTR if only some gradient outputs are given.
  */
 int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy,

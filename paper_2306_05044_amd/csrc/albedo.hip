@@ -124,51 +124,51 @@ __device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uin
     }
 }
 
-// Replaces the FP32 terms of the samples albedo_adj flagged (reflection
-// within FP32 rounding of the horizon, or ill-conditioned) by their double
-// precision evaluation: acc += t64 - t32 for each such sample of this
-// lane's pairs.  With one flagged pair (the usual case) only that pair is
-// evaluated again; with more, the lane walks its pairs once more.
-template <int STRIDE>
-__device__ __attribute__((noinline)) void fix_flagged(
-    const CellConst& c, float f0, uint64_t pbeg, uint64_t pend, uint64_t nsamples, uint32_t unit,
-    uint32_t k0, uint32_t k1, uint32_t lane, uint32_t nflag, uint32_t pflag, Comp* acc) {
-    auto fix_pair = [&](uint64_t p) {
-        const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
-        const float u[4] = {unit24(w.w0), unit24(w.w1), unit24(w.w2), unit24(w.w3)};
-        for (int h = 0; h < 2; ++h) {
-            if (2 * p + h >= nsamples) break;
-            const AdjTerm a = albedo_adj(c, f0, u[2 * h], u[2 * h + 1]);
-            if (!a.amb) continue;
-            const AdjTerm d = albedo_adj_f64(c, f0, u[2 * h], u[2 * h + 1]);
-            comp_add(acc[0], d.w - a.w);
-            comp_add(acc[1], d.dax - a.dax);
-            comp_add(acc[2], d.day - a.day);
-            comp_add(acc[3], d.dth - a.dth);
-            comp_add(acc[4], d.dwsx - a.dwsx);
-            comp_add(acc[5], d.dwsy - a.dwsy);
-            comp_add(acc[6], d.dzs - a.dzs);
-        }
-    };
-    if (nflag == 1) {
-        fix_pair(pbeg + pflag);
-    } else {
-        for (uint64_t p = pbeg + lane; p < pend; p += STRIDE) fix_pair(p);
-    }
+// ---------------------------------------------------------------------------
+// Horizon records.  albedo_adj flags, with a margin >= 0, the samples whose
+// FP32 reflection lies within rounding of the horizon or whose conditioning
+// is too poor for FP32 (a few in 10^5).  The adjoint loops keep per lane the
+// largest margin of its samples; the owner of each partial (a table slot's
+// block, a batch chunk's block or wavefront) then stores one 64-bit mask of
+// its flagged lanes per wavefront, its record.  k_horizon_fix walks the
+// pairs of the flagged lanes again, evaluates their flagged samples in
+// double precision and adds t64 - t32 to the owner's partial in a fixed
+// order.  The sample loops so carry one float and hold no call: a call
+// there, even one never taken, made them 1.4x to 2.9x slower on gfx950.
+// ---------------------------------------------------------------------------
+
+// Bytes of the records of nowners owners of nwords wavefronts.
+__host__ __device__ inline size_t rec_bytes(int64_t nowners, int nwords) {
+    return (size_t)nowners * (size_t)nwords * sizeof(uint64_t);
 }
 
-// Adjoint loop: accumulates w, the direct derivatives and the adjoint of ws,
-// then chains ws into (alpha_x, alpha_y, theta_o).  out = {w, gax, gay, gth}.
+// Record of a block owner: rec[w] = flags of wavefront w.
+__device__ __forceinline__ void store_flags_block(float margin, uint64_t* __restrict__ rec) {
+    const uint64_t m = __ballot(margin >= 0.0f);
+    if ((threadIdx.x & 63) == 0) rec[threadIdx.x >> 6] = m;
+}
+
+// Record of a wavefront owner.  Must be reached by all 64 lanes.
+__device__ __forceinline__ void store_flags_wave(float margin, uint32_t lane,
+                                                 uint64_t* __restrict__ rec) {
+    const uint64_t m = __ballot(margin >= 0.0f);
+    if (lane == 0) rec[0] = m;
+}
+
+// Adjoint loop: sums w and the derivatives over the lane's pairs.  Each
+// group of kGroup pairs sums the direct derivatives and the adjoint of ws
+// plainly, chains the ws adjoint into (alpha_x, alpha_y, theta_o) (ws_chain
+// is linear, and its constants are the cell's) and folds the four results
+// into compensated sums: out = {w, gax, gay, gth}.  margin is raised to the
+// largest margin of the lane's samples (horizon records).
 template <int STRIDE>
 __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t pbeg,
                                           uint64_t pend, uint64_t nsamples, uint32_t unit,
-                                          uint32_t k0, uint32_t k1, Comp (&out)[4],
+                                          uint32_t k0, uint32_t k1, Comp (&out)[4], float& margin,
                                           uint32_t lane = threadIdx.x) {
-    Comp acc[7];
+    Comp acc[4];
 #pragma unroll
-    for (int a = 0; a < 7; ++a) acc[a] = Comp{0.0f, 0.0f};
-    uint32_t nflag = 0;   // pairs with a flagged sample
-    uint32_t pflag = 0;   // the last of them, relative to pbeg (a chunk has < 2^32 pairs)
+    for (int a = 0; a < 4; ++a) acc[a] = Comp{0.0f, 0.0f};
     for (uint64_t p0 = pbeg + lane; p0 < pend; p0 += (uint64_t)STRIDE * kGroup) {
         float part[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll CAPVNDF_ADJ_UNROLL
@@ -179,30 +179,22 @@ __device__ __forceinline__ void pairs_adj(const CellConst& c, float f0, uint64_t
                 const AdjTerm t0 = albedo_adj(c, f0, unit24(w.w0), unit24(w.w1));
                 part[0] += t0.w; part[1] += t0.dax; part[2] += t0.day; part[3] += t0.dth;
                 part[4] += t0.dwsx; part[5] += t0.dwsy; part[6] += t0.dzs;
-                bool flag = t0.amb;
+                float f = t0.margin;
                 if (2 * p + 1 < nsamples) {
                     const AdjTerm t1 = albedo_adj(c, f0, unit24(w.w2), unit24(w.w3));
                     part[0] += t1.w; part[1] += t1.dax; part[2] += t1.day; part[3] += t1.dth;
                     part[4] += t1.dwsx; part[5] += t1.dwsy; part[6] += t1.dzs;
-                    flag = flag || t1.amb;
+                    f = fmaxf(f, t1.margin);
                 }
-                nflag += flag ? 1u : 0u;
-                pflag = flag ? (uint32_t)(p - pbeg) : pflag;
+                margin = fmaxf(margin, f);
             }
         }
+        ws_chain(c, part[4], part[5], part[6], part[1], part[2], part[3]);
 #pragma unroll
-        for (int a = 0; a < 7; ++a) comp_add(acc[a], part[a]);
+        for (int a = 0; a < 4; ++a) comp_add(acc[a], part[a]);
     }
-    if (nflag != 0)
-        fix_flagged<STRIDE>(c, f0, pbeg, pend, nsamples, unit, k0, k1, lane, nflag, pflag, acc);
-    float gax = acc[1].s + acc[1].c;
-    float gay = acc[2].s + acc[2].c;
-    float gth = acc[3].s + acc[3].c;
-    ws_chain(c, acc[4].s + acc[4].c, acc[5].s + acc[5].c, acc[6].s + acc[6].c, gax, gay, gth);
-    out[0] = acc[0];
-    out[1] = Comp{gax, 0.0f};
-    out[2] = Comp{gay, 0.0f};
-    out[3] = Comp{gth, 0.0f};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) out[a] = acc[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -280,19 +272,21 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
 
 // Adjoint of A(F0); WITH_VALUE also reduces the value itself (4 sums: A,
 // dA/d alpha_x, dA/d alpha_y, dA/d theta_o), otherwise the 3 gradient sums.
+// Block b also writes its horizon record at rec[4 b .. 4 b + 4).
 #define CAPVNDF_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(CAPVNDF_ADJ_WAVES)))
 template <bool WITH_VALUE>
 __global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
     const int64_t* __restrict__ nsamp, int32_t slots, uint32_t unit_base, uint32_t k0,
-    uint32_t k1, float* __restrict__ partial) {
+    uint32_t k1, float* __restrict__ partial, uint64_t* __restrict__ rec) {
     const SlotWork sw = slot_work(nsamp, slots);
     if (sw.slot >= sw.nchunks) return;
     const int64_t cell = sw.cell;
     const CellConst c = cell_setup(wox[cell], woy[cell], woz[cell], ax[cell], ay[cell]);
     const float f0 = f0p ? f0p[cell] : 1.0f;
     Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
+    float margin = -1.0f;
     const uint64_t npairs = (sw.n + 1) / 2;
     if (c.ok) {
         // one sweep per chunk of the slot; the pathwise sums of successive
@@ -302,7 +296,7 @@ __global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
             const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
             Comp part[4];
             pairs_adj<kLutBlock>(c, f0, pbeg, pend, sw.n, unit_base + (uint32_t)cell, k0, k1,
-                                 part);
+                                 part, margin);
 #pragma unroll
             for (int a = 0; a < 4; ++a) out[a] = comp_merge(out[a], part[a]);
         }
@@ -314,6 +308,7 @@ __global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
         Comp g[3] = {out[1], out[2], out[3]};
         block_reduce_store<3, kLutBlock>(g, dst);
     }
+    store_flags_block(margin, rec + (int64_t)blockIdx.x * (kLutBlock / 64));
 }
 
 // Direct illumination: one sum of F G2/G1 L(wl) per cell, NL lobes.
@@ -370,7 +365,7 @@ __device__ __forceinline__ void batch_chunk_block(
     const float* __restrict__ f0p, const int64_t* __restrict__ nsamp,
     const int32_t* __restrict__ chunk_job, const int64_t* __restrict__ chunk_pbeg,
     const int64_t* __restrict__ chunk_pend, uint32_t k0, uint32_t k1,
-    float* __restrict__ partial) {
+    float* __restrict__ partial, uint64_t* __restrict__ rec) {
     const int32_t j = chunk_job[ch];
     const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
     const float f0 = f0p ? f0p[j] : 1.0f;
@@ -379,8 +374,10 @@ __device__ __forceinline__ void batch_chunk_block(
     const uint64_t pend = (uint64_t)chunk_pend[ch];
     if (GRAD) {
         Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-        if (c.ok) pairs_adj<BLOCK>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out);
+        float margin = -1.0f;
+        if (c.ok) pairs_adj<BLOCK>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out, margin);
         block_reduce_store<4, BLOCK>(out, partial + (int64_t)ch * 8);
+        store_flags_block(margin, rec + (int64_t)ch * (BLOCK / 64));
     } else {
         Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
         if (c.ok) pairs_fwd<BLOCK>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc);
@@ -398,7 +395,7 @@ __device__ __forceinline__ void batch_chunk_wave(
     const float* __restrict__ f0p, const int64_t* __restrict__ nsamp,
     const int32_t* __restrict__ chunk_job, const int64_t* __restrict__ chunk_pbeg,
     const int64_t* __restrict__ chunk_pend, uint32_t k0, uint32_t k1,
-    float* __restrict__ partial) {
+    float* __restrict__ partial, uint64_t* __restrict__ rec) {
     const int32_t j = chunk_job[ch];
     const CellConst c = cell_setup(wox[j], woy[j], woz[j], ax[j], ay[j]);
     const float f0 = f0p ? f0p[j] : 1.0f;
@@ -407,7 +404,8 @@ __device__ __forceinline__ void batch_chunk_wave(
     const uint64_t pend = (uint64_t)chunk_pend[ch];
     if (GRAD) {
         Comp out[4] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
-        if (c.ok) pairs_adj<64>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out, lane);
+        float margin = -1.0f;
+        if (c.ok) pairs_adj<64>(c, f0, pbeg, pend, n, (uint32_t)j, k0, k1, out, margin, lane);
 #pragma unroll
         for (int a = 0; a < 4; ++a) out[a] = wave_reduce(out[a]);
         if (lane == 0) {
@@ -417,6 +415,7 @@ __device__ __forceinline__ void batch_chunk_wave(
                 partial[(int64_t)ch * 8 + 2 * a + 1] = out[a].c;
             }
         }
+        store_flags_wave(margin, lane, rec + ch);
     } else {
         Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
         if (c.ok) pairs_fwd<64>(c, pbeg, pend, n, (uint32_t)j, k0, k1, acc, lane);
@@ -436,9 +435,9 @@ __device__ __forceinline__ void batch_chunk_wave(
         const int32_t *__restrict__ chunk_job, const int64_t *__restrict__ chunk_pbeg,           \
         const int64_t *__restrict__ chunk_pend, const int32_t *__restrict__ owner_chunks,        \
         int32_t *__restrict__ counter, int32_t nchunks, uint32_t k0, uint32_t k1,              \
-        float *__restrict__ partial
+        float *__restrict__ partial, uint64_t *__restrict__ rec
 #define CAPVNDF_CHUNK_ARGS wox, woy, woz, ax, ay, f0p, nsamp, chunk_job, chunk_pbeg, chunk_pend, \
-                           k0, k1, partial
+                           k0, k1, partial, rec
 
 // A block owns a chunk (block-wide reduction through LDS).
 template <int BLOCK, bool GRAD, bool DYN>
@@ -504,6 +503,184 @@ __global__ void k_reset_counter(int32_t* counter) {
 }
 
 // ---------------------------------------------------------------------------
+// Horizon fix pass: runs between an adjoint kernel and the finishing pass.
+// Owners have `threads` threads (64, 256 or 512) and records of threads / 64
+// words.  Owner o is table block o (cell o / slots, slot o % slots, the
+// cell's chunks slot, slot + slots, ...; unit unit_base + cell) when TABLE,
+// else batch chunk o (job chunk_job[o], pairs [chunk_pbeg[o],
+// chunk_pend[o]); unit = job).  Owner thread t took the pairs
+// pbeg + t + s * threads of each of its ranges.  For each flagged sample of
+// a flagged thread's pairs the pass adds t64 - t32 (albedo_adj_f64 minus
+// albedo_adj) to compensated sums, chains the ws adjoint as the sample loops
+// do, reduces in a fixed tree and merges the result into the owner's
+// partial: (A, gax, gay, gth) at partial[8 o ..] if WITH_VALUE, the three
+// gradient sums at partial[6 o ..] otherwise.
+//
+// Wavefront o serves owner o: it returns at once if no thread was flagged
+// (most owners), else spreads each flagged thread's pairs over its 64 lanes.
+// ---------------------------------------------------------------------------
+constexpr int kFixBlock = 256;
+
+// The owner's cell or job and its pair ranges.
+struct Owner {
+    int64_t u;            // cell or job index
+    uint32_t unit;        // Philox unit
+    int64_t slot, nch;    // TABLE: the slot and the cell's chunk count
+    uint64_t pbeg, pend;  // batch: the chunk's pairs
+    bool live;            // false for a table slot past the cell's chunks (no record)
+};
+
+template <bool TABLE>
+__device__ __forceinline__ Owner owner_of(int64_t o, const int64_t* __restrict__ nsamp,
+                                          int32_t slots, uint32_t unit_base,
+                                          const int32_t* __restrict__ chunk_job,
+                                          const int64_t* __restrict__ chunk_pbeg,
+                                          const int64_t* __restrict__ chunk_pend) {
+    Owner w;
+    w.slot = 0;
+    w.nch = 1;
+    w.pbeg = 0;
+    w.pend = 0;
+    if (TABLE) {
+        w.u = o / slots;
+        w.slot = o - w.u * slots;
+        w.nch = cell_chunks(nsamp[w.u]);
+        w.live = w.slot < w.nch;
+        w.unit = unit_base + (uint32_t)w.u;
+    } else {
+        w.u = chunk_job[o];
+        w.pbeg = (uint64_t)chunk_pbeg[o];
+        w.pend = (uint64_t)chunk_pend[o];
+        w.live = true;
+        w.unit = (uint32_t)w.u;
+    }
+    return w;
+}
+
+// t64 - t32 of the flagged samples of pair p, added to corr.
+__device__ __forceinline__ void fix_pair(const CellConst& c, float f0, uint64_t n, uint32_t unit,
+                                         uint32_t k0, uint32_t k1, uint64_t p, Comp (&corr)[7]) {
+    const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
+    const float uu[4] = {unit24(w.w0), unit24(w.w1), unit24(w.w2), unit24(w.w3)};
+    for (int h = 0; h < 2; ++h) {
+        if (2 * p + h >= n) break;
+        const AdjTerm t = albedo_adj(c, f0, uu[2 * h], uu[2 * h + 1]);
+        if (!(t.margin >= 0.0f)) continue;
+        const AdjTerm d = albedo_adj_f64(c, f0, uu[2 * h], uu[2 * h + 1]);
+        comp_add(corr[0], d.w - t.w);
+        comp_add(corr[1], d.dax - t.dax);
+        comp_add(corr[2], d.day - t.day);
+        comp_add(corr[3], d.dth - t.dth);
+        comp_add(corr[4], d.dwsx - t.dwsx);
+        comp_add(corr[5], d.dwsy - t.dwsy);
+        comp_add(corr[6], d.dzs - t.dzs);
+    }
+}
+
+// The 7 correction sums of one thread as (A, gax, gay, gth), ws chained.
+__device__ __forceinline__ void chain_fix(const CellConst& c, const Comp (&corr)[7],
+                                          Comp (&out)[4]) {
+    float gax = corr[1].s + corr[1].c;
+    float gay = corr[2].s + corr[2].c;
+    float gth = corr[3].s + corr[3].c;
+    if (c.ok)
+        ws_chain(c, corr[4].s + corr[4].c, corr[5].s + corr[5].c, corr[6].s + corr[6].c, gax,
+                 gay, gth);
+    out[0] = corr[0];
+    out[1] = Comp{gax, 0.0f};
+    out[2] = Comp{gay, 0.0f};
+    out[3] = Comp{gth, 0.0f};
+}
+
+template <bool WITH_VALUE>
+__device__ __forceinline__ void merge_fix(const Comp (&fix)[4], float* __restrict__ partial,
+                                          int64_t o) {
+    constexpr int A0 = WITH_VALUE ? 0 : 1;
+    float* dst = partial + o * (WITH_VALUE ? 8 : 6);
+#pragma unroll
+    for (int a = A0; a < 4; ++a) {
+        const Comp r = comp_merge(Comp{dst[2 * (a - A0)], dst[2 * (a - A0) + 1]}, fix[a]);
+        dst[2 * (a - A0)] = r.s;
+        dst[2 * (a - A0) + 1] = r.c;
+    }
+}
+
+#define CAPVNDF_FIX_PARAMS                                                                     \
+    int64_t nowners, int32_t threads, const float *__restrict__ wox,                           \
+        const float *__restrict__ woy, const float *__restrict__ woz,                          \
+        const float *__restrict__ ax, const float *__restrict__ ay,                            \
+        const float *__restrict__ f0p, const int64_t *__restrict__ nsamp, int32_t slots,      \
+        uint32_t unit_base, const int32_t *__restrict__ chunk_job,                             \
+        const int64_t *__restrict__ chunk_pbeg, const int64_t *__restrict__ chunk_pend,        \
+        uint32_t k0, uint32_t k1, uint64_t *__restrict__ rec, float *__restrict__ partial
+
+template <bool TABLE, bool WITH_VALUE>
+__global__ __launch_bounds__(kFixBlock) void k_horizon_fix(CAPVNDF_FIX_PARAMS) {
+    const uint32_t lane = threadIdx.x & 63;
+    const int64_t o = (int64_t)blockIdx.x * (kFixBlock / 64) +
+                      __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t nwords = threads >> 6;
+    if (o >= nowners) return;  // the same for the whole wavefront
+    const Owner w = owner_of<TABLE>(o, nsamp, slots, unit_base, chunk_job, chunk_pbeg, chunk_pend);
+    if (!w.live) return;
+    int32_t flagged = 0;
+    for (int32_t k = 0; k < nwords; ++k) flagged += __popcll(rec[o * nwords + k]);
+    if (flagged == 0) return;
+    const int64_t u = w.u;
+    const CellConst c = cell_setup(wox[u], woy[u], woz[u], ax[u], ay[u]);
+    const float f0 = f0p ? f0p[u] : 1.0f;
+    const uint64_t n = (uint64_t)nsamp[u];
+    Comp corr[7];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) corr[a] = Comp{0.0f, 0.0f};
+    const uint64_t step = (uint64_t)threads * 64;
+    for (int32_t k = 0; k < nwords; ++k) {
+        uint64_t m = rec[o * nwords + k];
+        while (m != 0) {
+            const uint64_t t = (uint64_t)k * 64 + __builtin_ctzll(m);
+            m &= m - 1;
+            if (!c.ok) continue;
+            if (TABLE) {
+                const uint64_t npairs = (n + 1) / 2;
+                for (int64_t ch = w.slot; ch < w.nch; ch += slots) {
+                    const uint64_t b = (uint64_t)ch * kLutChunkPairs;
+                    const uint64_t e = std::min(b + kLutChunkPairs, npairs);
+                    for (uint64_t p = b + t + (uint64_t)lane * threads; p < e; p += step)
+                        fix_pair(c, f0, n, w.unit, k0, k1, p, corr);
+                }
+            } else {
+                for (uint64_t p = w.pbeg + t + (uint64_t)lane * threads; p < w.pend; p += step)
+                    fix_pair(c, f0, n, w.unit, k0, k1, p, corr);
+            }
+        }
+    }
+    Comp fix[4];
+    chain_fix(c, corr, fix);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fix[a] = wave_reduce(fix[a]);
+    if (lane == 0) merge_fix<WITH_VALUE>(fix, partial, o);
+}
+
+#undef CAPVNDF_FIX_PARAMS
+
+inline unsigned fix_grid(int64_t nowners) {
+    constexpr int64_t per_block = kFixBlock / 64;
+    return (unsigned)((nowners + per_block - 1) / per_block);
+}
+
+// The fix pass over nowners owners of `threads` threads.
+template <bool TABLE, bool WITH_VALUE>
+void launch_fix(int64_t nowners, int32_t threads, const float* wox, const float* woy,
+                const float* woz, const float* ax, const float* ay, const float* f0,
+                const int64_t* nsamp, int32_t slots, uint32_t unit_base, const int32_t* chunk_job,
+                const int64_t* chunk_pbeg, const int64_t* chunk_pend, uint32_t k0, uint32_t k1,
+                uint64_t* rec, float* part, hipStream_t st) {
+    hipLaunchKernelGGL((k_horizon_fix<TABLE, WITH_VALUE>), dim3(fix_grid(nowners)),
+                       dim3(kFixBlock), 0, st, nowners, threads, wox, woy, woz, ax, ay, f0, nsamp,
+                       slots, unit_base, chunk_job, chunk_pbeg, chunk_pend, k0, k1, rec, part);
+}
+
+// ---------------------------------------------------------------------------
 // Finishing pass: unit u merges its partials in order, divides by its sample
 // count and applies an optional per-unit scale.  Partials of unit u: the
 // first min(slots, chunks) of [u * slots, (u + 1) * slots) if unit_chunks is
@@ -559,13 +736,34 @@ int64_t target_slots(int64_t ncells) {
     return std::max<int64_t>(1, std::min<int64_t>(s, kMaxBlocks / ncells));
 }
 
-size_t slot_bytes(int nacc) { return (size_t)nacc * 2 * sizeof(float); }
+// Workspace of a table launch: the partials (slot-major, as k_finish reads
+// them), then for the adjoint kernels the horizon records.
+size_t table_bytes(int64_t ncells, int64_t slots, int nacc, bool records) {
+    const int64_t nowners = ncells * slots;
+    return (size_t)nowners * nacc * 2 * sizeof(float) +
+           (records ? rec_bytes(nowners, kLutBlock / 64) : 0);
+}
+
+uint64_t* records_after(float* part, int64_t ncells, int32_t slots, int nacc) {
+    return reinterpret_cast<uint64_t*>(part + (size_t)ncells * (size_t)slots * (size_t)(2 * nacc));
+}
+
+// The fix pass over a table launch of ncells cells and `slots` slots.
+template <bool WITH_VALUE>
+void launch_table_fix(int64_t ncells, int32_t slots, const float* wox, const float* woy,
+                      const float* woz, const float* ax, const float* ay, const float* f0,
+                      const int64_t* nsamples, uint32_t unit_base, uint32_t k0, uint32_t k1,
+                      uint64_t* rec, float* part, hipStream_t st) {
+    launch_fix<true, WITH_VALUE>(ncells * slots, kLutBlock, wox, woy, woz, ax, ay, f0, nsamples,
+                                 slots, unit_base, nullptr, nullptr, nullptr, k0, k1, rec, part, st);
+}
 
 // Argument checks of the table estimators and the slot count the workspace
 // allows: min(target_slots(ncells), workspace_bytes / (ncells * slot bytes)).
 int32_t prepare_cells(const char* fn, int64_t ncells, const float* wox, const float* woy,
                       const float* woz, const float* ax, const float* ay, const int64_t* nsamples,
-                      int nacc, const void* workspace, size_t workspace_bytes, int32_t* slots) {
+                      int nacc, bool records, const void* workspace, size_t workspace_bytes,
+                      int32_t* slots) {
     *slots = 0;
     if (ncells < 0) return fail(CAPVNDF_ERR_BAD_SIZE, "%s: ncells < 0", fn);
     if (ncells > kMaxBlocks)
@@ -579,13 +777,17 @@ int32_t prepare_cells(const char* fn, int64_t ncells, const float* wox, const fl
     if (nsamples == nullptr) return fail(CAPVNDF_ERR_NULL_PTR, "%s: nsamples is NULL", fn);
     if (!aligned_to(nsamples, 8))
         return fail(CAPVNDF_ERR_MISALIGNED, "%s: nsamples must be 8-byte aligned", fn);
-    const size_t per_cell = (size_t)ncells * slot_bytes(nacc);
-    if (workspace == nullptr || workspace_bytes < per_cell)
+    const size_t least = table_bytes(ncells, 1, nacc, records);
+    if (workspace == nullptr || workspace_bytes < least)
         return fail(CAPVNDF_ERR_WORKSPACE, "%s: workspace of at least %zu bytes needed, %zu given",
-                    fn, per_cell, workspace == nullptr ? (size_t)0 : workspace_bytes);
+                    fn, least, workspace == nullptr ? (size_t)0 : workspace_bytes);
     if (!aligned_to(workspace, 16))
         return fail(CAPVNDF_ERR_MISALIGNED, "%s: workspace must be 16-byte aligned", fn);
-    *slots = (int32_t)std::min<int64_t>(target_slots(ncells), (int64_t)(workspace_bytes / per_cell));
+    // table_bytes is affine in the slot count: fixed + slots * per_slot
+    const size_t fixed = table_bytes(ncells, 0, nacc, records);
+    const size_t per_slot = least - fixed;
+    *slots = (int32_t)std::min<int64_t>(target_slots(ncells),
+                                        (int64_t)((workspace_bytes - fixed) / per_slot));
     return CAPVNDF_OK;
 }
 
@@ -607,7 +809,7 @@ extern "C" size_t albedo_workspace_size(int64_t ncells, const int64_t* nsamples_
         }
         slots = std::min(slots, std::max<int64_t>(1, most));
     }
-    return (size_t)ncells * (size_t)slots * slot_bytes(with_grad ? 4 : 2);
+    return with_grad ? table_bytes(ncells, slots, 4, true) : table_bytes(ncells, slots, 2, false);
 }
 
 extern "C" int32_t albedo_estimate(int64_t ncells, const float* wox, const float* woy,
@@ -617,7 +819,7 @@ extern "C" int32_t albedo_estimate(int64_t ncells, const float* wox, const float
                                    void* stream) {
     int32_t slots = 0;
     if (int32_t rc = prepare_cells("albedo_estimate", ncells, wox, woy, woz, ax, ay, nsamples, 2,
-                                   workspace, workspace_bytes, &slots))
+                                   false, workspace, workspace_bytes, &slots))
         return rc;
     if (ncells == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(s_f1, "s_f1")) return rc;
@@ -642,7 +844,7 @@ extern "C" int32_t albedo_estimate_backward(int64_t ncells, const float* wox, co
                                             void* stream) {
     int32_t slots = 0;
     if (int32_t rc = prepare_cells("albedo_estimate_backward", ncells, wox, woy, woz, ax, ay,
-                                   nsamples, 3, workspace, workspace_bytes, &slots))
+                                   nsamples, 3, true, workspace, workspace_bytes, &slots))
         return rc;
     if (ncells == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(grad_ax, "grad_ax")) return rc;
@@ -654,10 +856,14 @@ extern "C" int32_t albedo_estimate_backward(int64_t ncells, const float* wox, co
         if (int32_t rc = check_array(grad_albedo, "grad_albedo")) return rc;
     const hipStream_t st = as_stream(stream);
     float* part = static_cast<float*>(workspace);
+    uint64_t* rec = records_after(part, ncells, slots, 3);
     hipLaunchKernelGGL(k_albedo_adj<false>, dim3((unsigned)(ncells * slots)), dim3(kLutBlock), 0,
                        st, wox, woy, woz, ax, ay, f0, nsamples, slots, 0u, key_lo(seed),
-                       key_hi(seed), part);
+                       key_hi(seed), part, rec);
     if (int32_t rc = check_launch("albedo_estimate_backward launch")) return rc;
+    launch_table_fix<false>(ncells, slots, wox, woy, woz, ax, ay, f0, nsamples, 0u, key_lo(seed),
+                            key_hi(seed), rec, part, st);
+    if (int32_t rc = check_launch("albedo_estimate_backward fix launch")) return rc;
     hipLaunchKernelGGL(k_finish<3>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
                        part, slots, nullptr, nsamples, grad_albedo, grad_ax, grad_ay, grad_theta_o,
                        nullptr);
@@ -677,9 +883,13 @@ int32_t enqueue_value_and_grad(int64_t ncells, const float* wox, const float* wo
                                bool grad, float* part, int32_t slots, hipStream_t st) {
     const dim3 grid((unsigned)(ncells * slots)), block(kLutBlock);
     if (grad) {
+        uint64_t* rec = records_after(part, ncells, slots, 4);
         hipLaunchKernelGGL(k_albedo_adj<true>, grid, block, 0, st, wox, woy, woz, ax, ay, f0,
-                           nsamples, slots, 0u, key_lo(seed), key_hi(seed), part);
+                           nsamples, slots, 0u, key_lo(seed), key_hi(seed), part, rec);
         if (int32_t rc = check_launch("albedo_value_and_grad launch")) return rc;
+        launch_table_fix<true>(ncells, slots, wox, woy, woz, ax, ay, f0, nsamples, 0u,
+                               key_lo(seed), key_hi(seed), rec, part, st);
+        if (int32_t rc = check_launch("albedo_value_and_grad fix launch")) return rc;
         hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(ncells)), dim3(kFinishBlock), 0, st, ncells,
                            part, slots, nullptr, nsamples, nullptr, albedo, grad_ax, grad_ay,
                            grad_theta_o);
@@ -731,7 +941,7 @@ extern "C" int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const
             return rc;
     int32_t slots = 0;
     if (int32_t rc = prepare_cells(fn, ncells, wox, woy, woz, ax, ay, nsamples, grad ? 4 : 1,
-                                   workspace, workspace_bytes, &slots))
+                                   grad, workspace, workspace_bytes, &slots))
         return rc;
     if (ncells == 0) return CAPVNDF_OK;
     return enqueue_value_and_grad(ncells, wox, woy, woz, ax, ay, nsamples, seed, f0, albedo,
@@ -748,7 +958,7 @@ extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const flo
         return fail(CAPVNDF_ERR_BAD_SIZE, "radiance_estimate: nlobes must be in [0, %d]", kMaxLobes);
     int32_t slots = 0;
     if (int32_t rc = prepare_cells("radiance_estimate", ncells, wox, woy, woz, ax, ay, nsamples, 1,
-                                   workspace, workspace_bytes, &slots))
+                                   false, workspace, workspace_bytes, &slots))
         return rc;
     if (ncells == 0) return CAPVNDF_OK;
     if (int32_t rc = check_array(radiance, "radiance")) return rc;
@@ -813,6 +1023,7 @@ __device__ __forceinline__ float microbench_lane(int64_t t, int32_t pairs, uint3
     const float ay = __builtin_amdgcn_exp2f(-6.643856189774724f * unit24(w.w3));
     const CellConst c = cell_setup(sz * cp, sz * sp, mu, ax, ay);
     float acc[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float mf = -1.0f;
     for (int32_t p = 0; p < pairs; ++p) {
         const Words q = philox_pair((uint64_t)p, (uint32_t)t, kTagAlbedo, k0, k1);
         const float u[4] = {unit24(q.w0), unit24(q.w1), unit24(q.w2), unit24(q.w3)};
@@ -826,12 +1037,14 @@ __device__ __forceinline__ float microbench_lane(int64_t t, int32_t pairs, uint3
                 const AdjTerm r = albedo_adj(c, 0.04f, u[2 * j], u[2 * j + 1]);
                 acc[0] += r.w; acc[1] += r.dax; acc[2] += r.day; acc[3] += r.dth;
                 acc[4] += r.dwsx; acc[5] += r.dwsy; acc[6] += r.dzs;
+                mf = fmaxf(mf, r.margin);  // the loops' flag
             } else {
                 acc[0] += radiance_term(c, 0.04f, lobes, u[2 * j], u[2 * j + 1]);
             }
         }
     }
-    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]);
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + acc[6]) +
+           mf;
 }
 
 template <int KIND>
@@ -1003,7 +1216,9 @@ struct capvndf_batch_plan {
     int32_t* d_job_chunks = nullptr;
     int64_t* d_nsamp = nullptr;
     float* d_partial = nullptr;
+    uint64_t* d_rec = nullptr;  // horizon records of the chunks (with_grad)
     float* d_req_ws = nullptr;  // per-request baseline scratch
+    uint64_t* d_req_rec = nullptr;
     int32_t* d_counter = nullptr;  // dynamic scheduling
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1086,6 +1301,9 @@ void cache_store(const std::string& sig, const capvndf_tiling& t, float ms) {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Threads of a chunk's owner: a wavefront per wave, else the block.
+int32_t owner_threads(const capvndf_tiling& t) { return t.per_wave ? 64 : t.block; }
+
 int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
     const int g = p->with_grad;
     const uint32_t k0 = key_lo(p->seed), k1 = key_hi(p->seed);
@@ -1098,7 +1316,8 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
 #define CAPVNDF_LAUNCH_BATCH(K, B, G, D)                                                            \
     hipLaunchKernelGGL((K<B, G, D>), grid, block, 0, st, p->wox, p->woy, p->woz, p->ax, p->ay,    \
                        p->f0, p->d_nsamp, p->d_chunk_job, p->d_chunk_pbeg, p->d_chunk_pend,        \
-                       p->d_block_chunks, p->d_counter, (int32_t)p->nchunks, k0, k1, p->d_partial)
+                       p->d_block_chunks, p->d_counter, (int32_t)p->nchunks, k0, k1, p->d_partial, \
+                       p->d_rec)
 #define CAPVNDF_LAUNCH_BATCH_D(K, B, G)                                                             \
     do {                                                                                            \
         if (dyn) CAPVNDF_LAUNCH_BATCH(K, B, G, true);                                               \
@@ -1122,6 +1341,13 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
 #undef CAPVNDF_LAUNCH_BATCH_D
 #undef CAPVNDF_LAUNCH_BATCH
     if (int32_t rc = check_launch("batch kernel launch")) return rc;
+    if (g) {
+        launch_fix<false, true>(p->nchunks, owner_threads(p->tiling), p->wox, p->woy, p->woz,
+                                p->ax, p->ay, p->f0, p->d_nsamp, 0, 0u, p->d_chunk_job,
+                                p->d_chunk_pbeg, p->d_chunk_pend, k0, k1, p->d_rec, p->d_partial,
+                                st);
+        if (int32_t rc = check_launch("batch fix launch")) return rc;
+    }
     if (g)
         hipLaunchKernelGGL(k_finish<4>, dim3(finish_grid(p->njobs)), dim3(kFinishBlock), 0, st,
                            p->njobs, p->d_partial, 0, p->d_job_chunks, p->d_nsamp, nullptr,
@@ -1270,7 +1496,10 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     const size_t o_jc = carve(sizeof(int32_t) * (size_t)(njobs + 1));
     const size_t o_ns = carve(sizeof(int64_t) * (size_t)njobs);
     const size_t o_pa = carve(sizeof(float) * 2 * nacc * (size_t)std::max<int64_t>(nchunks, 1));
+    const int rec_words = owner_threads(t) / 64;
+    const size_t o_rc = carve(with_grad ? rec_bytes(std::max<int64_t>(nchunks, 1), rec_words) : 8);
     const size_t o_rw = carve(sizeof(float) * 8 * (size_t)max_cpc);
+    const size_t o_rr = carve(with_grad ? rec_bytes(max_cpc, kLutBlock / 64) : 8);
     const size_t o_ct = carve(sizeof(int32_t));
     capvndf_batch_plan* p = new capvndf_batch_plan();
     if (int32_t rc = check_hip(hipMalloc(&p->dmem, off), "hipMalloc (batch plan)")) {
@@ -1286,7 +1515,9 @@ int32_t create_plan(int64_t njobs, const float* wox, const float* woy, const flo
     p->d_job_chunks = reinterpret_cast<int32_t*>(base + o_jc);
     p->d_nsamp = reinterpret_cast<int64_t*>(base + o_ns);
     p->d_partial = reinterpret_cast<float*>(base + o_pa);
+    p->d_rec = reinterpret_cast<uint64_t*>(base + o_rc);
     p->d_req_ws = reinterpret_cast<float*>(base + o_rw);
+    p->d_req_rec = reinterpret_cast<uint64_t*>(base + o_rr);
     p->d_counter = reinterpret_cast<int32_t*>(base + o_ct);
     int32_t rc = CAPVNDF_OK;
     if (nchunks > 0) {
@@ -1394,10 +1625,14 @@ extern "C" int32_t albedo_batch_run_per_request(capvndf_batch_plan* p, void* str
         const float* f0 = p->f0 ? p->f0 + j : nullptr;
         const int64_t* nj = p->d_nsamp + j;
         if (p->with_grad) {
-            if (cpc > 0)
+            if (cpc > 0) {
                 hipLaunchKernelGGL(k_albedo_adj<true>, dim3((unsigned)cpc), dim3(kLutBlock), 0, st,
                                    p->wox + j, p->woy + j, p->woz + j, p->ax + j, p->ay + j, f0,
-                                   nj, slots, (uint32_t)j, k0, k1, p->d_req_ws);
+                                   nj, slots, (uint32_t)j, k0, k1, p->d_req_ws, p->d_req_rec);
+                launch_table_fix<true>(1, slots, p->wox + j, p->woy + j, p->woz + j, p->ax + j,
+                                       p->ay + j, f0, nj, (uint32_t)j, k0, k1, p->d_req_rec,
+                                       p->d_req_ws, st);
+            }
             hipLaunchKernelGGL(k_finish<4>, dim3(1), dim3(kFinishBlock), 0, st, (int64_t)1,
                                p->d_req_ws, slots, nullptr, nj, nullptr, p->albedo + j,
                                p->gax + j, p->gay + j, p->gth + j);

@@ -17,6 +17,25 @@
 
 namespace capvndf {
 
+// Reflections within the FP32 path's rounding of the horizon.  The FP32
+// normal is within (8 + 48 kappa) 2^-24 of the exact one (first-order count,
+// kappa = max(1, ax, ay) / L with L = |M^-T hs|), and wl = 2 (wo.h) h - wo
+// multiplies that by 4 and adds the roundings of the dot product, the
+// reflection and wo's normalisation: wl_z within (44 + 192 kappa) 2^-24 of 0
+// may lie on either side of the horizon, where the weight's slope jumps from
+// its live value to 0.  albedo_adj flags such samples (a few in 10^5) with a
+// margin >= 0; the adjoint kernels record which lanes had one, and a separate
+// pass evaluates them again in double precision, replacing their FP32 terms.
+constexpr float kBandC0 = 44.0f * 0x1p-24f;
+constexpr float kBandC1 = 192.0f * 0x1p-24f;
+// Beyond this conditioning the FP32 sample's terms carry relative errors
+// above about 1 % ((35 + 200 kappa) 2^-24); such samples take the double path
+// too, wherever their reflection lies.
+constexpr float kIllConditioned = 1024.0f;
+// the band's width at that conditioning: a sample is flagged if |wl_z| or
+// kBandIll is within its band
+constexpr float kBandIll = kBandC0 + kBandC1 * kIllConditioned;
+
 // Per-cell (or per-job) constants, uniform across the lanes working on it.
 struct CellConst {
     float ox, oy, oz;  // unit view direction
@@ -26,7 +45,7 @@ struct CellConst {
     float tgo;         // 2 - G1(wo)
     float tx, ty, tz;  // meridian tangent dwo/dtheta_o
     float rx, ry, rz;  // the view direction as given (for the double-precision path)
-    float amax;        // max(1, ax, ay)
+    float b1;          // kBandC1 max(1, ax, ay): the horizon band's slope in 1 / L
     bool ok;           // inside the domain
 };
 
@@ -39,7 +58,8 @@ __device__ __forceinline__ CellConst cell_setup(float wx, float wy, float wz, fl
     c.rx = wx;
     c.ry = wy;
     c.rz = wz;
-    c.amax = fmaxf(1.0f, fmaxf(ax, ay));
+    const float amax = fmaxf(1.0f, fmaxf(ax, ay));
+    c.b1 = kBandC1 * amax;
     const float in = rsq(__builtin_fmaf(wx, wx, __builtin_fmaf(wy, wy, wz * wz)));
     c.ox = wx * in;
     c.oy = wy * in;
@@ -159,24 +179,8 @@ __device__ __forceinline__ float radiance_term(const CellConst& c, float f0, con
 // applied once per thread by ws_chain().
 struct AdjTerm {
     float w, dax, day, dth, dwsx, dwsy, dzs;
-    bool amb;  // FP32 cannot place the reflection relative to the horizon
+    float margin;  // >= 0: a flagged sample (see kBandC0), else negative
 };
-
-// Reflections within the FP32 path's rounding of the horizon.  The FP32
-// normal is within (8 + 48 kappa) 2^-24 of the exact one (first-order count,
-// kappa = max(1, ax, ay) / L with L = |M^-T hs|), and wl = 2 (wo.h) h - wo
-// multiplies that by 4 and adds the roundings of the dot product, the
-// reflection and wo's normalisation: wl_z within (44 + 192 kappa) 2^-24 of 0
-// may lie on either side of the horizon, where the weight's slope jumps from
-// its live value to 0.  albedo_adj flags such samples (a few in 10^5), and
-// the sample loops evaluate them again in double precision after their pass
-// over the chunk, replacing the FP32 terms.
-constexpr float kBandC0 = 44.0f * 0x1p-24f;
-constexpr float kBandC1 = 192.0f * 0x1p-24f;
-// Beyond this conditioning the FP32 sample's terms carry relative errors
-// above about 1 % ((35 + 200 kappa) 2^-24); such samples take the double path
-// too, wherever their reflection lies.
-constexpr float kIllConditioned = 1024.0f;
 
 // albedo_adj's value and derivatives in double precision from the cell's
 // inputs as given (the same steps; the FP32 view direction, roughness and
@@ -273,7 +277,7 @@ __device__ __attribute__((noinline)) AdjTerm albedo_adj_f64(const CellConst& c, 
     r.dwsx = (float)dhsx;
     r.dwsy = (float)dhsy;
     r.dzs = (float)dzs;
-    r.amb = false;
+    r.margin = -1.0f;
     return r;
 }
 
@@ -300,8 +304,9 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     const float wlx = __builtin_fmaf(x2, hx, -c.ox);
     const float wly = __builtin_fmaf(x2, hy, -c.oy);
     const float wlz = __builtin_fmaf(x2, hz, -c.oz);
-    const float kap = c.amax * iL;
-    const bool amb = !(fabsf(wlz) > __builtin_fmaf(kBandC1, kap, kBandC0)) || kap > kIllConditioned;
+    // kappa = max(1, ax, ay) iL and band = (44 + 192 kappa) 2^-24: flagged if
+    // |wl_z| <= band or kappa >= kIllConditioned, i.e. band >= kBandIll
+    const float margin = __builtin_fmaf(c.b1, iL, kBandC0) - fminf(fabsf(wlz), kBandIll);
     const float plx = c.ax * wlx, ply = c.ay * wly;
     const float pp = __builtin_fmaf(plx, plx, ply * ply);
     const float m2 = __builtin_fmaf(wlz, wlz, pp);
@@ -369,7 +374,7 @@ __device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, floa
     r.dwsx = dhsx;
     r.dwsy = dhsy;
     r.dzs = dzs;
-    r.amb = amb;
+    r.margin = margin;
     return r;
 }
 

@@ -93,20 +93,21 @@ def test_albedo_argument_errors(lib):
     def counts(*v):
         return (i64 * len(v))(*v)
 
-    # workspace: ncells * slots * partial sums * 8 bytes; slots per cell aim
-    # at 8192 blocks with at least 64, below 2^24 blocks, and (given host
-    # counts) no more than the largest cell's chunks of 16384 samples
+    # workspace: ncells * slots * partial sums * 8 bytes, plus with gradients
+    # a 32-byte horizon record per slot; slots per cell aim at 8192 blocks with
+    # at least 64, below 2^24 blocks, and (given host counts) no more than the
+    # largest cell's chunks of 16384 samples
     assert lib.albedo_workspace_size(-1, None, 0) == 0
     assert lib.albedo_workspace_size(0, None, 0) == 0
     assert lib.albedo_workspace_size(1 << 24, None, 0) == 0
     assert lib.albedo_workspace_size(16, None, 2) == 0
     assert lib.albedo_workspace_size(4096, None, 0) == 4096 * 64 * 2 * 8
-    assert lib.albedo_workspace_size(4096, None, 1) == 4096 * 64 * 4 * 8
+    assert lib.albedo_workspace_size(4096, None, 1) == 4096 * 64 * (4 * 8 + 32)
     assert lib.albedo_workspace_size(4096, counts(*[1 << 20] * 4096), 0) == 4096 * 64 * 2 * 8
-    assert lib.albedo_workspace_size(4096, counts(*[4096] * 4096), 1) == 4096 * 1 * 4 * 8
+    assert lib.albedo_workspace_size(4096, counts(*[4096] * 4096), 1) == 4096 * 1 * (4 * 8 + 32)
     assert lib.albedo_workspace_size(1, None, 0) == 8192 * 2 * 8
     assert lib.albedo_workspace_size(1, counts(1 << 20), 0) == 64 * 2 * 8
-    assert lib.albedo_workspace_size(1, counts(1 << 30), 1) == 8192 * 4 * 8
+    assert lib.albedo_workspace_size(1, counts(1 << 30), 1) == 8192 * (4 * 8 + 32)
     assert lib.albedo_workspace_size(3, counts(0, 1, 0), 0) == 3 * 1 * 2 * 8
     assert lib.albedo_workspace_size(2, counts(0, 0), 0) == 2 * 1 * 2 * 8
     assert lib.albedo_workspace_size(1 << 20, None, 0) == (1 << 20) * 15 * 2 * 8
@@ -128,12 +129,12 @@ def test_albedo_argument_errors(lib):
     assert lib.albedo_estimate(4, *five, fake, 0, None, fake, fake, 1 << 20, None) == -1
     assert lib.albedo_estimate(0, *[None] * 5, None, 0, None, None, None, 0, None) == 0
     assert lib.albedo_estimate_backward(4, *five, fake, 0, None, None, fake, fake, fake, fake,
-                                        4 * 24 - 1, None) == -5
+                                        4 * (24 + 32) - 1, None) == -5
     # value_and_grad: partial gradient outputs, small workspace, no value output
     assert lib.albedo_value_and_grad(4, *five, fake, 0, None, fake, fake, None, None, fake,
                                      1 << 20, None) == -1
     assert lib.albedo_value_and_grad(4, *five, fake, 0, None, fake, fake, fake, fake, fake,
-                                     4 * 32 - 1, None) == -5
+                                     4 * (32 + 32) - 1, None) == -5
     assert lib.albedo_value_and_grad(4, *five, fake, 0, None, None, None, None, None, fake,
                                      4 * 8 - 1, None) == -1
     assert lib.albedo_value_and_grad(4, *five, fake, 0, None, fake, None, None, None, fake,

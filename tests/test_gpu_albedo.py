@@ -117,7 +117,8 @@ def test_one_slot_per_cell():
     g = workloads.lut_grid(4, 4)
     t = to_dev(g)
     ns = np.array([0, 1, 70001, 1 << 18] * 4, dtype=np.int64)
-    ws = torch.empty(16 * 4 * 2, device="cuda")  # 16 cells x 4 sums x (s, c)
+    # 16 cells x (4 sums x (s, c) + a 32-byte horizon record)
+    ws = torch.empty(16 * (4 * 2 + 8), device="cuda")
     a, gx, gy, gt = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], ns, 14,
                                              workspace=ws)
     A, rx, ry, rt = oracle.albedo_grad((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], ns, 14)
