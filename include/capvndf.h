@@ -66,15 +66,16 @@ extern "C" {
 #define CAPVNDF_DISK2018 1 /* Heitz 2018 cross section, Sec. 2 (baseline)    */
 #define CAPVNDF_CAP_F64 2  /* spherical cap evaluated in double precision   */
 
-/* Version of this ABI (major * 10000 + minor * 100 + patch): 3.1.0.  Minor 1
- * of major 3 added a 32-byte horizon record per slot to the workspace of the
- * gradient entry points (albedo_workspace_size covers it); major 3
+/* Version of this ABI (major * 10000 + minor * 100 + patch): 3.2.0.  Minor 2
+ * of major 3 added albedo_value_and_grad_noalloc; minor 1 added a 32-byte
+ * horizon record per slot to the workspace of the gradient entry points
+ * (albedo_workspace_size covers it); major 3
  * gave the table estimators per-cell device sample counts and
  * albedo_workspace_size its (ncells, host counts, with_grad) form; major 2
  * added the `dynamic` field to capvndf_tiling (a layout change) and the
  * CAPVNDF_CAP_F64 method; minor 1 of major 2 added albedo_view_from_angles
  * and albedo_apply_jacobian. */
-#define CAPVNDF_VERSION 30100
+#define CAPVNDF_VERSION 30200
 int32_t capvndf_version(void);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -322,6 +323,31 @@ int32_t albedo_value_and_grad(int64_t ncells, const float* wox, const float* woy
                               const int64_t* nsamples, uint64_t seed, const float* f0,
                               float* albedo, float* grad_ax, float* grad_ay, float* grad_theta_o,
                               void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * albedo_value_and_grad_noalloc -- albedo_value_and_grad without a workspace
+ * argument, for callers that cannot allocate device memory: code that must
+ * not call hipMalloc while it enqueues work (a stream being captured into a
+ * graph, a tight serving loop, a harness that forbids allocation).  It
+ * allocates nothing: its partial sums and horizon records live in a 16 MiB
+ * device buffer of the library (a file-scope array, one copy per device,
+ * held until the process ends), whose address is looked up once per device
+ * on the first call there.  Same arguments, results and errors as
+ * albedo_value_and_grad (the same kernels, so the same bits as a call with a
+ * workspace of the size this buffer gives), except:
+ *   - at most 262144 cells per call with gradients (64 bytes per cell at one
+ *     slot) and 2097152 without (8 bytes); more gives BAD_SIZE;
+ *   - the slot count is the one a 16 MiB workspace allows;
+ *   - every call on one device shares the buffer: calls that overlap on one
+ *     device (two streams, two host threads) race on it and must be ordered
+ *     by the caller.  Nothing needs clearing between calls: each call writes
+ *     every partial and record it reads.
+ */
+int32_t albedo_value_and_grad_noalloc(int64_t ncells, const float* wox, const float* woy,
+                                      const float* woz, const float* ax, const float* ay,
+                                      const int64_t* nsamples, uint64_t seed, const float* f0,
+                                      float* albedo, float* grad_ax, float* grad_ay,
+                                      float* grad_theta_o, void* stream);
 
 /*
  * radiance_estimate -- direct illumination per cell: the Monte Carlo

@@ -7,7 +7,8 @@ the current stream) into the C ABI declared in ``include/capvndf.h``.  There is
 no CPU fallback: without the built library every call raises.
 
 Names mirror the C entry points: ``vndf_sample``, ``vndf_pdf``, ``vndf_inverse``,
-``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_value_and_grad``,
+``albedo_estimate``, ``albedo_estimate_backward``, ``albedo_value_and_grad``
+(and ``albedo_value_and_grad_noalloc``),
 ``albedo_workspace_size``, ``radiance_estimate``,
 ``BatchPlan`` (``albedo_batch_plan_create`` / ``albedo_batch_run`` /
 ``albedo_batch_run_per_request``), ``albedo_batch_autotune``, and the hooks
@@ -76,6 +77,8 @@ _SIGNATURES = {
                                   ctypes.c_size_t, _P], _I32),
     "albedo_value_and_grad": ([_I64, _P, _P, _P, _P, _P, _P, _U64, _P, _P, _P, _P, _P, _P,
                                ctypes.c_size_t, _P], _I32),
+    "albedo_value_and_grad_noalloc": ([_I64, _P, _P, _P, _P, _P, _P, _U64, _P, _P, _P, _P, _P,
+                                       _P], _I32),
     "radiance_estimate": ([_I64, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _I32, _P, _P,
                            ctypes.c_size_t, _P], _I32),
     "albedo_view_from_angles": ([_I64, _P, _P, _P, _P, _P, _P], _I32),
@@ -360,6 +363,33 @@ def albedo_value_and_grad(wox, woy, woz, ax, ay, nsamples, seed, f0=None, with_g
                                    _ptr(ns), seed, _ptr(f0), _ptr(a), *[_ptr(x) for x in g],
                                    _ptr(ws), ws.numel() * 4, _stream(stream))
     _check("albedo_value_and_grad", rc)
+    return (a, *g)
+
+
+def albedo_value_and_grad_noalloc(wox, woy, woz, ax, ay, nsamples, seed, f0=None,
+                                  with_grad=True, stream=None, out=None):
+    """albedo_value_and_grad on the library's own device buffer (no workspace
+    argument).  `nsamples` must already be a GPU int64 tensor and `out`, if
+    given, the (albedo, grad_ax, grad_ay, grad_theta_o) tensors (the grads
+    None without gradients), so that the call allocates nothing."""
+    lib = load_library()
+    n = wox.numel()
+    for k, t in dict(wox=wox, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0).items():
+        _dev(t, k)
+    _same_len(n, woy=woy, woz=woz, ax=ax, ay=ay, f0=f0)
+    if not (isinstance(nsamples, torch.Tensor) and nsamples.is_cuda):
+        raise TypeError("nsamples must be a GPU int64 tensor")
+    _dev(nsamples, "nsamples", torch.int64)
+    _same_len(n, nsamples=nsamples)
+    if out is None:
+        a = torch.empty_like(wox)
+        g = [torch.empty_like(wox) for _ in range(3)] if with_grad else [None, None, None]
+    else:
+        a, g = out[0], list(out[1:])
+    rc = lib.albedo_value_and_grad_noalloc(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
+                                           _ptr(nsamples), seed, _ptr(f0), _ptr(a),
+                                           *[_ptr(x) for x in g], _stream(stream))
+    _check("albedo_value_and_grad_noalloc", rc)
     return (a, *g)
 
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -996,6 +997,85 @@ extern "C" int32_t radiance_estimate(int64_t ncells, const float* wox, const flo
                        nullptr);
     return check_launch("radiance_estimate finish launch");
 }
+
+// ===========================================================================
+// albedo_value_and_grad on a partial buffer the library owns, for callers
+// that cannot allocate device memory.  The buffer is a file-scope device
+// array; host code never passes its name to a kernel, only the device
+// address hipGetSymbolAddress returns for the current device (each device
+// holds its own copy), taken once per device on the first call there.
+// Nothing in it needs clearing: every partial and horizon record a call
+// reads was written by the same call.  Calls that overlap on one device race
+// on it.
+// ===========================================================================
+namespace capvndf {
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) float scratch[kScratchBytes / sizeof(float)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+float* g_scratch[kMaxDevices] = {};
+
+int32_t scratch_of_current_device(const char* fn, float** out) {
+    int dev = 0;
+    if (int32_t rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(CAPVNDF_ERR_BAD_ARG, "%s: device %d beyond the %d this library tracks", fn, dev,
+                    kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[dev] == nullptr) {
+        void* ptr = nullptr;
+        if (int32_t rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)),
+                                   "hipGetSymbolAddress (scratch)"))
+            return rc;
+        g_scratch[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch[dev];
+    return CAPVNDF_OK;
+}
+
+}  // namespace
+}  // namespace capvndf
+
+extern "C" int32_t albedo_value_and_grad_noalloc(int64_t ncells, const float* wox,
+                                                 const float* woy, const float* woz,
+                                                 const float* ax, const float* ay,
+                                                 const int64_t* nsamples, uint64_t seed,
+                                                 const float* f0, float* albedo, float* grad_ax,
+                                                 float* grad_ay, float* grad_theta_o,
+                                                 void* stream) {
+    const char* fn = "albedo_value_and_grad_noalloc";
+    bool grad = false;
+    if (ncells > 0)
+        if (int32_t rc = check_value_and_grad_outputs(fn, f0, albedo, grad_ax, grad_ay,
+                                                      grad_theta_o, &grad))
+            return rc;
+    // one slot per cell: partials, and with gradients the horizon record
+    const size_t per_cell = table_bytes(1, 1, grad ? 4 : 1, grad);
+    if (ncells > (int64_t)(kScratchBytes / per_cell))
+        return fail(CAPVNDF_ERR_BAD_SIZE,
+                    "%s: at most %lld cells per call %s gradients (the library's buffer holds "
+                    "%zu bytes); use albedo_value_and_grad with a workspace", fn,
+                    (long long)(kScratchBytes / per_cell), grad ? "with" : "without",
+                    kScratchBytes);
+    if (ncells <= 0) {
+        int32_t slots = 0;
+        return prepare_cells(fn, ncells, wox, woy, woz, ax, ay, nsamples, 1, false, nullptr, 0,
+                             &slots);
+    }
+    float* buf = nullptr;
+    if (int32_t rc = scratch_of_current_device(fn, &buf)) return rc;
+    int32_t slots = 0;
+    if (int32_t rc = prepare_cells(fn, ncells, wox, woy, woz, ax, ay, nsamples, grad ? 4 : 1,
+                                   grad, buf, kScratchBytes, &slots))
+        return rc;
+    return enqueue_value_and_grad(ncells, wox, woy, woz, ax, ay, nsamples, seed, f0, albedo,
+                                  grad_ax, grad_ay, grad_theta_o, grad, buf, slots,
+                                  as_stream(stream));
+}
+
 
 // ===========================================================================
 // Register-resident estimator microbenchmark: each lane runs the per-sample
