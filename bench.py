@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 HEADLINE_METHOD = 2    # CAPVNDF_CAP_F64
 MIN_LAUNCHES = 100     # per-launch statistics of the streaming kernels
 MIN_EST_STEPS = 10     # timed launches of the estimator sections
-SETTLE_LAUNCHES = 250  # untimed launches of the headline kernel before its warm-up
+SETTLE_LAUNCHES = 500  # untimed launches of the headline kernel before its warm-up
 SECTIONS = ("stream", "fp32", "disk", "probe", "inverse", "dielectric", "micro", "lut", "grad",
             "batch", "radiance")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "estimator_full.npz")
@@ -69,6 +69,10 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-short-jobs", action="store_true",
                     help="batch section: leave out the short-job mix")
+    ap.add_argument("--no-plain-pipeline", action="store_true",
+                    help="batch section: leave out the per-request plain-sampler pipeline "
+                         "(about 28k launches per pass and a graph of as many nodes; the "
+                         "counter passes, which only need the batch kernels, skip it)")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None)
     ap.add_argument("--oracle-full-table", action="store_true",
                     help="CPU leg: run the oracle over the whole 64 x 64 x 2^20 table, timed, "
@@ -380,9 +384,9 @@ def _stream_entry(ms, stats, bytes_per_sample=BYTES_PER_SAMPLE):
 #   trace/   --kernel-trace --stats  of  bench.py --only stream fp32 disk probe
 #   fetch/   --pmc FETCH_SIZE        of  the same sections (fewer steps)
 #   write/   --pmc WRITE_SIZE        of  the same sections (fewer steps)
-#   valu_a/  --pmc <VALU counters>   of  bench.py --only micro lut
-#   valu_b/  --pmc <VALU counters> --kernel-include-regex (k_batch|k_radiance)
-#            of bench.py --only batch radiance --no-short-jobs
+#   valu_a/  --pmc <VALU counters>   of  bench.py --only micro lut radiance
+#   valu_b/  (optional) --pmc <VALU counters> --kernel-include-regex
+#            (k_batch|k_radiance|k_horizon_fix) of bench.py --only batch ...
 # and bench_plain.json (the JSON line of the traced command run without the
 # profiler, same box) and commands.txt ("<pass>: <command>" per line).
 # ---------------------------------------------------------------------------
@@ -578,7 +582,9 @@ def summarize_valu(d, cmds, prof, batch_samples):
     from SQ counters; samples per dispatch from the workloads' sizes."""
     import numpy as np
     a = read_counters(os.path.join(d, "valu_a"))
-    b = read_counters(os.path.join(d, "valu_b"))
+    # the batch kernels' pass is optional (its own run, with the include regex)
+    b = read_counters(os.path.join(d, "valu_b")) if os.path.isdir(os.path.join(d, "valu_b")) \
+        else {}
     lut = 4096 * (1 << 20)
     lut_grid = 4096 * 64 * 256
     micro = 256 * 2048 * 4 * 64
@@ -590,6 +596,15 @@ def summarize_valu(d, cmds, prof, batch_samples):
         if k:
             rows.append((key, k, desc + " (64x64 cells x 2^20)", lut,
                          [x for x in a[k] if x["grid"] == lut_grid]))
+    # the horizon fix passes after the table's adjoint kernels (a wavefront
+    # per slot: 65536 blocks of 256 work-items)
+    for pre, key, desc in (("k_horizon_fix<true, false>", "fix_backward", "horizon fix after backward"),
+                           ("k_horizon_fix<true, true>", "fix_value_and_grad",
+                            "horizon fix after value + Jacobian")):
+        k = _kernel(a, pre)
+        if k:
+            rows.append((key, k, desc + " (per table sample)", lut,
+                         [x for x in a[k] if x["grid"] == lut_grid // 4]))
     for m, name in ((0, "cap"), (1, "disk"), (2, "cap in double precision")):
         k = _kernel(a, f"k_microbench<{m}>")
         if k:
@@ -602,19 +617,23 @@ def summarize_valu(d, cmds, prof, batch_samples):
         if k:
             rows.append((key, k, f"register-resident estimator code: {name} (2^21 lanes x 64)",
                          ESTIMATOR_MICRO_SAMPLES, a[k]))
-    k = _kernel(b, "k_radiance<4>")
+    src = b if _kernel(b, "k_radiance<4>") else a
+    k = _kernel(src, "k_radiance<4>")
     if k:
         rows.append(("radiance", k, "direct illumination, 4 lobes (64x64 cells x 2^20)", lut,
-                     [x for x in b[k] if x["grid"] == lut_grid]))
+                     [x for x in src[k] if x["grid"] == lut_grid]))
     for k in sorted(b):
         if k.startswith("k_batch"):
             rows.append((f"batch:{k}", k, "batch forward + adjoint, 4096 jobs", batch_samples,
+                         b[k]))
+        elif k.startswith("k_horizon_fix<false"):
+            rows.append((f"batch:{k}", k, "batch horizon fix (per batch sample)", batch_samples,
                          b[k]))
     rec = {"source_digest": _valu_digest(), "valu_lane_instr_per_sample": {},
            "peak_lane_instr_per_s": VALU_PEAK, "source": "profiles/albedo_valu_counters.md"}
     lines = ["# VALU counters of the estimators and the sampler microbenchmark", "",
              "MI355X (gfx950).  Commands (counter passes of the benchmark itself):", "", "```",
-             cmds.get("valu_a", ""), cmds.get("valu_b", ""), "```", "",
+             *[cmds[k] for k in ("valu_a", "valu_b") if k in cmds], "```", "",
              "Counts per dispatch (mean over the dispatches listed).  VALU lane-instructions = "
              "`SQ_INSTS_VALU` x 64.  `GRBM_GUI_ACTIVE` is summed over the 8 XCDs, so busy "
              "time = value / 8 / 2.4 GHz.  Peak for the fraction: 256 CUs x 128 FP32 lanes x "
@@ -674,7 +693,7 @@ def summarize_profiles(d, prof=None, batch_samples=None):
     if os.path.isdir(os.path.join(d, "fetch")) and os.path.isdir(os.path.join(d, "write")):
         summarize_traffic(d, cmds, prof)
         done.append("stream_sampler_2p26_counters")
-    if os.path.isdir(os.path.join(d, "valu_a")) and os.path.isdir(os.path.join(d, "valu_b")):
+    if os.path.isdir(os.path.join(d, "valu_a")):
         if batch_samples is None:
             import workloads
             batch_samples = int(workloads.batch_jobs(4096, seed=4)["n"].sum())
@@ -977,29 +996,37 @@ def main():
         # pipeline also needs a weighting and reduction pass, left out here,
         # so its time is a lower bound.  Timed eagerly and captured in one
         # graph (which removes the host's launch cost).
-        log("per-request plain-sampler pipeline (lower bound: no weighting pass)")
-        ns = [int(x) for x in j["n"]]
-        nmax = max(ns)
-        vals = [c[k].tolist() for k in ("wx", "wy", "wz", "ax", "ay")]
-        bi = [torch.empty(nmax, device=dev) for _ in range(5)]
-        bu = [torch.empty(nmax, device=dev) for _ in range(2)]
-        bo = [torch.empty(nmax, device=dev) for _ in range(4)]
+        plain_res = None
+        if not args.no_plain_pipeline:
+            log("per-request plain-sampler pipeline (lower bound: no weighting pass)")
+            ns = [int(x) for x in j["n"]]
+            nmax = max(ns)
+            vals = [c[k].tolist() for k in ("wx", "wy", "wz", "ax", "ay")]
+            bi = [torch.empty(nmax, device=dev) for _ in range(5)]
+            bu = [torch.empty(nmax, device=dev) for _ in range(2)]
+            bo = [torch.empty(nmax, device=dev) for _ in range(4)]
 
-        def plain():
-            for q, m in enumerate(ns):
-                for b, v in zip(bi, vals):
-                    b[:m].fill_(v[q])
-                u1, u2 = cv.capvndf_uniforms(4, 3, q, 0, m, out=(bu[0][:m], bu[1][:m]))
-                cv.vndf_sample(bi[0][:m], bi[1][:m], bi[2][:m], bi[3][:m], bi[4][:m], u1=u1,
-                               u2=u2, method=HEADLINE_METHOD, out=tuple(o[:m] for o in bo))
-        ms_plain, _ = timed(plain, 2, 1)
-        t0 = time.perf_counter()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            plain()
-        capture_s = time.perf_counter() - t0
-        ms_plain_graph, _ = timed(graph.replay, 3, 1)
-        del graph, bi, bu, bo
+            def plain():
+                for q, m in enumerate(ns):
+                    for b, v in zip(bi, vals):
+                        b[:m].fill_(v[q])
+                    u1, u2 = cv.capvndf_uniforms(4, 3, q, 0, m, out=(bu[0][:m], bu[1][:m]))
+                    cv.vndf_sample(bi[0][:m], bi[1][:m], bi[2][:m], bi[3][:m], bi[4][:m], u1=u1,
+                                   u2=u2, method=HEADLINE_METHOD, out=tuple(o[:m] for o in bo))
+            ms_plain, _ = timed(plain, 2, 1)
+            t0 = time.perf_counter()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                plain()
+            capture_s = time.perf_counter() - t0
+            ms_plain_graph, _ = timed(graph.replay, 3, 1)
+            del graph, bi, bu, bo
+            plain_res = {"what": "per job: 5 fills, the job's uniforms, vndf_sample; no "
+                                 "weighting or reduction pass (a lower bound)",
+                         "eager_ms": round(ms_plain, 2),
+                         "graph_ms": round(ms_plain_graph, 2),
+                         "graph_capture_s": round(capture_s, 2),
+                         "speedup_vs_graph": round(ms_plain_graph / ms_b, 2)}
         info = plan.info()
         out["batched"] = {"jobs": 4096, "total_samples": info["total_samples"],
                           "tiling": info["tiling"], "chunks": info["nchunks"],
@@ -1014,13 +1041,7 @@ def main():
                           "roofline": alu_roofline(batch_kernel(info["tiling"]), info["total_samples"],
                                                    ms_b),
                           "max_abs_diff_graph_vs_per_request": diff,
-                          "per_request_plain_sampler": {
-                              "what": "per job: 5 fills, the job's uniforms, vndf_sample; no "
-                                      "weighting or reduction pass (a lower bound)",
-                              "eager_ms": round(ms_plain, 2),
-                              "graph_ms": round(ms_plain_graph, 2),
-                              "graph_capture_s": round(capture_s, 2),
-                              "speedup_vs_graph": round(ms_plain_graph / ms_b, 2)}}
+                          "per_request_plain_sampler": plain_res}
         plan.close()
         if not args.no_short_jobs:
             # a mix of short jobs (2^10 .. 2^14 samples), where wavefront-owned
