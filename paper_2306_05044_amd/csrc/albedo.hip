@@ -1421,7 +1421,7 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
 #undef CAPVNDF_LAUNCH_BATCH_D
 #undef CAPVNDF_LAUNCH_BATCH
     if (int32_t rc = check_launch("batch kernel launch")) return rc;
-    if (g) {
+    if (g && p->nchunks > 0) {  // a plan of empty jobs has no chunks, and nothing to fix
         launch_fix<false, true>(p->nchunks, owner_threads(p->tiling), p->wox, p->woy, p->woz,
                                 p->ax, p->ay, p->f0, p->d_nsamp, 0, 0u, p->d_chunk_job,
                                 p->d_chunk_pbeg, p->d_chunk_pend, k0, k1, p->d_rec, p->d_partial,

@@ -153,3 +153,20 @@ def test_full_batch_every_job():
                   f"{bool(np.all(gold['batch_band_count'][over] > 0))}")
             assert np.all(d <= lim), f"{mode} d/d {name}: job {worst} at {d[worst] / lim[worst]:.2f}x"
     plan.close()
+
+
+@pytest.mark.parametrize("tiling", [None, (256, 16, 8, 1, 0), (512, 32, 4, 0, 1)])
+def test_plan_of_empty_jobs(tiling):
+    """A plan whose jobs all have 0 samples has no chunks: it is created,
+    replays and yields 0 for every value and derivative."""
+    j = workloads.batch_jobs(5, seed=9, log2_min=4, log2_max=6)
+    j["n"][:] = 0
+    t = to_dev({k: v for k, v in j.items() if k != "n"})
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True,
+                        tiling=tiling)
+    for _ in range(2):
+        plan.run()
+        torch.cuda.synchronize()
+        for x in (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o):
+            assert np.all(host(x) == 0.0)
+    plan.close()
