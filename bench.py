@@ -43,8 +43,8 @@ HEADLINE_METHOD = 2    # CAPVNDF_CAP_F64
 MIN_LAUNCHES = 100     # per-launch statistics of the streaming kernels
 MIN_EST_STEPS = 10     # timed launches of the estimator sections
 SETTLE_LAUNCHES = 500  # untimed launches of the headline kernel before its warm-up
-SECTIONS = ("stream", "fp32", "disk", "probe", "inverse", "dielectric", "micro", "lut", "grad",
-            "batch", "radiance")
+SECTIONS = ("plain", "stream", "fp32", "disk", "probe", "inverse", "dielectric", "micro", "lut",
+            "grad", "batch", "radiance")
 GOLDEN = os.path.join(ROOT, "tests", "golden", "estimator_full.npz")
 
 
@@ -293,6 +293,19 @@ def oracle_checks(checks):
     errs = {}
     gold = load_golden()
     threads, _ = cpu_share()
+    if "plain_65536" in checks:
+        c = checks["plain_65536"]
+        d0 = c["inputs"]
+        wi = tuple(d0[k].astype(np.float64) for k in ("wx", "wy", "wz"))
+        t0 = time.perf_counter()
+        h_ref, p_ref = oracle.vndf_sample(wi, d0["ax"], d0["ay"], seed=0, nthreads=threads)
+        dt = time.perf_counter() - t0
+        h = np.stack(c["got"][:3], axis=1).astype(np.float64)
+        herr = float(np.linalg.norm(h - h_ref, axis=1).max())
+        perr = float(np.abs(c["got"][3].astype(np.float64) / p_ref - 1.0).max())
+        errs["plain_65536"] = {"oracle_seconds": round(dt, 3), "oracle_threads": threads,
+                               "max_abs_err_h": herr, "max_rel_err_pdf": perr,
+                               "every_tuple_within_2e-6": herr <= 2e-6 and perr <= 2e-6}
     if "albedo_lut" in checks:
         c = checks["albedo_lut"]
         r = {}
@@ -745,6 +758,27 @@ def main():
     # to 1.5x slower for some 40 ms), which the headline's timed region is
     # kept out of.
     ms_32 = ms_disk = None
+    if "plain" in only:
+        # the plain sampler on its 65,536 isotropic tuples (Philox seed 0):
+        # launch-bound on the GPU; the CPU leg runs the oracle over every
+        # tuple, timed, and compares each output
+        log("timing the plain sampler, 65,536 tuples")
+        d0 = workloads.tuples_small(65536, seed=0)
+        t0_ = {k: torch.from_numpy(v).to(dev) for k, v in d0.items()}
+        outs0 = tuple(torch.empty_like(t0_["wx"]) for _ in range(4))
+
+        def run0():
+            cv.vndf_sample(t0_["wx"], t0_["wy"], t0_["wz"], t0_["ax"], t0_["ay"], seed=0,
+                           method=HEADLINE_METHOD, out=outs0)
+        for _ in range(args.warmup):
+            run0()
+        st0 = launch_stats(run0, 100)
+        run0()
+        torch.cuda.synchronize()
+        out["plain_65536"] = {"tuples": 65536, "method": "cap_f64", "launch_stats": st0,
+                              "gsamples_per_s": round(65536 / st0["median_ms"] / 1e6, 2)}
+        checks["plain_65536"] = {"inputs": d0, "got": [o.cpu().numpy() for o in outs0]}
+        del t0_, outs0
     if "fp32" in only:
         log("timing the cap sampler in FP32 arithmetic")
         ms_32, _ = timed(run(0), args.steps, args.warmup)
