@@ -158,6 +158,25 @@ def test_albedo_argument_errors(lib):
     lib.albedo_batch_plan_destroy(None)  # no-op
 
 
+def test_no_alloc_argument_errors(lib):
+    """albedo_value_and_grad_noalloc validates before it touches a device:
+    its cell limit (64 bytes per cell with gradients, 8 without, in a 16 MiB
+    buffer), partial gradient outputs, and an empty call."""
+    P = ctypes.c_void_p
+    fake = P(0x1000)  # never dereferenced: validation fails first
+    five = [fake] * 5
+    fn = lib.albedo_value_and_grad_noalloc
+    limit_grad, limit_value = (16 << 20) // 64, (16 << 20) // 8
+    assert fn(limit_grad + 1, *five, fake, 0, None, fake, fake, fake, fake, None) == -2
+    assert "at most %d cells" % limit_grad in _err(lib)
+    assert fn(limit_value + 1, *five, fake, 0, None, fake, None, None, None, None) == -2
+    assert "at most %d cells" % limit_value in _err(lib)
+    assert fn(4, *five, fake, 0, None, fake, fake, None, None, None) == -1
+    assert fn(4, *five, fake, 0, None, None, fake, fake, fake, None) == -1
+    assert fn(0, *[None] * 5, None, 0, None, None, None, None, None, None) == 0
+    assert fn(-1, *[None] * 5, None, 0, None, None, None, None, None, None) == -2
+
+
 def test_gradient_helper_argument_errors(lib):
     P = ctypes.c_void_p
     fake, odd = P(0x1000), P(0x1002)
