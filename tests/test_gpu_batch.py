@@ -117,16 +117,20 @@ def test_dynamic_replays_are_bitwise_stable(tiling):
     plan.close()
 
 
-def test_full_batch_every_job():
+@pytest.mark.parametrize("tiling", [None, (256, 16, 8, 1, 1), (512, 64, 8, 0, 1)])
+def test_full_batch_every_job(tiling):
     """4096 uneven jobs (2^10 .. 2^22 samples, the batch workload): value and
     gradients of every job, from the graph replay and from the per-request
-    launches, against the oracle's dual-number gradient."""
+    launches, against the oracle's dual-number gradient.  The tilings give
+    the horizon fix pass block-owned chunks of 256 and 512 threads and
+    wavefront-owned ones."""
     gold = golden("batch")
     j = workloads.batch_jobs(4096, seed=4)
     assert np.array_equal(j["n"], gold["batch_n"])
     t = to_dev({k: v for k, v in j.items() if k != "n"})
-    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True)
-    for mode in ("graph", "per-request"):
+    plan = cv.BatchPlan(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], j["n"], 4, with_grad=True,
+                        tiling=tiling)
+    for mode in (("graph", "per-request") if tiling is None else ("graph",)):
         for o in (plan.albedo, plan.grad_ax, plan.grad_ay, plan.grad_theta_o):
             o.fill_(float("nan"))
         plan.run() if mode == "graph" else plan.run_per_request()
