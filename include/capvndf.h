@@ -422,9 +422,11 @@ int32_t albedo_apply_jacobian(int64_t n, const float* grad_albedo, const float* 
 /*
  * Batched estimation of many jobs with uneven sample counts (forward value
  * A_j(F0_j) plus, with with_grad, dA_j/d alpha_x, dA_j/d alpha_y and
- * dA_j/d theta_o), in one persistent launch plus a fixed-order finishing pass,
- * captured once into a HIP graph and replayed by albedo_batch_run.  Job j uses
- * unit j of tag 3, so its values equal albedo_estimate/backward on that job.
+ * dA_j/d theta_o), in one persistent launch plus a fixed-order finishing pass
+ * (and, with gradients, the horizon fix pass of albedo_estimate_backward
+ * between them), captured once into a HIP graph and replayed by
+ * albedo_batch_run.  Job j uses unit j of tag 3, so its values equal
+ * albedo_estimate/backward on that job.
  *
  * Tiling: block size, pairs of samples per thread per chunk (multiple of 8),
  * resident blocks per compute unit, who owns a chunk -- the whole block
@@ -480,8 +482,8 @@ int32_t albedo_batch_plan_create(int64_t njobs, const float* wox, const float* w
 int32_t albedo_batch_run(capvndf_batch_plan* plan, void* stream);
 
 /* Same jobs and outputs as albedo_batch_run, launched the per-request way:
- * per job one albedo_value_and_grad-style estimate kernel plus its finishing
- * kernel, no graph.  The baseline the batch is measured against.  Errors as
+ * per job one albedo_value_and_grad-style estimate kernel (with gradients
+ * followed by its horizon fix kernel) plus its finishing kernel, no graph.  The baseline the batch is measured against.  Errors as
  * albedo_batch_run, and BAD_SIZE (nothing enqueued) when a job has 2^24 or
  * more chunks of 16384 samples, more than one launch of this path covers. */
 int32_t albedo_batch_run_per_request(capvndf_batch_plan* plan, void* stream);
@@ -490,8 +492,9 @@ int32_t albedo_batch_run_per_request(capvndf_batch_plan* plan, void* stream);
 int32_t albedo_batch_plan_info(const capvndf_batch_plan* plan, capvndf_tiling* tiling,
                                int64_t* nchunks, int64_t* total_samples);
 
-/* Free the plan, its device buffers and its graph (NULL is a no-op).  Call it
- * only when no replay is pending. */
+/* Free the plan, its device buffers and its graph (NULL is a no-op).  It
+ * first waits for the plan's last albedo_batch_run or
+ * albedo_batch_run_per_request to finish (an event recorded by each). */
 void albedo_batch_plan_destroy(capvndf_batch_plan* plan);
 
 /*
