@@ -385,7 +385,15 @@ def albedo_value_and_grad_noalloc(wox, woy, woz, ax, ay, nsamples, seed, f0=None
         a = torch.empty_like(wox)
         g = [torch.empty_like(wox) for _ in range(3)] if with_grad else [None, None, None]
     else:
-        a, g = out[0], list(out[1:])
+        a = out[0]
+        g = list(out[1:4]) if with_grad else []
+        if len(g) != (3 if with_grad else 0):
+            raise ValueError("out must hold albedo and, with gradients, the three gradient tensors")
+        g += [None] * (3 - len(g))
+        for k, x in zip(("albedo", "grad_ax", "grad_ay", "grad_theta_o"), [a] + g):
+            if x is not None:
+                _dev(x, k)
+                _same_len(n, **{k: x})
     rc = lib.albedo_value_and_grad_noalloc(n, _ptr(wox), _ptr(woy), _ptr(woz), _ptr(ax), _ptr(ay),
                                            _ptr(nsamples), seed, _ptr(f0), _ptr(a),
                                            *[_ptr(x) for x in g], _stream(stream))

@@ -93,3 +93,32 @@ def test_no_alloc_size_limit(lib):
     assert b"at most" in lib.capvndf_last_error()
     assert lib.albedo_value_and_grad_noalloc(0, *[None] * 6, 0, None, None, None, None, None,
                                              None) == 0
+
+
+def test_no_alloc_binding_with_given_outputs(lib):
+    """The Python binding with caller-given outputs (nothing allocated per
+    call): values and gradients, then values only, equal to the workspace
+    entry point bit for bit on the same inputs."""
+    g = workloads.lut_grid(5, 7)
+    t = to_dev(g)
+    c = torch.full((35,), 3000, dtype=torch.int64, device="cuda")
+    outs = [torch.empty(35, device="cuda") for _ in range(4)]
+    got = cv.albedo_value_and_grad_noalloc(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], c, 5,
+                                           out=outs)
+    ref = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], c, 5)
+    torch.cuda.synchronize()
+    assert all(x is y for x, y in zip(got, outs))
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    a = torch.empty(35, device="cuda")
+    only = cv.albedo_value_and_grad_noalloc(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], c, 5,
+                                            with_grad=False, out=(a,))
+    torch.cuda.synchronize()
+    assert only[0] is a and only[1:] == (None, None, None)
+    ref_value = cv.albedo_value_and_grad(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], c, 5,
+                                         with_grad=False)[0]
+    torch.cuda.synchronize()
+    assert torch.equal(a, ref_value)
+    with pytest.raises(ValueError):
+        cv.albedo_value_and_grad_noalloc(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], c, 5,
+                                         out=(a,))
