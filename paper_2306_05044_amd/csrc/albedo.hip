@@ -518,7 +518,11 @@ __global__ void k_reset_counter(int32_t* counter) {
 // gradient sums at partial[6 o ..] otherwise.
 //
 // Wavefront o serves owner o: it returns at once if no thread was flagged
-// (most owners), else spreads each flagged thread's pairs over its 64 lanes.
+// (most owners), else spreads each flagged thread's pairs over its 64 lanes,
+// computes only their samples' margins (the forward sweep up to the
+// reflection), queues the flagged samples in LDS in scan order and evaluates
+// them, up to 64 at a time, one per lane: a chunk with hundreds of flagged
+// samples then costs a few double evaluations per wavefront, not hundreds.
 // ---------------------------------------------------------------------------
 constexpr int kFixBlock = 256;
 
@@ -558,26 +562,6 @@ __device__ __forceinline__ Owner owner_of(int64_t o, const int64_t* __restrict__
     return w;
 }
 
-// t64 - t32 of the flagged samples of pair p, added to corr.
-__device__ __forceinline__ void fix_pair(const CellConst& c, float f0, uint64_t n, uint32_t unit,
-                                         uint32_t k0, uint32_t k1, uint64_t p, Comp (&corr)[7]) {
-    const Words w = philox_pair(p, unit, kTagAlbedo, k0, k1);
-    const float uu[4] = {unit24(w.w0), unit24(w.w1), unit24(w.w2), unit24(w.w3)};
-    for (int h = 0; h < 2; ++h) {
-        if (2 * p + h >= n) break;
-        const AdjTerm t = albedo_adj(c, f0, uu[2 * h], uu[2 * h + 1]);
-        if (!(t.margin >= 0.0f)) continue;
-        const AdjTerm d = albedo_adj_f64(c, f0, uu[2 * h], uu[2 * h + 1]);
-        comp_add(corr[0], d.w - t.w);
-        comp_add(corr[1], d.dax - t.dax);
-        comp_add(corr[2], d.day - t.day);
-        comp_add(corr[3], d.dth - t.dth);
-        comp_add(corr[4], d.dwsx - t.dwsx);
-        comp_add(corr[5], d.dwsy - t.dwsy);
-        comp_add(corr[6], d.dzs - t.dzs);
-    }
-}
-
 // The 7 correction sums of one thread as (A, gax, gay, gth), ws chained.
 __device__ __forceinline__ void chain_fix(const CellConst& c, const Comp (&corr)[7],
                                           Comp (&out)[4]) {
@@ -615,11 +599,29 @@ __device__ __forceinline__ void merge_fix(const Comp (&fix)[4], float* __restric
         const int64_t *__restrict__ chunk_pbeg, const int64_t *__restrict__ chunk_pend,        \
         uint32_t k0, uint32_t k1, uint64_t *__restrict__ rec, float *__restrict__ partial
 
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
+    return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Orders one wavefront's LDS accesses across its lanes (the writes before
+// it are seen by the reads after it).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Flagged samples a fix wavefront holds before it evaluates them.
+constexpr int kFixQueue = 64;
+
 template <bool TABLE, bool WITH_VALUE>
 __global__ __launch_bounds__(kFixBlock) void k_horizon_fix(CAPVNDF_FIX_PARAMS) {
+    // per wavefront: the pair index (times 2, plus 1 for the pair's second
+    // sample) of each flagged sample found, in scan order
+    __shared__ uint64_t queue[kFixBlock / 64][kFixQueue];
     const uint32_t lane = threadIdx.x & 63;
-    const int64_t o = (int64_t)blockIdx.x * (kFixBlock / 64) +
-                      __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
+    const int64_t o = (int64_t)blockIdx.x * (kFixBlock / 64) + wv;
     const int32_t nwords = threads >> 6;
     if (o >= nowners) return;  // the same for the whole wavefront
     const Owner w = owner_of<TABLE>(o, nsamp, slots, unit_base, chunk_job, chunk_pbeg, chunk_pend);
@@ -634,26 +636,80 @@ __global__ __launch_bounds__(kFixBlock) void k_horizon_fix(CAPVNDF_FIX_PARAMS) {
     Comp corr[7];
 #pragma unroll
     for (int a = 0; a < 7; ++a) corr[a] = Comp{0.0f, 0.0f};
-    const uint64_t step = (uint64_t)threads * 64;
-    for (int32_t k = 0; k < nwords; ++k) {
-        uint64_t m = rec[o * nwords + k];
-        while (m != 0) {
-            const uint64_t t = (uint64_t)k * 64 + __builtin_ctzll(m);
-            m &= m - 1;
-            if (!c.ok) continue;
-            if (TABLE) {
-                const uint64_t npairs = (n + 1) / 2;
-                for (int64_t ch = w.slot; ch < w.nch; ch += slots) {
-                    const uint64_t b = (uint64_t)ch * kLutChunkPairs;
-                    const uint64_t e = std::min(b + kLutChunkPairs, npairs);
-                    for (uint64_t p = b + t + (uint64_t)lane * threads; p < e; p += step)
-                        fix_pair(c, f0, n, w.unit, k0, k1, p, corr);
+    uint64_t* q = queue[wv];
+    uint32_t qn = 0;  // queued samples, the same in every lane
+
+    // Evaluates the queued samples, one per lane, in FP32 and in double, and
+    // adds t64 - t32 to the lane's sums.
+    auto flush = [&]() {
+        wave_sync();
+        if (lane < qn) {
+            const uint64_t e = q[lane];
+            const uint64_t p = e >> 1;
+            const Words ww = philox_pair(p, w.unit, kTagAlbedo, k0, k1);
+            const bool second = (e & 1ull) != 0;
+            const float u1 = unit24(second ? ww.w2 : ww.w0);
+            const float u2 = unit24(second ? ww.w3 : ww.w1);
+            const AdjTerm t = albedo_adj(c, f0, u1, u2);
+            const AdjTerm d = albedo_adj_f64(c, f0, u1, u2);
+            comp_add(corr[0], d.w - t.w);
+            comp_add(corr[1], d.dax - t.dax);
+            comp_add(corr[2], d.day - t.day);
+            comp_add(corr[3], d.dth - t.dth);
+            comp_add(corr[4], d.dwsx - t.dwsx);
+            comp_add(corr[5], d.dwsy - t.dwsy);
+            comp_add(corr[6], d.dzs - t.dzs);
+        }
+        wave_sync();
+        qn = 0;
+    };
+    // Queues the lanes whose sample has margin >= 0; code = 2 p + h.
+    auto note = [&](float margin, uint64_t code) {
+        const uint64_t b = __ballot(margin >= 0.0f);
+        const uint32_t nb = (uint32_t)__popcll(b);
+        if (nb == 0) return;
+        if (qn + nb > (uint32_t)kFixQueue) flush();
+        if (margin >= 0.0f) q[qn + lanes_below(b, lane)] = code;
+        qn += nb;
+    };
+    // The margins of the samples of pair p (valid: p is a pair of the owner),
+    // the same arithmetic as the sample loops.
+    auto scan = [&](uint64_t p, bool valid) {
+        float m0 = -1.0f, m1 = -1.0f;
+        if (valid) {
+            const Words ww = philox_pair(p, w.unit, kTagAlbedo, k0, k1);
+            m0 = reflect_sample(c, unit24(ww.w0), unit24(ww.w1)).margin;
+            if (2 * p + 1 < n) m1 = reflect_sample(c, unit24(ww.w2), unit24(ww.w3)).margin;
+        }
+        note(m0, p << 1);
+        note(m1, (p << 1) | 1ull);
+    };
+    // thread t of the owner took pairs b + t + s * threads of range [b, e):
+    // lane l scans s = l, l + 64, ... (the loop is the same for all lanes)
+    auto range = [&](uint64_t b, uint64_t e, uint64_t t) {
+        for (uint64_t s0 = 0; b + t + s0 * (uint64_t)threads < e; s0 += 64) {
+            const uint64_t p = b + t + (s0 + lane) * (uint64_t)threads;
+            scan(p, p < e);
+        }
+    };
+    if (c.ok) {
+        for (int32_t k = 0; k < nwords; ++k) {
+            uint64_t m = rec[o * nwords + k];
+            while (m != 0) {
+                const uint64_t t = (uint64_t)k * 64 + __builtin_ctzll(m);
+                m &= m - 1;
+                if (TABLE) {
+                    const uint64_t npairs = (n + 1) / 2;
+                    for (int64_t ch = w.slot; ch < w.nch; ch += slots) {
+                        const uint64_t b = (uint64_t)ch * kLutChunkPairs;
+                        range(b, std::min(b + kLutChunkPairs, npairs), t);
+                    }
+                } else {
+                    range(w.pbeg, w.pend, t);
                 }
-            } else {
-                for (uint64_t p = w.pbeg + t + (uint64_t)lane * threads; p < w.pend; p += step)
-                    fix_pair(c, f0, n, w.unit, k0, k1, p, corr);
             }
         }
+        if (qn != 0) flush();
     }
     Comp fix[4];
     chain_fix(c, corr, fix);

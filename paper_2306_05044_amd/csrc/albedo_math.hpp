@@ -281,32 +281,52 @@ __device__ __attribute__((noinline)) AdjTerm albedo_adj_f64(const CellConst& c, 
     return r;
 }
 
-__device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, float u1, float u2) {
+// The adjoint's forward sweep up to the reflected direction (as albedo_fwd,
+// keeping the intermediates), and the sample's horizon margin: kappa =
+// max(1, ax, ay) iL and band = (44 + 192 kappa) 2^-24; flagged (margin >= 0)
+// if |wl_z| <= band or kappa >= kIllConditioned, i.e. band >= kBandIll.
+struct Reflected {
+    float a, hsz, s2, ist, st, sp, cp, hsx, hsy, iL, hx, hy, hz, x, x2, wlx, wly, wlz, margin;
+    bool apex;
+};
+
+__device__ __forceinline__ Reflected reflect_sample(const CellConst& c, float u1, float u2) {
     const Stretched& s = c.s;
-    // forward sweep (as albedo_fwd, keeping the intermediates)
-    const float a = 1.0f - u2;
-    const float hsz = a * s.opz;
-    const float s2 = u2 * s.opz * (hsz + s.omz);
+    Reflected r;
+    r.a = 1.0f - u2;
+    r.hsz = r.a * s.opz;
+    r.s2 = u2 * s.opz * (r.hsz + s.omz);
     // sin(theta_c) = s2 / sqrt(s2), keeping 1 / sin(theta_c) for the reverse
     // sweep; s2 == 0 only at the apex (u2 == 0), where both are taken as 0
-    const bool apex = !(s2 > 0.0f);
-    const float ist = rsq(s2);
-    const float st = apex ? 0.0f : s2 * ist;
-    float sp, cp;
-    sincos_turns(u1, &sp, &cp);
-    const float hsx = __builtin_fmaf(st, cp, s.wsx);
-    const float hsy = __builtin_fmaf(st, sp, s.wsy);
-    const float vx = c.ax * hsx, vy = c.ay * hsy, vz = hsz;
-    const float iL = rsq(__builtin_fmaf(vx, vx, __builtin_fmaf(vy, vy, vz * vz)));
-    const float hx = vx * iL, hy = vy * iL, hz = vz * iL;
-    const float x = __builtin_fmaf(c.ox, hx, __builtin_fmaf(c.oy, hy, c.oz * hz));
-    const float x2 = x + x;
-    const float wlx = __builtin_fmaf(x2, hx, -c.ox);
-    const float wly = __builtin_fmaf(x2, hy, -c.oy);
-    const float wlz = __builtin_fmaf(x2, hz, -c.oz);
-    // kappa = max(1, ax, ay) iL and band = (44 + 192 kappa) 2^-24: flagged if
-    // |wl_z| <= band or kappa >= kIllConditioned, i.e. band >= kBandIll
-    const float margin = __builtin_fmaf(c.b1, iL, kBandC0) - fminf(fabsf(wlz), kBandIll);
+    r.apex = !(r.s2 > 0.0f);
+    r.ist = rsq(r.s2);
+    r.st = r.apex ? 0.0f : r.s2 * r.ist;
+    sincos_turns(u1, &r.sp, &r.cp);
+    r.hsx = __builtin_fmaf(r.st, r.cp, s.wsx);
+    r.hsy = __builtin_fmaf(r.st, r.sp, s.wsy);
+    const float vx = c.ax * r.hsx, vy = c.ay * r.hsy, vz = r.hsz;
+    r.iL = rsq(__builtin_fmaf(vx, vx, __builtin_fmaf(vy, vy, vz * vz)));
+    r.hx = vx * r.iL;
+    r.hy = vy * r.iL;
+    r.hz = vz * r.iL;
+    r.x = __builtin_fmaf(c.ox, r.hx, __builtin_fmaf(c.oy, r.hy, c.oz * r.hz));
+    r.x2 = r.x + r.x;
+    r.wlx = __builtin_fmaf(r.x2, r.hx, -c.ox);
+    r.wly = __builtin_fmaf(r.x2, r.hy, -c.oy);
+    r.wlz = __builtin_fmaf(r.x2, r.hz, -c.oz);
+    r.margin = __builtin_fmaf(c.b1, r.iL, kBandC0) - fminf(fabsf(r.wlz), kBandIll);
+    return r;
+}
+
+__device__ __forceinline__ AdjTerm albedo_adj(const CellConst& c, float f0, float u1, float u2) {
+    const Stretched& s = c.s;
+    // forward sweep
+    const Reflected rf = reflect_sample(c, u1, u2);
+    const float a = rf.a, hsz = rf.hsz, ist = rf.ist, sp = rf.sp, cp = rf.cp;
+    const float hsx = rf.hsx, hsy = rf.hsy, iL = rf.iL, hx = rf.hx, hy = rf.hy, hz = rf.hz;
+    const float x = rf.x, x2 = rf.x2, wlx = rf.wlx, wly = rf.wly, wlz = rf.wlz;
+    const bool apex = rf.apex;
+    const float margin = rf.margin;
     const float plx = c.ax * wlx, ply = c.ay * wly;
     const float pp = __builtin_fmaf(plx, plx, ply * ply);
     const float m2 = __builtin_fmaf(wlz, wlz, pp);
