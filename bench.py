@@ -639,14 +639,16 @@ def summarize_valu(d, cmds, prof, batch_samples):
             rows.append((key, k, desc + " (64x64 cells x 2^20)", lut,
                          [x for x in a[k] if x["grid"] == lut_grid]))
     # the horizon fix passes after the table's adjoint kernels (a wavefront
-    # per slot: 65536 blocks of 256 work-items)
-    for pre, key, desc in (("k_horizon_fix<true, false>", "fix_backward", "horizon fix after backward"),
-                           ("k_horizon_fix<true, true>", "fix_value_and_grad",
+    # per 8 slots: 4096 x 8 blocks of 64 work-items)
+    fix_grid = 4096 * 8 * 64
+    for pre, key, desc in (("k_horizon_fix_table<false>", "fix_backward",
+                            "horizon fix after backward"),
+                           ("k_horizon_fix_table<true>", "fix_value_and_grad",
                             "horizon fix after value + Jacobian")):
         k = _kernel(a, pre)
         if k:
             rows.append((key, k, desc + " (per table sample)", lut,
-                         [x for x in a[k] if x["grid"] == lut_grid // 4]))
+                         [x for x in a[k] if x["grid"] == fix_grid]))
     for m, name in ((0, "cap"), (1, "disk"), (2, "cap in double precision")):
         k = _kernel(a, f"k_microbench<{m}>")
         if k:
@@ -668,7 +670,7 @@ def summarize_valu(d, cmds, prof, batch_samples):
         if k.startswith("k_batch"):
             rows.append((f"batch:{k}", k, "batch forward + adjoint, 4096 jobs", batch_samples,
                          b[k]))
-        elif k.startswith("k_horizon_fix<false"):
+        elif k.startswith("k_horizon_fix_batch"):
             rows.append((f"batch:{k}", k, "batch horizon fix (per batch sample)", batch_samples,
                          b[k]))
     rec = {"source_digest": _valu_digest(), "valu_lane_instr_per_sample": {},

@@ -131,7 +131,7 @@ __device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uin
 // is too poor for FP32 (a few in 10^5).  The adjoint loops keep per lane the
 // largest margin of its samples; the owner of each partial (a table slot's
 // block, a batch chunk's block or wavefront) then stores one 64-bit mask of
-// its flagged lanes per wavefront, its record.  k_horizon_fix walks the
+// its flagged lanes per wavefront, its record.  The fix pass walks the
 // pairs of the flagged lanes again, evaluates their flagged samples in
 // double precision and adds t64 - t32 to the owner's partial in a fixed
 // order.  The sample loops so carry one float and hold no call: a call
@@ -505,77 +505,31 @@ __global__ void k_reset_counter(int32_t* counter) {
 
 // ---------------------------------------------------------------------------
 // Horizon fix pass: runs between an adjoint kernel and the finishing pass.
-// Owners have `threads` threads (64, 256 or 512) and records of threads / 64
-// words.  Owner o is table block o (cell o / slots, slot o % slots, the
-// cell's chunks slot, slot + slots, ...; unit unit_base + cell) when TABLE,
-// else batch chunk o (job chunk_job[o], pairs [chunk_pbeg[o],
-// chunk_pend[o]); unit = job).  Owner thread t took the pairs
-// pbeg + t + s * threads of each of its ranges.  For each flagged sample of
-// a flagged thread's pairs the pass adds t64 - t32 (albedo_adj_f64 minus
-// albedo_adj) to compensated sums, chains the ws adjoint as the sample loops
-// do, reduces in a fixed tree and merges the result into the owner's
-// partial: (A, gax, gay, gth) at partial[8 o ..] if WITH_VALUE, the three
-// gradient sums at partial[6 o ..] otherwise.
+// An owner (a table block: cell, slot; or a batch chunk) has `threads`
+// threads and a record of threads / 64 words, bit t set when thread t met a
+// sample with margin >= 0.  For each such sample of a flagged thread's pairs
+// the pass adds t64 - t32 (albedo_adj_f64 minus albedo_adj), the ws adjoint
+// chained as the sample loops do, and merges the sums into the owner's
+// partial in a fixed order: (A, gax, gay, gth) at partial[8 o ..] if
+// WITH_VALUE, the three gradient sums at partial[6 o ..] otherwise.
 //
-// Wavefront o serves owner o: it returns at once if no thread was flagged
-// (most owners), else spreads each flagged thread's pairs over its 64 lanes,
+// A wavefront reads its owners' records at once and returns if nothing was
+// flagged.  Else it spreads flagged threads' pairs over its lanes and
 // computes only their samples' margins (the forward sweep up to the
-// reflection), queues the flagged samples in LDS in scan order and evaluates
-// them, up to 64 at a time, one per lane: a chunk with hundreds of flagged
-// samples then costs a few double evaluations per wavefront, not hundreds.
+// reflection), two pairs per lane from two flagged threads, so that each
+// lane runs two independent chains (one chain per lane left the scan bound
+// by latency at about three wavefronts per SIMD).  The flagged samples go
+// to a queue in LDS, which is evaluated one sample per lane: a chunk with
+// hundreds of flagged samples costs a few double evaluations per wavefront,
+// not hundreds.
+//
+// One wavefront per block: the block scheduler deals consecutive blocks to
+// the 8 XCDs in turn, so the groups of one cell (or neighbouring chunks of
+// one job) spread over all of them; with 4-wavefront blocks a cell's groups
+// shared an XCD and the XCDs holding the smoothest, most grazing cells ran
+// about twice as long as the others.
 // ---------------------------------------------------------------------------
-constexpr int kFixBlock = 256;
-
-// The owner's cell or job and its pair ranges.
-struct Owner {
-    int64_t u;            // cell or job index
-    uint32_t unit;        // Philox unit
-    int64_t slot, nch;    // TABLE: the slot and the cell's chunk count
-    uint64_t pbeg, pend;  // batch: the chunk's pairs
-    bool live;            // false for a table slot past the cell's chunks (no record)
-};
-
-template <bool TABLE>
-__device__ __forceinline__ Owner owner_of(int64_t o, const int64_t* __restrict__ nsamp,
-                                          int32_t slots, uint32_t unit_base,
-                                          const int32_t* __restrict__ chunk_job,
-                                          const int64_t* __restrict__ chunk_pbeg,
-                                          const int64_t* __restrict__ chunk_pend) {
-    Owner w;
-    w.slot = 0;
-    w.nch = 1;
-    w.pbeg = 0;
-    w.pend = 0;
-    if (TABLE) {
-        w.u = o / slots;
-        w.slot = o - w.u * slots;
-        w.nch = cell_chunks(nsamp[w.u]);
-        w.live = w.slot < w.nch;
-        w.unit = unit_base + (uint32_t)w.u;
-    } else {
-        w.u = chunk_job[o];
-        w.pbeg = (uint64_t)chunk_pbeg[o];
-        w.pend = (uint64_t)chunk_pend[o];
-        w.live = true;
-        w.unit = (uint32_t)w.u;
-    }
-    return w;
-}
-
-// The 7 correction sums of one thread as (A, gax, gay, gth), ws chained.
-__device__ __forceinline__ void chain_fix(const CellConst& c, const Comp (&corr)[7],
-                                          Comp (&out)[4]) {
-    float gax = corr[1].s + corr[1].c;
-    float gay = corr[2].s + corr[2].c;
-    float gth = corr[3].s + corr[3].c;
-    if (c.ok)
-        ws_chain(c, corr[4].s + corr[4].c, corr[5].s + corr[5].c, corr[6].s + corr[6].c, gax,
-                 gay, gth);
-    out[0] = corr[0];
-    out[1] = Comp{gax, 0.0f};
-    out[2] = Comp{gay, 0.0f};
-    out[3] = Comp{gth, 0.0f};
-}
+constexpr int kFixBlock = 64;
 
 template <bool WITH_VALUE>
 __device__ __forceinline__ void merge_fix(const Comp (&fix)[4], float* __restrict__ partial,
@@ -590,15 +544,6 @@ __device__ __forceinline__ void merge_fix(const Comp (&fix)[4], float* __restric
     }
 }
 
-#define CAPVNDF_FIX_PARAMS                                                                     \
-    int64_t nowners, int32_t threads, const float *__restrict__ wox,                           \
-        const float *__restrict__ woy, const float *__restrict__ woz,                          \
-        const float *__restrict__ ax, const float *__restrict__ ay,                            \
-        const float *__restrict__ f0p, const int64_t *__restrict__ nsamp, int32_t slots,      \
-        uint32_t unit_base, const int32_t *__restrict__ chunk_job,                             \
-        const int64_t *__restrict__ chunk_pbeg, const int64_t *__restrict__ chunk_pend,        \
-        uint32_t k0, uint32_t k1, uint64_t *__restrict__ rec, float *__restrict__ partial
-
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask, uint32_t lane) {
     return (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
 }
@@ -611,130 +556,330 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Flagged samples a fix wavefront holds before it evaluates them.
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int32_t src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The margins of pair p's two samples, the same arithmetic as the sample
+// loops; -1 for a pair outside the owner (valid false) and for a second
+// sample past the count n.  No branch: the two chains of a scan step stay
+// in one basic block.
+__device__ __forceinline__ void pair_margins(const CellConst& c, uint64_t p, bool valid,
+                                             uint64_t n, uint32_t unit, uint32_t k0,
+                                             uint32_t k1, float& m0, float& m1) {
+    const Words ww = philox_pair(p, unit, kTagAlbedo, k0, k1);
+    const float a = reflect_sample(c, unit24(ww.w0), unit24(ww.w1)).margin;
+    const float b = reflect_sample(c, unit24(ww.w2), unit24(ww.w3)).margin;
+    m0 = valid ? a : -1.0f;
+    m1 = valid && 2 * p + 1 < n ? b : -1.0f;
+}
+
+// t64 - t32 of one flagged sample (code 2 p + h: pair p, its second sample
+// when h = 1) as (A, gax, gay, gth), the ws adjoint chained.
+__device__ __forceinline__ void sample_fix(const CellConst& c, float f0, uint64_t code,
+                                           uint32_t unit, uint32_t k0, uint32_t k1,
+                                           float (&v)[4]) {
+    const Words ww = philox_pair(code >> 1, unit, kTagAlbedo, k0, k1);
+    const bool second = (code & 1ull) != 0;
+    const float u1 = unit24(second ? ww.w2 : ww.w0);
+    const float u2 = unit24(second ? ww.w3 : ww.w1);
+    const AdjTerm t = albedo_adj(c, f0, u1, u2);
+    const AdjTerm d = albedo_adj_f64(c, f0, u1, u2);
+    v[0] = d.w - t.w;
+    v[1] = d.dax - t.dax;
+    v[2] = d.day - t.day;
+    v[3] = d.dth - t.dth;
+    ws_chain(c, d.dwsx - t.dwsx, d.dwsy - t.dwsy, d.dzs - t.dzs, v[1], v[2], v[3]);
+}
+
+// The batch's fix pass: wavefront o serves chunk o (job chunk_job[o], pairs
+// [chunk_pbeg[o], chunk_pend[o]), unit = job), whose thread t took the pairs
+// pbeg + t + s * threads.  Lane k < threads / 64 loads record word k; the
+// flagged threads are taken two at a time in thread order, lane l scanning
+// pair s = s0 + l of both.  Each lane adds its samples' fixes to compensated
+// sums, which are reduced in a fixed tree and merged into the chunk's
+// partial (value and gradients).
 constexpr int kFixQueue = 64;
 
-template <bool TABLE, bool WITH_VALUE>
-__global__ __launch_bounds__(kFixBlock) void k_horizon_fix(CAPVNDF_FIX_PARAMS) {
-    // per wavefront: the pair index (times 2, plus 1 for the pair's second
-    // sample) of each flagged sample found, in scan order
-    __shared__ uint64_t queue[kFixBlock / 64][kFixQueue];
+__global__ __launch_bounds__(kFixBlock) void k_horizon_fix_batch(
+    int64_t nchunks, int32_t threads, const float* __restrict__ wox,
+    const float* __restrict__ woy, const float* __restrict__ woz, const float* __restrict__ ax,
+    const float* __restrict__ ay, const float* __restrict__ f0p,
+    const int64_t* __restrict__ nsamp, const int32_t* __restrict__ chunk_job,
+    const int64_t* __restrict__ chunk_pbeg, const int64_t* __restrict__ chunk_pend, uint32_t k0,
+    uint32_t k1, const uint64_t* __restrict__ rec, float* __restrict__ partial) {
+    // the code (2 p + h) of each flagged sample found, in scan order
+    __shared__ uint64_t queue[kFixQueue];
     const uint32_t lane = threadIdx.x & 63;
-    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));
-    const int64_t o = (int64_t)blockIdx.x * (kFixBlock / 64) + wv;
+    const int64_t o = blockIdx.x;
+    if (o >= nchunks) return;
     const int32_t nwords = threads >> 6;
-    if (o >= nowners) return;  // the same for the whole wavefront
-    const Owner w = owner_of<TABLE>(o, nsamp, slots, unit_base, chunk_job, chunk_pbeg, chunk_pend);
-    if (!w.live) return;
-    int32_t flagged = 0;
-    for (int32_t k = 0; k < nwords; ++k) flagged += __popcll(rec[o * nwords + k]);
-    if (flagged == 0) return;
-    const int64_t u = w.u;
+    const uint64_t wd = (int32_t)lane < nwords ? rec[o * nwords + lane] : 0ull;
+    uint64_t words = __ballot(wd != 0);
+    if (words == 0) return;  // most chunks
+    const int32_t u = chunk_job[o];
     const CellConst c = cell_setup(wox[u], woy[u], woz[u], ax[u], ay[u]);
+    if (!c.ok) return;  // no samples were taken
     const float f0 = f0p ? f0p[u] : 1.0f;
     const uint64_t n = (uint64_t)nsamp[u];
-    Comp corr[7];
+    const uint64_t pbeg = (uint64_t)chunk_pbeg[o], pend = (uint64_t)chunk_pend[o];
+    const uint32_t unit = (uint32_t)u;
+    Comp corr[4];
 #pragma unroll
-    for (int a = 0; a < 7; ++a) corr[a] = Comp{0.0f, 0.0f};
-    uint64_t* q = queue[wv];
+    for (int a = 0; a < 4; ++a) corr[a] = Comp{0.0f, 0.0f};
     uint32_t qn = 0;  // queued samples, the same in every lane
 
-    // Evaluates the queued samples, one per lane, in FP32 and in double, and
-    // adds t64 - t32 to the lane's sums.
     auto flush = [&]() {
         wave_sync();
         if (lane < qn) {
-            const uint64_t e = q[lane];
-            const uint64_t p = e >> 1;
-            const Words ww = philox_pair(p, w.unit, kTagAlbedo, k0, k1);
-            const bool second = (e & 1ull) != 0;
-            const float u1 = unit24(second ? ww.w2 : ww.w0);
-            const float u2 = unit24(second ? ww.w3 : ww.w1);
-            const AdjTerm t = albedo_adj(c, f0, u1, u2);
-            const AdjTerm d = albedo_adj_f64(c, f0, u1, u2);
-            comp_add(corr[0], d.w - t.w);
-            comp_add(corr[1], d.dax - t.dax);
-            comp_add(corr[2], d.day - t.day);
-            comp_add(corr[3], d.dth - t.dth);
-            comp_add(corr[4], d.dwsx - t.dwsx);
-            comp_add(corr[5], d.dwsy - t.dwsy);
-            comp_add(corr[6], d.dzs - t.dzs);
+            float v[4];
+            sample_fix(c, f0, queue[lane], unit, k0, k1, v);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) comp_add(corr[a], v[a]);
         }
         wave_sync();
         qn = 0;
     };
-    // Queues the lanes whose sample has margin >= 0; code = 2 p + h.
+    // queues the lanes whose sample has margin >= 0
     auto note = [&](float margin, uint64_t code) {
         const uint64_t b = __ballot(margin >= 0.0f);
         const uint32_t nb = (uint32_t)__popcll(b);
         if (nb == 0) return;
         if (qn + nb > (uint32_t)kFixQueue) flush();
-        if (margin >= 0.0f) q[qn + lanes_below(b, lane)] = code;
+        if (margin >= 0.0f) queue[qn + lanes_below(b, lane)] = code;
         qn += nb;
     };
-    // The margins of the samples of pair p (valid: p is a pair of the owner),
-    // the same arithmetic as the sample loops.
-    auto scan = [&](uint64_t p, bool valid) {
-        float m0 = -1.0f, m1 = -1.0f;
-        if (valid) {
-            const Words ww = philox_pair(p, w.unit, kTagAlbedo, k0, k1);
-            m0 = reflect_sample(c, unit24(ww.w0), unit24(ww.w1)).margin;
-            if (2 * p + 1 < n) m1 = reflect_sample(c, unit24(ww.w2), unit24(ww.w3)).margin;
+    // next flagged thread in thread order; false when none is left
+    uint64_t m = 0;
+    int32_t wi = 0;
+    auto next = [&](uint32_t& t) -> bool {
+        while (m == 0) {
+            if (words == 0) return false;
+            wi = __builtin_ctzll(words);
+            words &= words - 1;
+            m = shfl64(wd, wi);
         }
-        note(m0, p << 1);
-        note(m1, (p << 1) | 1ull);
+        t = (uint32_t)wi * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        return true;
     };
-    // thread t of the owner took pairs b + t + s * threads of range [b, e):
-    // lane l scans s = l, l + 64, ... (the loop is the same for all lanes)
-    auto range = [&](uint64_t b, uint64_t e, uint64_t t) {
-        for (uint64_t s0 = 0; b + t + s0 * (uint64_t)threads < e; s0 += 64) {
-            const uint64_t p = b + t + (s0 + lane) * (uint64_t)threads;
-            scan(p, p < e);
+
+    uint32_t ta, tb;
+    while (next(ta)) {
+        const bool two = next(tb);
+        if (!two) tb = ta;
+        // ta < tb: thread ta has at least as many pairs as tb
+        for (uint64_t s0 = 0; pbeg + ta + s0 * (uint64_t)threads < pend; s0 += 64) {
+            const uint64_t pa = pbeg + ta + (s0 + lane) * (uint64_t)threads;
+            const uint64_t pb = pbeg + tb + (s0 + lane) * (uint64_t)threads;
+            float a0, a1, b0, b1;
+            pair_margins(c, pa, pa < pend, n, unit, k0, k1, a0, a1);
+            pair_margins(c, pb, two && pb < pend, n, unit, k0, k1, b0, b1);
+            note(a0, pa << 1);
+            note(a1, (pa << 1) | 1ull);
+            note(b0, pb << 1);
+            note(b1, (pb << 1) | 1ull);
         }
+    }
+    if (qn != 0) flush();
+#pragma unroll
+    for (int a = 0; a < 4; ++a) corr[a] = wave_reduce(corr[a]);
+    if (lane == 0) merge_fix<true>(corr, partial, o);
+}
+
+// The table's fix pass.  Wavefront w serves a group of kFixGroup owners of
+// one cell (cell u = w / groups, slots g * kFixGroup + j, groups =
+// ceil(slots / kFixGroup)); they share the cell's constants and Philox
+// unit.  Lane l < 4 kFixGroup loads word l % 4 of owner l / 4 (one
+// coalesced read), so a ballot of the nonzero words lists the flagged
+// threads in owner order.  A thread holds kLutPairsPerThread = 32 pairs of
+// each chunk, so a scan step gives one flagged thread half a wavefront and
+// takes four (two per lane) when each slot holds one chunk; a slot of
+// several chunks is scanned chunk by chunk, one thread per half wavefront,
+// and a second owner joins only when it has one chunk.  The flagged samples
+// are queued with their slot in owner order, so that each owner's entries
+// are contiguous.  A queue of up to 2 x 64 samples is evaluated one sample
+// per lane per round, each fix placed in LDS, and the lane that holds the
+// first entry of an owner's run sums the run in queue order and merges it
+// into that owner's partial (an owner whose run spans two queues is merged
+// twice, in queue order).  Eight owners per wavefront measured best: a
+// cell holds up to about 500 flagged samples (grazing views of smooth
+// surfaces, 2^20 samples), so 16 owners per wavefront leaves a long tail,
+// and fewer owners per wavefront repeat the set-up more often.
+constexpr int kFixGroup = 8;
+constexpr int kFixTableQueue = 128;
+static_assert(kLutPairsPerThread == 32, "a scan step gives each flagged thread 32 lanes");
+static_assert(kFixGroup * (kLutBlock / 64) <= 64, "a group's records fit one wavefront");
+
+template <bool WITH_VALUE>
+__global__ __launch_bounds__(kFixBlock) void k_horizon_fix_table(
+    int64_t ncells, const float* __restrict__ wox, const float* __restrict__ woy,
+    const float* __restrict__ woz, const float* __restrict__ ax, const float* __restrict__ ay,
+    const float* __restrict__ f0p, const int64_t* __restrict__ nsamp, int32_t slots,
+    uint32_t unit_base, uint32_t k0, uint32_t k1, const uint64_t* __restrict__ rec,
+    float* __restrict__ partial) {
+    constexpr int nwords = kLutBlock / 64;
+    __shared__ uint64_t q[kFixTableQueue];
+    __shared__ int32_t qs[kFixTableQueue];
+    __shared__ float qf[4][kFixTableQueue];
+    const uint32_t lane = threadIdx.x & 63;
+    const int64_t groups = (slots + kFixGroup - 1) / kFixGroup;
+    const int64_t w = blockIdx.x;
+    if (w >= ncells * groups) return;
+    const int64_t u = w / groups;
+    const int32_t s0 = (int32_t)(w - u * groups) * kFixGroup;
+    const uint64_t n = (uint64_t)nsamp[u];
+    const int64_t nch = cell_chunks((int64_t)n);
+    const int64_t live = std::min<int64_t>(slots, nch);
+    const int32_t my_slot = s0 + (int32_t)(lane / nwords);
+    const uint64_t wd = lane < kFixGroup * nwords && my_slot < live
+                            ? rec[(u * slots + my_slot) * nwords + lane % nwords]
+                            : 0ull;
+    uint64_t words = __ballot(wd != 0);
+    if (words == 0) return;
+    const CellConst c = cell_setup(wox[u], woy[u], woz[u], ax[u], ay[u]);
+    if (!c.ok) return;  // no samples were taken
+    const float f0 = f0p ? f0p[u] : 1.0f;
+    const uint32_t unit = unit_base + (uint32_t)u;
+    const uint64_t npairs = (n + 1) / 2;
+    uint32_t qn = 0;  // the same in every lane
+
+    auto flush = [&]() {
+        wave_sync();
+        for (uint32_t base = 0; base < qn; base += 64) {
+            const uint32_t i = base + lane;
+            float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (i < qn) sample_fix(c, f0, q[i], unit, k0, k1, v);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) qf[a][i] = v[a];
+        }
+        wave_sync();
+        for (uint32_t i = lane; i < qn; i += 64) {
+            const int32_t s = qs[i];
+            if (i != 0 && qs[i - 1] == s) continue;  // not the head of its run
+            Comp f[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) f[a] = Comp{0.0f, 0.0f};
+            for (uint32_t j = i; j < qn && qs[j] == s; ++j) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) comp_add(f[a], qf[a][j]);
+            }
+            merge_fix<WITH_VALUE>(f, partial, u * slots + s);
+        }
+        wave_sync();
+        qn = 0;
     };
-    if (c.ok) {
-        for (int32_t k = 0; k < nwords; ++k) {
-            uint64_t m = rec[o * nwords + k];
-            while (m != 0) {
-                const uint64_t t = (uint64_t)k * 64 + __builtin_ctzll(m);
-                m &= m - 1;
-                if (TABLE) {
-                    const uint64_t npairs = (n + 1) / 2;
-                    for (int64_t ch = w.slot; ch < w.nch; ch += slots) {
-                        const uint64_t b = (uint64_t)ch * kLutChunkPairs;
-                        range(b, std::min(b + kLutChunkPairs, npairs), t);
-                    }
-                } else {
-                    range(w.pbeg, w.pend, t);
+    // queues the lane's flagged samples of pair p (slot s) in lane order
+    auto push = [&](float m0, float m1, uint64_t p, int32_t s) {
+        const bool g0 = m0 >= 0.0f, g1 = m1 >= 0.0f;
+        const uint64_t b0 = __ballot(g0), b1 = __ballot(g1);
+        const uint32_t nb = (uint32_t)(__popcll(b0) + __popcll(b1));
+        if (nb == 0) return;
+        if (qn + nb > (uint32_t)kFixTableQueue) flush();
+        const uint32_t at = qn + lanes_below(b0, lane) + lanes_below(b1, lane);
+        if (g0) {
+            q[at] = p << 1;
+            qs[at] = s;
+        }
+        if (g1) {
+            q[at + (g0 ? 1 : 0)] = (p << 1) | 1ull;
+            qs[at + (g0 ? 1 : 0)] = s;
+        }
+        qn += nb;
+    };
+    // next flagged (slot, thread) of the group in owner order; false when none
+    uint64_t m = 0;
+    int32_t wi = 0;
+    auto next = [&](int32_t& s, uint32_t& t) -> bool {
+        while (m == 0) {
+            if (words == 0) return false;
+            wi = __builtin_ctzll(words);
+            words &= words - 1;
+            m = shfl64(wd, wi);
+        }
+        s = s0 + wi / nwords;
+        t = (uint32_t)(wi % nwords) * 64 + (uint32_t)__builtin_ctzll(m);
+        m &= m - 1;
+        return true;
+    };
+    // lane k of a half wavefront takes pair k of its thread's chunk ch
+    const uint32_t half = lane >> 5, k = lane & 31;
+    auto chunk_pair = [&](int64_t ch, uint32_t t, bool& valid) -> uint64_t {
+        const uint64_t b = (uint64_t)ch * kLutChunkPairs;
+        const uint64_t p = b + t + (uint64_t)k * kLutBlock;
+        valid = valid && p < std::min(b + kLutChunkPairs, npairs);
+        return p;
+    };
+
+    int32_t sa, sb;
+    uint32_t ta, tb;
+    bool more = next(sa, ta);
+    while (more) {
+        // chunks s, s + slots, ... of the cell belong to slot s; the count
+        // does not grow with s, so once it is 1 it stays 1
+        const int64_t rounds = (nch - sa + slots - 1) / slots;
+        if (rounds == 1) {
+            // up to four threads: lanes 0-31 take the first and third,
+            // lanes 32-63 the second and fourth (queued in that order)
+            int32_t s1 = sa, s2 = sa, s3 = sa;
+            uint32_t t1 = ta, t2 = ta, t3 = ta;
+            int32_t ni = 1;
+            if (next(s1, t1)) {
+                ni = 2;
+                if (next(s2, t2)) {
+                    ni = 3;
+                    if (next(s3, t3)) ni = 4;
                 }
             }
+            const int32_t sx = half ? s1 : sa, sy = half ? s3 : s2;
+            const uint32_t tx = half ? t1 : ta, ty = half ? t3 : t2;
+            bool vx = half == 0 || ni >= 2, vy = half ? ni >= 4 : ni >= 3;
+            const uint64_t px = chunk_pair(sx, tx, vx);
+            const uint64_t py = chunk_pair(sy, ty, vy);
+            float x0, x1, y0, y1;
+            pair_margins(c, px, vx, n, unit, k0, k1, x0, x1);
+            pair_margins(c, py, vy, n, unit, k0, k1, y0, y1);
+            push(x0, x1, px, sx);
+            push(y0, y1, py, sy);
+            more = next(sa, ta);
+            continue;
         }
-        if (qn != 0) flush();
+        bool two = next(sb, tb);
+        // a second owner joins only when it holds one chunk, else its
+        // entries would interleave with the first's
+        const bool carry = two && sb != sa;
+        if (carry) two = false;
+        const int32_t s = half && two ? sb : sa;
+        const uint32_t t = half && two ? tb : ta;
+        for (int64_t r = 0; r < rounds; ++r) {
+            const int64_t ch = s + r * slots;
+            bool v = (half == 0 || two) && ch < nch;
+            const uint64_t p = chunk_pair(ch, t, v);
+            float m0, m1;
+            pair_margins(c, p, v, n, unit, k0, k1, m0, m1);
+            push(m0, m1, p, s);
+        }
+        if (carry) {
+            sa = sb;
+            ta = tb;
+        } else {
+            more = next(sa, ta);
+        }
     }
-    Comp fix[4];
-    chain_fix(c, corr, fix);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) fix[a] = wave_reduce(fix[a]);
-    if (lane == 0) merge_fix<WITH_VALUE>(fix, partial, o);
+    if (qn != 0) flush();
 }
 
-#undef CAPVNDF_FIX_PARAMS
-
-inline unsigned fix_grid(int64_t nowners) {
-    constexpr int64_t per_block = kFixBlock / 64;
-    return (unsigned)((nowners + per_block - 1) / per_block);
-}
-
-// The fix pass over nowners owners of `threads` threads.
-template <bool TABLE, bool WITH_VALUE>
-void launch_fix(int64_t nowners, int32_t threads, const float* wox, const float* woy,
-                const float* woz, const float* ax, const float* ay, const float* f0,
-                const int64_t* nsamp, int32_t slots, uint32_t unit_base, const int32_t* chunk_job,
-                const int64_t* chunk_pbeg, const int64_t* chunk_pend, uint32_t k0, uint32_t k1,
-                uint64_t* rec, float* part, hipStream_t st) {
-    hipLaunchKernelGGL((k_horizon_fix<TABLE, WITH_VALUE>), dim3(fix_grid(nowners)),
-                       dim3(kFixBlock), 0, st, nowners, threads, wox, woy, woz, ax, ay, f0, nsamp,
-                       slots, unit_base, chunk_job, chunk_pbeg, chunk_pend, k0, k1, rec, part);
+// The batch fix pass over a plan's nchunks chunks of `threads` threads.
+void launch_fix_batch(int64_t nchunks, int32_t threads, const float* wox, const float* woy,
+                      const float* woz, const float* ax, const float* ay, const float* f0,
+                      const int64_t* nsamp, const int32_t* chunk_job, const int64_t* chunk_pbeg,
+                      const int64_t* chunk_pend, uint32_t k0, uint32_t k1, const uint64_t* rec,
+                      float* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_horizon_fix_batch, dim3((unsigned)nchunks), dim3(kFixBlock), 0, st,
+                       nchunks, threads, wox, woy, woz, ax, ay, f0, nsamp, chunk_job, chunk_pbeg,
+                       chunk_pend, k0, k1, rec, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -811,8 +956,10 @@ void launch_table_fix(int64_t ncells, int32_t slots, const float* wox, const flo
                       const float* woz, const float* ax, const float* ay, const float* f0,
                       const int64_t* nsamples, uint32_t unit_base, uint32_t k0, uint32_t k1,
                       uint64_t* rec, float* part, hipStream_t st) {
-    launch_fix<true, WITH_VALUE>(ncells * slots, kLutBlock, wox, woy, woz, ax, ay, f0, nsamples,
-                                 slots, unit_base, nullptr, nullptr, nullptr, k0, k1, rec, part, st);
+    const int64_t waves = ncells * ((slots + kFixGroup - 1) / kFixGroup);
+    hipLaunchKernelGGL(k_horizon_fix_table<WITH_VALUE>, dim3((unsigned)waves), dim3(kFixBlock), 0,
+                       st, ncells, wox, woy, woz, ax, ay, f0, nsamples, slots, unit_base, k0, k1,
+                       rec, part);
 }
 
 // Argument checks of the table estimators and the slot count the workspace
@@ -1478,10 +1625,9 @@ int32_t enqueue_batch(capvndf_batch_plan* p, hipStream_t st) {
 #undef CAPVNDF_LAUNCH_BATCH
     if (int32_t rc = check_launch("batch kernel launch")) return rc;
     if (g && p->nchunks > 0) {  // a plan of empty jobs has no chunks, and nothing to fix
-        launch_fix<false, true>(p->nchunks, owner_threads(p->tiling), p->wox, p->woy, p->woz,
-                                p->ax, p->ay, p->f0, p->d_nsamp, 0, 0u, p->d_chunk_job,
-                                p->d_chunk_pbeg, p->d_chunk_pend, k0, k1, p->d_rec, p->d_partial,
-                                st);
+        launch_fix_batch(p->nchunks, owner_threads(p->tiling), p->wox, p->woy, p->woz, p->ax,
+                         p->ay, p->f0, p->d_nsamp, p->d_chunk_job, p->d_chunk_pbeg,
+                         p->d_chunk_pend, k0, k1, p->d_rec, p->d_partial, st);
         if (int32_t rc = check_launch("batch fix launch")) return rc;
     }
     if (g)

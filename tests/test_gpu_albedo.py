@@ -420,8 +420,9 @@ def test_horizon_fix_on_grazing_cells():
     cells (most with samples in the oracle's FP32 horizon band, whose bound
     reaches 2000 times the tolerance) the value and its derivatives match
     the oracle within the plain tolerance, the same bits come back twice,
-    the backward entry point agrees, and so does a workspace of one slot per
-    cell (each slot walks four chunks, and the fix pass with it)."""
+    the backward entry point agrees, and so do workspaces of one to three
+    slots per cell (a slot then walks several of the four chunks, and the
+    fix pass with it)."""
     g = _grazing_cells()
     t = to_dev(g)
     n = 1 << 16
@@ -441,9 +442,13 @@ def test_horizon_fix_on_grazing_cells():
     back = cv.albedo_estimate_backward(*args)
     for got, ref, name in zip(back, (rx, ry, rt), ("alpha_x", "alpha_y", "theta_o")):
         _check_grad(host(got), ref, f"grazing backward d/d {name}")
-    # one slot per cell: 4 sums x (s, c) and a 32-byte horizon record
-    ws = torch.empty(32 * (4 * 2 + 8), device="cuda")
-    one = cv.albedo_value_and_grad(*args, workspace=ws)
-    assert np.abs(host(one[0]) - A).max() <= ATOL_A
-    for got, ref, name in zip(one[1:], (rx, ry, rt), ("alpha_x", "alpha_y", "theta_o")):
-        _check_grad(host(got), ref, f"grazing one slot d/d {name}")
+    # 1, 2 and 3 slots per cell (4 sums x (s, c) and a 32-byte horizon
+    # record each): the fix pass then walks 4, 2 or 1-2 chunks per slot
+    for slots in (1, 2, 3):
+        ws = torch.empty(32 * slots * (4 * 2 + 8), device="cuda")
+        few = cv.albedo_value_and_grad(*args, workspace=ws)
+        for x, y in zip(few, cv.albedo_value_and_grad(*args, workspace=ws)):
+            assert torch.equal(x, y)
+        assert np.abs(host(few[0]) - A).max() <= ATOL_A
+        for got, ref, name in zip(few[1:], (rx, ry, rt), ("alpha_x", "alpha_y", "theta_o")):
+            _check_grad(host(got), ref, f"grazing {slots} slot(s) d/d {name}")
