@@ -125,6 +125,54 @@ __device__ __forceinline__ void pairs_fwd(const CellConst& c, uint64_t pbeg, uin
     }
 }
 
+// The table's forward loop over one chunk: pairs base + off for off < len,
+// a pair's second sample existing for off < sec (2 p + 1 < n, i.e.
+// p < n / 2).  base is a multiple of kLutChunkPairs and len at most
+// kLutChunkPairs, so offsets and bounds fit 32 bits and the pair index
+// base + off is base | off: the same pairs in the same order as pairs_fwd,
+// with no 64-bit index arithmetic per pair.  Measured on gfx950: the
+// table's forward kernel 1.4 % faster; the same form in the table's
+// adjoint kernel within 1 % either way from box to box, and in the batch's
+// persistent kernels (chunks at any pair offset, so a 64-bit add per pair)
+// 5 % slower, so those keep pairs_adj and pairs_fwd.
+struct Chunk {
+    uint32_t lo, hi;  // base
+    uint32_t len, sec;
+};
+
+__device__ __forceinline__ Chunk table_chunk(int64_t k, uint64_t npairs, uint64_t n) {
+    const uint64_t pbeg = (uint64_t)k * kLutChunkPairs;
+    const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
+    const uint64_t full = std::min(std::max(n / 2, pbeg), pend);
+    return Chunk{(uint32_t)pbeg, (uint32_t)(pbeg >> 32), (uint32_t)(pend - pbeg),
+                 (uint32_t)(full - pbeg)};
+}
+
+template <int STRIDE>
+__device__ __forceinline__ void chunk_fwd(const CellConst& c, const Chunk& ck, uint32_t unit,
+                                          uint32_t k0, uint32_t k1, Comp (&acc)[2]) {
+    for (uint32_t off0 = threadIdx.x; off0 < ck.len; off0 += (uint32_t)STRIDE * kGroup) {
+        float sg = 0.0f, sgm = 0.0f;
+#pragma unroll 2
+        for (int j = 0; j < kGroup; ++j) {
+            const uint32_t off = off0 + (uint32_t)j * STRIDE;
+            if (off < ck.len) {
+                const Words w = philox4x32_10(ck.lo | off, unit, kTagAlbedo, ck.hi, k0, k1);
+                const FwdTerm t0 = albedo_fwd(c, unit24(w.w0), unit24(w.w1));
+                sg += t0.g;
+                sgm = __builtin_fmaf(t0.g, t0.m5, sgm);
+                if (off < ck.sec) {
+                    const FwdTerm t1 = albedo_fwd(c, unit24(w.w2), unit24(w.w3));
+                    sg += t1.g;
+                    sgm = __builtin_fmaf(t1.g, t1.m5, sgm);
+                }
+            }
+        }
+        comp_add(acc[0], sg);
+        comp_add(acc[1], sgm);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Horizon records.  albedo_adj flags, with a margin >= 0, the samples whose
 // FP32 reflection lies within rounding of the horizon or whose conditioning
@@ -254,11 +302,9 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
     Comp acc[2] = {Comp{0.0f, 0.0f}, Comp{0.0f, 0.0f}};
     const uint64_t npairs = (sw.n + 1) / 2;
     if (c.ok)
-        for (int64_t k = sw.slot; k < sw.nchunks; k += slots) {
-            const uint64_t pbeg = (uint64_t)k * kLutChunkPairs;
-            const uint64_t pend = std::min(pbeg + kLutChunkPairs, npairs);
-            pairs_fwd<kLutBlock>(c, pbeg, pend, sw.n, unit_base + (uint32_t)cell, k0, k1, acc);
-        }
+        for (int64_t k = sw.slot; k < sw.nchunks; k += slots)
+            chunk_fwd<kLutBlock>(c, table_chunk(k, npairs, sw.n), unit_base + (uint32_t)cell, k0,
+                                 k1, acc);
     float* dst = partial + (int64_t)blockIdx.x * 2 * NACC;
     if (MODE == 0) {
         block_reduce_store<2, kLutBlock>(acc, dst);
