@@ -628,7 +628,9 @@ def summarize_valu(d, cmds, prof, batch_samples):
     b = read_counters(os.path.join(d, "valu_b")) if os.path.isdir(os.path.join(d, "valu_b")) \
         else {}
     lut = 4096 * (1 << 20)
-    lut_grid = 4096 * 64 * 256
+    # the 64x64 table's launches: 4096 cells x slots blocks of 256 work-items
+    # (32 slots per cell; 64 in traces of builds before that change)
+    lut_grids = {4096 * slots * 256 for slots in (32, 64)}
     micro = 256 * 2048 * 4 * 64
     rows = []  # (key, kernel, description, samples, [dispatch dicts])
     for pre, key, desc in (("k_albedo_fwd<0>", "forward_two_sums", "forward, two Fresnel sums"),
@@ -637,10 +639,11 @@ def summarize_valu(d, cmds, prof, batch_samples):
         k = _kernel(a, pre)
         if k:
             rows.append((key, k, desc + " (64x64 cells x 2^20)", lut,
-                         [x for x in a[k] if x["grid"] == lut_grid]))
-    # the horizon fix passes after the table's adjoint kernels (a wavefront
-    # per 8 slots: 4096 x 8 blocks of 64 work-items)
-    fix_grid = 4096 * 8 * 64
+                         [x for x in a[k] if x["grid"] in lut_grids]))
+    # the horizon fix passes after the table's adjoint kernels: a wavefront
+    # per 4 of a cell's 32 slots (per 8 of 64 in earlier builds), 4096 x 8
+    # blocks of 64 work-items
+    fix_grids = {4096 * 8 * 64}
     for pre, key, desc in (("k_horizon_fix_table<false>", "fix_backward",
                             "horizon fix after backward"),
                            ("k_horizon_fix_table<true>", "fix_value_and_grad",
@@ -648,7 +651,7 @@ def summarize_valu(d, cmds, prof, batch_samples):
         k = _kernel(a, pre)
         if k:
             rows.append((key, k, desc + " (per table sample)", lut,
-                         [x for x in a[k] if x["grid"] == fix_grid]))
+                         [x for x in a[k] if x["grid"] in fix_grids]))
     for m, name in ((0, "cap"), (1, "disk"), (2, "cap in double precision")):
         k = _kernel(a, f"k_microbench<{m}>")
         if k:
@@ -665,7 +668,7 @@ def summarize_valu(d, cmds, prof, batch_samples):
     k = _kernel(src, "k_radiance<4>")
     if k:
         rows.append(("radiance", k, "direct illumination, 4 lobes (64x64 cells x 2^20)", lut,
-                     [x for x in src[k] if x["grid"] == lut_grid]))
+                     [x for x in src[k] if x["grid"] in lut_grids]))
     for k in sorted(b):
         if k.startswith("k_batch"):
             rows.append((f"batch:{k}", k, "batch forward + adjoint, 4096 jobs", batch_samples,

@@ -752,11 +752,12 @@ __global__ __launch_bounds__(kFixBlock) void k_horizon_fix_batch(
 // per lane per round, each fix placed in LDS, and the lane that holds the
 // first entry of an owner's run sums the run in queue order and merges it
 // into that owner's partial (an owner whose run spans two queues is merged
-// twice, in queue order).  Eight owners per wavefront measured best: a
-// cell holds up to about 500 flagged samples (grazing views of smooth
-// surfaces, 2^20 samples), so 16 owners per wavefront leaves a long tail,
-// and fewer owners per wavefront repeat the set-up more often.
-constexpr int kFixGroup = 8;
+// twice, in queue order).  Four owners per wavefront measured best with 32
+// slots per cell (two chunks each): a cell holds up to about 500 flagged
+// samples (grazing views of smooth surfaces, 2^20 samples), so more owners
+// per wavefront leave a long tail (with 64 slots of one chunk, 16 owners
+// took 1.4 times as long as 8), and fewer repeat the set-up more often.
+constexpr int kFixGroup = 4;
 constexpr int kFixTableQueue = 128;
 static_assert(kLutPairsPerThread == 32, "a scan step gives each flagged thread 32 lanes");
 static_assert(kFixGroup * (kLutBlock / 64) <= 64, "a group's records fit one wavefront");
@@ -977,8 +978,11 @@ inline unsigned finish_grid(int64_t n) { return (unsigned)((n + kFinishBlock - 1
 // Slots per cell.  A call aims for kFillBlocks blocks (about four rounds of
 // the blocks the chip holds at once) with at least kMinSlots per cell, and
 // stays below 2^24 blocks (a dispatch counts its work-items in 32 bits).
+// On 4096 cells of 2^20 samples (64 chunks each) 32 slots measured faster
+// than 64 (value + gradient 0.8 %, forward 1.3 %; the recompute-style
+// backward 0.5 % slower) and than 16 (value + gradient 1.8 % slower).
 constexpr int64_t kFillBlocks = 8192;
-constexpr int64_t kMinSlots = 64;
+constexpr int64_t kMinSlots = 32;
 constexpr int64_t kMaxBlocks = ((int64_t)1 << 24) - 1;
 
 int64_t target_slots(int64_t ncells) {

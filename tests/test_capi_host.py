@@ -95,15 +95,15 @@ def test_albedo_argument_errors(lib):
 
     # workspace: ncells * slots * partial sums * 8 bytes, plus with gradients
     # a 32-byte horizon record per slot; slots per cell aim at 8192 blocks with
-    # at least 64, below 2^24 blocks, and (given host counts) no more than the
+    # at least 32, below 2^24 blocks, and (given host counts) no more than the
     # largest cell's chunks of 16384 samples
     assert lib.albedo_workspace_size(-1, None, 0) == 0
     assert lib.albedo_workspace_size(0, None, 0) == 0
     assert lib.albedo_workspace_size(1 << 24, None, 0) == 0
     assert lib.albedo_workspace_size(16, None, 2) == 0
-    assert lib.albedo_workspace_size(4096, None, 0) == 4096 * 64 * 2 * 8
-    assert lib.albedo_workspace_size(4096, None, 1) == 4096 * 64 * (4 * 8 + 32)
-    assert lib.albedo_workspace_size(4096, counts(*[1 << 20] * 4096), 0) == 4096 * 64 * 2 * 8
+    assert lib.albedo_workspace_size(4096, None, 0) == 4096 * 32 * 2 * 8
+    assert lib.albedo_workspace_size(4096, None, 1) == 4096 * 32 * (4 * 8 + 32)
+    assert lib.albedo_workspace_size(4096, counts(*[1 << 20] * 4096), 0) == 4096 * 32 * 2 * 8
     assert lib.albedo_workspace_size(4096, counts(*[4096] * 4096), 1) == 4096 * 1 * (4 * 8 + 32)
     assert lib.albedo_workspace_size(1, None, 0) == 8192 * 2 * 8
     assert lib.albedo_workspace_size(1, counts(1 << 20), 0) == 64 * 2 * 8
