@@ -817,7 +817,10 @@ __global__ __launch_bounds__(kFixBlock) void k_horizon_fix_table(
             }
             merge_fix<WITH_VALUE>(f, partial, u * slots + s);
         }
-        wave_sync();
+        // an owner merged here may be merged again by another lane after a
+        // later round: a workgroup barrier (the block is this wavefront)
+        // orders those global accesses, and the LDS ones
+        __syncthreads();
         qn = 0;
     };
     // queues the lane's flagged samples of pair p (slot s) in lane order
