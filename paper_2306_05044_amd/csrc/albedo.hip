@@ -30,12 +30,17 @@ constexpr int kGroup = 8;  // pairs summed plainly before each TwoSum fold
 // Unroll depth of the adjoint's pair loop and the waves per SIMD the
 // adjoint kernels are compiled for (build-time tuning constants).  Seven
 // resident waves beat the compiler's default register budget (five waves) by
-// about 8 % on gfx950, even though a few loop-invariant values then spill.
+// about 8 % on gfx950, even though a few loop-invariant values then spill;
+// the table's gradient-only (recompute) kernel runs 1 % faster at six (the
+// value + gradient kernel 5 % slower, the batch kernels 0-2 % slower).
 #ifndef CAPVNDF_ADJ_UNROLL
 #define CAPVNDF_ADJ_UNROLL 1
 #endif
 #ifndef CAPVNDF_ADJ_WAVES
 #define CAPVNDF_ADJ_WAVES 7
+#endif
+#ifndef CAPVNDF_ADJ_GRAD_WAVES
+#define CAPVNDF_ADJ_GRAD_WAVES 6
 #endif
 constexpr int kFinishBlock = 256;
 
@@ -322,7 +327,8 @@ __global__ __launch_bounds__(kLutBlock) void k_albedo_fwd(
 // Block b also writes its horizon record at rec[4 b .. 4 b + 4).
 #define CAPVNDF_ADJ_ATTR __attribute__((amdgpu_waves_per_eu(CAPVNDF_ADJ_WAVES)))
 template <bool WITH_VALUE>
-__global__ __launch_bounds__(kLutBlock) CAPVNDF_ADJ_ATTR void k_albedo_adj(
+__global__ __launch_bounds__(kLutBlock) __attribute__((amdgpu_waves_per_eu(
+    WITH_VALUE ? CAPVNDF_ADJ_WAVES : CAPVNDF_ADJ_GRAD_WAVES))) void k_albedo_adj(
     const float* __restrict__ wox, const float* __restrict__ woy, const float* __restrict__ woz,
     const float* __restrict__ ax, const float* __restrict__ ay, const float* __restrict__ f0p,
     const int64_t* __restrict__ nsamp, int32_t slots, uint32_t unit_base, uint32_t k0,
