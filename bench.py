@@ -272,7 +272,7 @@ def load_golden():
         return {}
     out = {}
     for part, gen in (("lut", mk.lut_inputs), ("grad", mk.grad_inputs),
-                      ("batch", mk.batch_inputs)):
+                      ("batch", mk.batch_inputs), ("radiance", mk.radiance_inputs)):
         if f"{part}_digest" in data and str(data[f"{part}_digest"]) == mk.digest(gen()):
             out[part] = data
     return out
@@ -380,6 +380,15 @@ def oracle_checks(checks):
         errs["direct_illumination"] = {
             "max_abs_err_vs_oracle": float(f"{np.abs(c['value'] - ref).max():.3e}"),
             "err_checked_cells": len(c["cells"])}
+        if "radiance" in gold and np.array_equal(gold["radiance"]["radiance_lobes"],
+                                                 c["lobes"]):
+            G = gold["radiance"]
+            errs["direct_illumination"]["every_cell"] = {
+                "cells": 4096,
+                "max_abs_err": float(f"{np.abs(c['all'] - G['radiance_value']).max():.3e}"),
+                "tolerance": float(f"{1e-4 * float(c['lobes'][:, 4].sum()):.3e}"),
+                "oracle_seconds": round(float(G["radiance_seconds"]), 1),
+                "oracle_threads": int(G["host_threads"])}
     return errs
 
 
@@ -1154,9 +1163,10 @@ def main():
         r = rad()
         torch.cuda.synchronize()
         cells = np.array([5, 2900, 4095])
+        r_all = r.cpu().numpy()
         checks["direct_illumination"] = {"grid": {k: v[cells] for k, v in g.items()},
                                          "cells": cells, "n": n, "lobes": lobes_np,
-                                         "value": r.cpu().numpy()[cells]}
+                                         "value": r_all[cells], "all": r_all}
         out["direct_illumination"] = {
             "cells": 4096, "samples_per_cell": n, "lobes": 4, "ms": round(ms_r, 4),
             "timed_launches": est_steps,

@@ -49,7 +49,8 @@ _golden_cache = {}
 
 def golden(part):
     """The oracle's stored values for every unit of one estimator workload
-    ("lut", "grad" or "batch"), written by tests/golden/make_estimator_golden.py.
+    ("lut", "grad", "batch" or "radiance"), written by
+    tests/golden/make_estimator_golden.py.
     The digest of the inputs it was computed on must match the inputs the
     workload generator gives now."""
     if "mk" not in _golden_cache:
@@ -61,7 +62,8 @@ def golden(part):
             _golden_cache["data"] = {k: f[k] for k in f.files}
         _golden_cache["mk"] = mk
     mk, data = _golden_cache["mk"], _golden_cache["data"]
-    inputs = {"lut": mk.lut_inputs, "grad": mk.grad_inputs, "batch": mk.batch_inputs}[part]()
+    inputs = {"lut": mk.lut_inputs, "grad": mk.grad_inputs, "batch": mk.batch_inputs,
+              "radiance": mk.radiance_inputs}[part]()
     assert str(data[f"{part}_digest"]) == mk.digest(inputs), \
         f"{part}: the stored oracle values were computed on other inputs; rerun the script"
     return data

@@ -18,6 +18,10 @@ tag 3, unit = cell or job index):
   differences of the same estimator with step 1e-4.
 * ``batch`` -- the 4096 uneven jobs (2^10 .. 2^22 samples), seed 4, F0 = 1:
   value and the three dual-number derivatives.
+* ``radiance`` -- direct illumination over the same 64 x 64 table, 2^20
+  samples per cell, seed 2, F0 = 1, under four spherical-Gaussian lobes
+  (RAD_LOBES, the benchmark's): the estimator of Appendix A with the lobes'
+  radiance L(w_l) in place of L == 1.
 
 For each workload the file also holds, per cell or job, the oracle's bound on
 how far the gradient may move when samples whose reflected direction lies
@@ -34,7 +38,7 @@ The file also records a digest of every input array, the wall times, the
 thread count and the host's CPU model.
 
 Usage: python tests/golden/make_estimator_golden.py [--threads T]
-           [--only lut grad batch bands]
+           [--only lut grad batch bands radiance]
 """
 
 from __future__ import annotations
@@ -61,6 +65,11 @@ OUT = os.path.join(HERE, "estimator_full.npz")
 LUT_N, LUT_SEED, LUT_F0 = 1 << 20, 2, 0.04
 GRAD_N, GRAD_SEED, GRAD_STEP = 1 << 18, 3, 1e-4
 BATCH_SEED = 4
+RAD_N, RAD_SEED = 1 << 20, 2
+# rows (mu_x, mu_y, mu_z, kappa, lambda), float32 as the library receives them
+RAD_LOBES = np.array([[0.0, 0.0, 1.0, 4.0, 2.0], [0.6, 0.0, 0.8, 30.0, 5.0],
+                      [-0.5, 0.5, 0.70710678, 10.0, 1.5], [0.0, 0.0, 1.0, 0.0, 0.3]],
+                     dtype=np.float32)
 # the kernels' double-precision horizon decision: band (c0 + c1 kappa) 2^-48
 BAND_C0, BAND_C1 = oracle.HORIZON_C0 * 2.0 ** -24, oracle.HORIZON_C1 * 2.0 ** -24
 
@@ -100,6 +109,10 @@ def batch_inputs():
     return workloads.batch_jobs(4096, seed=BATCH_SEED)
 
 
+def radiance_inputs():
+    return {**workloads.lut_grid(64, 64), "lobes": RAD_LOBES}
+
+
 def per_unit(fn, g, n, seed, threads, nout, **kw):
     """fn over every unit, one unit per call (nthreads=1) on a thread pool,
     largest sample count first; returns nout arrays indexed by unit."""
@@ -124,7 +137,7 @@ def per_unit(fn, g, n, seed, threads, nout, **kw):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
-    ap.add_argument("--only", nargs="*", default=["lut", "grad", "batch", "bands"])
+    ap.add_argument("--only", nargs="*", default=["lut", "grad", "batch", "bands", "radiance"])
     args = ap.parse_args()
     T = args.threads
     rec = {}
@@ -189,6 +202,17 @@ def main():
                         f"{part}_band_count": bc.astype(np.int64),
                         "band_c0": np.array(BAND_C0), "band_c1": np.array(BAND_C1)})
         print(f"horizon bands: {time.perf_counter() - t0:.1f} s", flush=True)
+
+    if "radiance" in args.only:
+        g = radiance_inputs()
+        t0 = time.perf_counter()
+        r = oracle.radiance((g["wx"], g["wy"], g["wz"]), g["ax"], g["ay"], RAD_N, RAD_SEED,
+                            RAD_LOBES.astype(np.float64), f0=1.0, nthreads=T)
+        t_r = time.perf_counter() - t0
+        print(f"radiance: {t_r:.1f} s", flush=True)
+        rec.update({"radiance_digest": np.array(digest(g)), "radiance_n": np.array(RAD_N),
+                    "radiance_seed": np.array(RAD_SEED), "radiance_lobes": RAD_LOBES,
+                    "radiance_value": r, "radiance_seconds": np.array(t_r)})
 
     np.savez_compressed(OUT, **rec)
     print("wrote", OUT)

@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import workloads
-from _gpu import host, to_dev
+from _gpu import golden, host, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -65,17 +65,25 @@ def test_constant_radiance_and_edges():
                              torch.zeros((9, 5), device="cuda"))
 
 
-def test_radiance_full_table_sampled():
-    """64 x 64 cells x 2^20 samples under 4 lobes; 32 cells vs the oracle."""
+def test_radiance_full_table_every_cell():
+    """64 x 64 cells x 2^20 samples under 4 lobes: every cell against the
+    oracle's stored values, and four cells against the oracle run live."""
+    gold = golden("radiance")
     g = workloads.lut_grid(64, 64)
     t = to_dev(g)
-    n = 1 << 20
-    r = cv.radiance_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, 2,
-                             torch.from_numpy(LOBES).cuda())
+    n, seed = int(gold["radiance_n"]), int(gold["radiance_seed"])
+    lobes = np.ascontiguousarray(gold["radiance_lobes"])
+    r = cv.radiance_estimate(t["wx"], t["wy"], t["wz"], t["ax"], t["ay"], n, seed,
+                             torch.from_numpy(lobes).cuda())
     torch.cuda.synchronize()
-    cells = np.unique(np.concatenate([np.linspace(0, 4095, 28).astype(np.int64),
-                                      [5, 1234, 2900, 4094]]))
+    got = host(r)
+    tol = 1e-4 * float(lobes[:, 4].sum())
+    err = np.abs(got - gold["radiance_value"]).max()
+    print(f"radiance, every cell: max |err| {err:.2e} (tolerance {tol:.1e})")
+    assert err <= tol
+    cells = np.array([5, 1234, 2900, 4094])
     sub = {k: v[cells] for k, v in g.items()}
-    ref = oracle.radiance((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"], n, 2,
-                          LOBES.astype(np.float64), units=cells)
-    assert np.abs(host(r)[cells] - ref).max() <= 1e-4 * float(LOBES[:, 4].sum())
+    ref = oracle.radiance((sub["wx"], sub["wy"], sub["wz"]), sub["ax"], sub["ay"], n, seed,
+                          lobes.astype(np.float64), units=cells)
+    assert np.abs(got[cells] - ref).max() <= tol
+    assert np.abs(gold["radiance_value"][cells] - ref).max() <= 1e-12
