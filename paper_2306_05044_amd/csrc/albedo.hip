@@ -1048,11 +1048,21 @@ int32_t prepare_cells(const char* fn, int64_t ncells, const float* wox, const fl
                     fn, least, workspace == nullptr ? (size_t)0 : workspace_bytes);
     if (!aligned_to(workspace, 16))
         return fail(CAPVNDF_ERR_MISALIGNED, "%s: workspace must be 16-byte aligned", fn);
-    // table_bytes is affine in the slot count: fixed + slots * per_slot
-    const size_t fixed = table_bytes(ncells, 0, nacc, records);
-    const size_t per_slot = least - fixed;
-    *slots = (int32_t)std::min<int64_t>(target_slots(ncells),
-                                        (int64_t)((workspace_bytes - fixed) / per_slot));
+    // table_bytes is affine in the slot count: fixed + slots * per_slot.
+    // One-sum calls (the value-only pass, radiance) count slots at the
+    // two-sum forward's size: albedo_workspace_size(.., 0) sizes for two sums
+    // per slot, up to the largest cell's chunk count when given the host
+    // counts, so the same workspace gives the three calls the same slots.  At
+    // half the size per slot a one-sum call got twice as many, and a block
+    // without a chunk costs about as much as one with a chunk when the
+    // blocks each hold one (dispatch-bound: 2^18 samples per cell ran at
+    // half the rate).
+    const int sizing = nacc == 1 && !records ? 2 : nacc;
+    const size_t fixed = table_bytes(ncells, 0, sizing, records);
+    const size_t per_slot = table_bytes(ncells, 1, sizing, records) - fixed;
+    *slots = (int32_t)std::min<int64_t>(
+        target_slots(ncells),
+        std::max<int64_t>(1, (int64_t)((workspace_bytes - fixed) / per_slot)));
     return CAPVNDF_OK;
 }
 
