@@ -176,6 +176,13 @@ def alu_roofline(kind, samples, ms):
             "lane_instr_per_sample": round(ips, 1)}
 
 
+def proxy_roofline(kind, samples, ms):
+    """alu_roofline of a kernel priced at another kernel's per-sample count,
+    labelled with that kernel's key; None where alu_roofline is None."""
+    r = alu_roofline(kind, samples, ms)
+    return None if r is None else {"per_sample_count_of": kind, **r}
+
+
 def batch_kernel(tiling):
     """Counter-summary key of the batch kernel a tiling (block, pairs per
     thread, blocks per CU, per_wave, dynamic) runs, with gradients."""
@@ -1117,6 +1124,11 @@ def main():
                           # over the whole replay (persistent kernel + finishing pass)
                           "roofline": alu_roofline(batch_kernel(info["tiling"]), info["total_samples"],
                                                    ms_b),
+                          # the batch kernel's own counts are not in the summary;
+                          # this prices its samples at the table's value +
+                          # Jacobian kernel's count (the same per-sample code)
+                          "roofline_proxy": proxy_roofline("value_and_grad", info["total_samples"],
+                                                           ms_b),
                           "max_abs_diff_graph_vs_per_request": diff,
                           "per_request_plain_sampler": plain_res}
         plan.close()
