@@ -55,6 +55,19 @@ def test_alu_roofline_arithmetic():
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
 
 
+def test_batch_roofline_proxy_is_labelled():
+    """The batch line's proxy prices its samples at another kernel's count and
+    says so, with the same figures as that kernel's roofline."""
+    assert bench.batch_kernel((512, 64, 8, 0, 1)) == "batch:k_batch<512, true, true>"
+    r = bench.proxy_roofline("value_and_grad", 2073825747, 6.5)
+    ref = bench.alu_roofline("value_and_grad", 2073825747, 6.5)
+    if ref is None:
+        assert r is None
+        pytest.skip("VALU counter summary not taken on the current sources")
+    assert r["per_sample_count_of"] == "value_and_grad"
+    assert {k: v for k, v in r.items() if k != "per_sample_count_of"} == ref
+
+
 FIXTURE = os.path.join(ROOT, "tests", "fixtures", "rocprof")
 
 
